@@ -1,0 +1,222 @@
+"""Oracle for the block-tridiagonal-arrow KKT system -- test infrastructure only.
+
+Notation (paper, Eq. 3, 1-based there, 0-based here):
+  D[i]   = Psi_{i,i}    (b x b, SPD; the matrix uses sym(D[i]) = (D[i] + D[i]^T)/2)
+  C[i]   = Psi_{i+1,i}  (b x b, i = 0..N-2; Psi_{i,i+1} = C[i]^T)
+  B[i]   = Psi_{g,i}    (ng x b, the arrow; Psi_{i,g} = B[i]^T)
+  corner = Psi_{g,g}    (ng x ng, SPD; the matrix uses sym(corner))
+  r                     (N*b + ng) x nrhs right-hand side, stages first, g last.
+
+Segmentation (Sec. 3.1): with segment lengths N_1..N_p, segment k holds N_k
+consecutive stages and a single separator stage sits between segment k-1 and
+segment k, so N = sum_k N_k + p - 1.  The permutation P of Sec. 3.1 (Fig. 1b)
+lists the segment stages first (segment 1, then 2, ...), then the separators
+(of segments 2..p, in order), then g.  The factor of P Psi P^T is unique
+(positive diagonal), so it is computed here by plain block Cholesky in that order
+(``blockchol``); p = 1 is the sequential method the paper compares against
+(Sec. 3.3, O_seq).
+
+Readings where the paper is silent (listed in the design doc as well):
+  * failure: ``info`` is the 1-based natural stage index of the first diagonal
+    block, in elimination order, whose pivot is not positive and finite; N + 1
+    names the corner.  The paper does not discuss indefinite input.
+  * symmetric parametrisation: the matrix uses sym(D[i]) and sym(corner); C[i]
+    and B[i] each appear twice.  This fixes the gradient of the adjoint.
+"""
+import numpy as np
+
+from .blockchol import BlockMatrix
+
+
+def sym(a):
+    return 0.5 * (a + np.swapaxes(a, -1, -2))
+
+
+def stage_layout(N, seg_lens):
+    """Natural 0-based stage indices of every segment, and of the separators.
+
+    Returns (segments, separators): segments[k] is the list of stages of segment
+    k+1; separators[k-2] is the separator stage between segments k-1 and k
+    (k = 2..p, paper's 1-based k)."""
+    seg_lens = [int(v) for v in seg_lens]
+    p = len(seg_lens)
+    if p < 1 or min(seg_lens) < 1 or sum(seg_lens) + p - 1 != N:
+        raise ValueError("segment lengths %s do not tile N=%d" % (seg_lens, N))
+    segments, separators = [], []
+    s = 0
+    for k, nk in enumerate(seg_lens):
+        if k > 0:
+            separators.append(s)
+            s += 1
+        segments.append(list(range(s, s + nk)))
+        s += nk
+    return segments, separators
+
+
+def elimination_order(N, seg_lens):
+    """Stage order of P Psi P^T: all segment stages, then the separators (g is last)."""
+    segments, separators = stage_layout(N, seg_lens)
+    return [i for seg in segments for i in seg] + separators
+
+
+def _dims(D, B):
+    D = np.asarray(D)
+    N, b = D.shape[0], D.shape[1]
+    ng = 0 if B is None else int(np.asarray(B).shape[1])
+    return N, b, ng
+
+
+class KKTFactor:
+    """hat L = chol(P Psi P^T) for the order given by ``seg_lens`` (default: p = 1)."""
+
+    def __init__(self, D, C, B, corner, seg_lens=None):
+        D = np.asarray(D, dtype=np.float64)
+        C = np.asarray(C, dtype=np.float64).reshape(-1, D.shape[1], D.shape[1])
+        N, b, ng = _dims(D, B)
+        if seg_lens is None:
+            seg_lens = [N]
+        self.N, self.b, self.ng = N, b, ng
+        self.seg_lens = list(seg_lens)
+        self.order = elimination_order(N, seg_lens)
+        self.pos = {s: i for i, s in enumerate(self.order)}
+        if ng:
+            self.pos["g"] = N
+        sizes = [b] * N + ([ng] if ng else [])
+        M = BlockMatrix(sizes)
+        for s in range(N):
+            M.set(self.pos[s], self.pos[s], sym(D[s]))
+        for s in range(N - 1):
+            i, j = self.pos[s + 1], self.pos[s]
+            if i > j:
+                M.set(i, j, C[s])
+            else:
+                M.set(j, i, C[s].T)
+        if ng:
+            B = np.asarray(B, dtype=np.float64)
+            for s in range(N):
+                M.set(N, self.pos[s], B[s])
+            M.set(N, N, sym(np.asarray(corner, dtype=np.float64)))
+        rc = M.cholesky()
+        if rc < 0:
+            raise RuntimeError("oracle block Cholesky failed on its input")
+        if rc == 0:
+            self.info = 0
+        else:
+            col = rc - 1
+            self.info = self.order[col] + 1 if col < N else N + 1
+        self._M = M
+
+    def block(self, row, col):
+        """hat L block at (row stage, col stage), natural labels (ints or 'g').
+
+        Returns None for a structural zero.  Requires row to follow col in the
+        elimination order."""
+        i, j = self.pos[row], self.pos[col]
+        if i < j:
+            raise ValueError("(%r, %r) lies above the diagonal of hat L" % (row, col))
+        return self._M.get(i, j)
+
+    def _to_perm(self, r):
+        N, b, ng = self.N, self.b, self.ng
+        r = np.asarray(r, dtype=np.float64)
+        rs = r[: N * b].reshape(N, b, *r.shape[1:])
+        parts = [rs[s] for s in self.order]
+        if ng:
+            parts.append(r[N * b:])
+        return np.concatenate(parts, axis=0)
+
+    def _from_perm(self, xp):
+        N, b = self.N, self.b
+        x = np.empty_like(xp)
+        for i, s in enumerate(self.order):
+            x[s * b:(s + 1) * b] = xp[i * b:(i + 1) * b]
+        x[N * b:] = xp[N * b:]
+        return x
+
+    def forward(self, r):
+        """hat y with hat L hat y = P r (in elimination order), via solve of L only."""
+        raise NotImplementedError("the oracle exposes the full solve only")
+
+    def solve(self, r):
+        """x with Psi x = r (natural order, any number of columns)."""
+        if self.info:
+            raise FloatingPointError("matrix is not positive definite (info=%d)" % self.info)
+        return self._from_perm(self._M.solve(self._to_perm(r)))
+
+    def logdet(self):
+        """log det Psi = 2 * sum log diag(hat L); identical for every block order."""
+        tot = 0.0
+        keys = list(range(self.N)) + (["g"] if self.ng else [])
+        for s in keys:
+            tot += 2.0 * np.sum(np.log(np.diag(self.block(s, s))))
+        return float(tot)
+
+
+def solve(D, C, B, corner, r, seg_lens=None):
+    return KKTFactor(D, C, B, corner, seg_lens).solve(r)
+
+
+def matvec(D, C, B, corner, x):
+    """Psi x with the symmetric parametrisation (block form, natural order)."""
+    D = np.asarray(D, dtype=np.float64)
+    N, b, ng = _dims(D, B)
+    x = np.asarray(x, dtype=np.float64)
+    one = x.ndim == 1
+    X = x[:, None] if one else x
+    xs = X[: N * b].reshape(N, b, -1)
+    ys = np.einsum("irc,icq->irq", sym(D), xs)
+    if N > 1:
+        C = np.asarray(C, dtype=np.float64).reshape(N - 1, b, b)
+        ys[1:] += np.einsum("irc,icq->irq", C, xs[:-1])
+        ys[:-1] += np.einsum("icr,icq->irq", C, xs[1:])
+    out = [ys.reshape(N * b, -1)]
+    if ng:
+        B = np.asarray(B, dtype=np.float64)
+        xg = X[N * b:]
+        ys2 = ys + np.einsum("iqr,qk->irk", B, xg)
+        out = [ys2.reshape(N * b, -1)]
+        yg = np.einsum("iqc,ick->qk", B, xs) + sym(np.asarray(corner, dtype=np.float64)) @ xg
+        out.append(yg)
+    y = np.concatenate(out, axis=0)
+    return y[:, 0] if one else y
+
+
+def rel_residual(D, C, B, corner, x, r):
+    """max over rhs columns of ||Psi x - r||_2 / ||r||_2."""
+    res = matvec(D, C, B, corner, x) - np.asarray(r, dtype=np.float64)
+    R = np.asarray(r, dtype=np.float64)
+    if res.ndim == 1:
+        res, R = res[:, None], R[:, None]
+    return float(np.max(np.linalg.norm(res, axis=0) / np.maximum(np.linalg.norm(R, axis=0), 1e-300)))
+
+
+def adjoint(D, C, B, corner, x, gbar, seg_lens=None):
+    """Gradients of L = <gbar, x> where Psi x = r (x given, gbar = dL/dx).
+
+    lambda = Psi^{-1} gbar (Psi symmetric), dL/dPsi = -lambda x^T summed over the
+    rhs columns, then pulled back through the parametrisation Psi(D, C, B, corner):
+      dD[i]   = -sym(lambda_i x_i^T)
+      dC[i]   = -(lambda_{i+1} x_i^T + x_{i+1} lambda_i^T)
+      dB[i]   = -(lambda_g x_i^T + x_g lambda_i^T)
+      dcorner = -sym(lambda_g x_g^T)
+      dr      = lambda
+    Returns (lambda, dD, dC, dB, dcorner)."""
+    D = np.asarray(D, dtype=np.float64)
+    N, b, ng = _dims(D, B)
+    lam = solve(D, C, B, corner, gbar, seg_lens)
+    X = np.asarray(x, dtype=np.float64)
+    Lm = lam
+    if X.ndim == 1:
+        X, Lm = X[:, None], lam[:, None]
+    xs = X[: N * b].reshape(N, b, -1)
+    ls = Lm[: N * b].reshape(N, b, -1)
+    dD = -sym(np.einsum("irq,icq->irc", ls, xs))
+    dC = -(np.einsum("irq,icq->irc", ls[1:], xs[:-1]) + np.einsum("irq,icq->irc", xs[1:], ls[:-1]))
+    if ng:
+        xg, lg = X[N * b:], Lm[N * b:]
+        dB = -(np.einsum("rq,icq->irc", lg, xs) + np.einsum("rq,icq->irc", xg, ls))
+        dcorner = -sym(lg @ xg.T)
+    else:
+        dB = np.zeros((N, 0, b))
+        dcorner = np.zeros((0, 0))
+    return lam, dD, dC, dB, dcorner
