@@ -1,0 +1,152 @@
+/*
+ * kkt.h -- C ABI of the MI355X (gfx950) segmented block Cholesky KKT solver.
+ *
+ * Solves Psi x = r (arXiv 2511.00946, Eq. 2) for block-tridiagonal-arrow SPD
+ * matrices Psi (Eq. 3) with uniform stage size b (Sec. 3.1) and a global block
+ * of size ng >= 0, for one system or a ragged batch of systems.  The horizon of
+ * each system is split into p segments; segments are factored independently
+ * (Algorithm 1, parallel phase, Eqs. 4-5), the separator and arrow blocks form a
+ * reduced system (Eq. 7) that is factored next (Algorithm 1, sequential phase),
+ * and the substitutions sweep the same way (Algorithms 2 and 3, Eqs. 9-12).
+ * p = 1 is the sequential block Cholesky.
+ *
+ * Precision: FP64 throughout.
+ *
+ * Memory: every data pointer is a DEVICE pointer owned by the caller.  The
+ * library never allocates device memory and never synchronises the host: all
+ * work is enqueued on the caller's stream, so calls can be captured in a HIP
+ * graph.  Scratch lives in the caller's workspace (kkt_plan_info.workspace_bytes,
+ * 256-byte aligned); kkt_workspace_init must be enqueued once on a workspace
+ * before its first use with a plan.  Calls that share a workspace must not
+ * overlap in time.
+ *
+ * Data layout (FP64, row-major blocks).  Systems are packed one after another in
+ * five pools; kkt_plan_system gives each system's offsets (in doubles):
+ *   D      [N, b, b]     D_i   = Psi_{i,i}    (the solver uses (D_i + D_i^T)/2)
+ *   C      [N-1, b, b]   C_i   = Psi_{i+1,i}  (Psi_{i,i+1} = C_i^T)
+ *   B      [N, ng, b]    B_i   = Psi_{g,i}    (Psi_{i,g} = B_i^T)
+ *   corner [ng, ng]      Psi_{g,g}            (the solver uses its symmetric part)
+ *   rhs    [N b + ng, nrhs]  stage rows first, g rows last; overwritten by x.
+ * With ng = 0 the B and corner pools are empty and may be NULL.
+ *
+ * Return codes: 0 OK; negative values are launch-time errors (see KKT_E*).
+ * Numerical breakdown is reported per system in the device array info[S]:
+ *   0      factorization succeeded;
+ *   j > 0  the diagonal block of natural stage j (1-based) met a pivot that is
+ *          not positive and finite; j = N + 1 names the corner block.  With
+ *          several failures the first in elimination order is reported
+ *          (segment stages, then separators, then the corner).
+ *   A failed system's solution is set to NaN; other systems are unaffected.
+ */
+#ifndef KKT_MI355X_H
+#define KKT_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KKT_OK              0
+#define KKT_EDIMS          -1   /* N < 1, b outside 1..32, ng outside 0..16, nrhs outside 1..8,
+                                   p > (N+1)/2, or an impossible first-segment length      */
+#define KKT_EPOINTER       -2   /* NULL or misaligned pointer                               */
+#define KKT_EWORKSPACE     -3   /* workspace too small or not initialised for this plan     */
+#define KKT_ELAUNCH        -4   /* HIP launch error                                         */
+#define KKT_ENOTFACTORED   -5   /* solve before any factorization into this workspace       */
+#define KKT_EINTERNAL      -6
+
+#define KKT_MAX_B     32
+#define KKT_MAX_NG    16
+#define KKT_MAX_NRHS   8
+
+typedef struct kkt_plan kkt_plan;   /* opaque, host-only, immutable after creation */
+
+/* One system's shape.
+ *   N   number of stages (diagonal blocks), >= 1
+ *   b   stage block size, 1..KKT_MAX_B
+ *   ng  global block size, 0..KKT_MAX_NG
+ *   p   segments: 1 = sequential method; p >= 2 = segmented method with p
+ *       segments (needs N >= 2p - 1); 0 = let the plan's cost model choose.
+ *   N1  first-segment length; 0 = the balance rule of Eq. (13) (sigma = 19/7).
+ *       Otherwise the other p-1 segments get (N - N1 - (p-1)) / (p-1) stages,
+ *       which must be a positive integer.                                        */
+typedef struct {
+    int32_t N, b, ng, p, N1;
+} kkt_dims;
+
+typedef struct {
+    int32_t num_systems;
+    int32_t nrhs;
+    int32_t num_items;        /* (system, segment) work items                      */
+    int32_t num_classes;      /* block-size classes = persistent launches per call */
+    int64_t D_len, C_len, B_len, corner_len, rhs_len;   /* pool lengths, doubles   */
+    int64_t workspace_bytes;
+    double  factor_flops;     /* standard flop count of one factorization          */
+    double  solve_flops;      /* one solve (all rhs)                               */
+    int64_t factor_words;     /* |hat L| in doubles, including fill-in             */
+    int64_t input_words;      /* |Psi| in doubles (D, C, B, corner pools)           */
+} kkt_plan_info;
+
+/* Where one system lives.  Pool offsets in doubles from the pool base; factor
+ * offsets in doubles from the workspace's factor region (see kkt_plan_info).
+ * The factor is stored block for block in the pattern of the input:
+ *   Ld[s]  (b x b, lower)  hat D of segment stages, hat A_k at separators
+ *   Lc[s]  (b x b)         the factor block coupling stages s and s+1, oriented as
+ *                          in hat L: hat L[s+1, s] (hat E, or hat F_k when s is the
+ *                          last stage of segment k), except at a separator s, where
+ *                          it is hat L[s, s+1] (hat B^T_{1k}, Eq. 5)
+ *   Lb[s]  (ng x b)        hat G of segment stages, hat Q_k at separators
+ *   Lg     (ng x ng, lower) hat R
+ *   fill   ((N_k - 1) b x b per segment k >= 2) hat B^T_{ik} = hat L[sep_k, (i,k)], i >= 2
+ *   H      ((p - 2) b x b) hat H_k = hat L[sep_{k+1}, sep_k], k = 2..p-1        */
+typedef struct {
+    int32_t N, b, ng, p, N1, Nk;      /* Nk: length of segments 2..p (0 if p = 1) */
+    int64_t off_D, off_C, off_B, off_corner, off_rhs;
+    int64_t off_Ld, off_Lc, off_Lb, off_Lg, off_fill, off_H;
+} kkt_system_layout;
+
+/* Plan a batch of num_systems systems (dims: host array), nrhs right-hand sides
+ * each.  Fails with KKT_EDIMS on an unsupported shape. */
+int kkt_plan_create(kkt_plan **plan, int32_t num_systems, const kkt_dims *dims, int32_t nrhs);
+int kkt_plan_destroy(kkt_plan *plan);
+int kkt_plan_get_info(const kkt_plan *plan, kkt_plan_info *info);
+int kkt_plan_system(const kkt_plan *plan, int32_t s, kkt_system_layout *out);
+/* Byte offset of the factor region inside the workspace. */
+int64_t kkt_plan_factor_offset(const kkt_plan *plan);
+
+/* Copy the plan's tables into the workspace (enqueued on stream; the host copy
+ * is pageable, so the call returns once the copy is staged).  Once per workspace. */
+int kkt_workspace_init(const kkt_plan *plan, void *workspace, hipStream_t stream);
+
+/* Factorization (Algorithm 1).  info: device int32[S]. */
+int kkt_factor(const kkt_plan *plan, const double *D, const double *C, const double *B,
+               const double *corner, void *workspace, int32_t *info, hipStream_t stream);
+
+/* Forward and backward substitution (Algorithms 2, 3) with a factor already in
+ * the workspace; rhs (device, rhs pool layout) is overwritten by x. */
+int kkt_solve(const kkt_plan *plan, void *workspace, double *rhs, hipStream_t stream);
+
+/* Factorization fused with the forward substitution, then the backward
+ * substitution, in one pass over the data: rhs is overwritten by x. */
+int kkt_factor_solve(const kkt_plan *plan, const double *D, const double *C, const double *B,
+                     const double *corner, void *workspace, double *rhs, int32_t *info,
+                     hipStream_t stream);
+
+/* Adjoint of x = Psi^{-1} r for a loss L(x): given x and gx = dL/dx (rhs pool
+ * layout), overwrite gx with lambda = Psi^{-1} gx = dL/dr and write the
+ * gradients restricted to the block pattern (pools laid out like D, C, B, corner):
+ *   dD_i = -sym(lambda_i x_i^T),  dC_i = -(lambda_{i+1} x_i^T + x_{i+1} lambda_i^T),
+ *   dB_i = -(lambda_g x_i^T + x_g lambda_i^T),  dcorner = -sym(lambda_g x_g^T),
+ * summed over the rhs columns.  Uses the factor in the workspace. */
+int kkt_solve_adjoint(const kkt_plan *plan, void *workspace, const double *x, double *gx,
+                      double *dD, double *dC, double *dB, double *dcorner, hipStream_t stream);
+
+const char *kkt_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KKT_MI355X_H */

@@ -1,0 +1,234 @@
+"""Thin Python binding of the C ABI in include/kkt.h (argument marshalling only).
+
+Every step of the factorization and the solves runs in the HIP library
+``libkkt.so``; PyTorch only provides device memory and the stream.  Importing
+this module fails loudly if the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkkt.so")
+
+KKT_OK = 0
+MAX_B, MAX_NG, MAX_NRHS = 32, 16, 8
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("b", ctypes.c_int32), ("ng", ctypes.c_int32),
+                ("p", ctypes.c_int32), ("N1", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("num_systems", ctypes.c_int32), ("nrhs", ctypes.c_int32), ("num_items", ctypes.c_int32),
+                ("num_classes", ctypes.c_int32), ("D_len", ctypes.c_int64), ("C_len", ctypes.c_int64),
+                ("B_len", ctypes.c_int64), ("corner_len", ctypes.c_int64), ("rhs_len", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64), ("factor_flops", ctypes.c_double),
+                ("solve_flops", ctypes.c_double), ("factor_words", ctypes.c_int64),
+                ("input_words", ctypes.c_int64)]
+
+
+class SystemLayout(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("b", ctypes.c_int32), ("ng", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("N1", ctypes.c_int32), ("Nk", ctypes.c_int32),
+                ("off_D", ctypes.c_int64), ("off_C", ctypes.c_int64), ("off_B", ctypes.c_int64),
+                ("off_corner", ctypes.c_int64), ("off_rhs", ctypes.c_int64),
+                ("off_Ld", ctypes.c_int64), ("off_Lc", ctypes.c_int64), ("off_Lb", ctypes.c_int64),
+                ("off_Lg", ctypes.c_int64), ("off_fill", ctypes.c_int64), ("off_H", ctypes.c_int64)]
+
+
+class KKTError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libkkt.so`` (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libkkt.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.kkt_plan_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(Dims), i32]
+        L.kkt_plan_destroy.argtypes = [vp]
+        L.kkt_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        L.kkt_plan_system.argtypes = [vp, i32, ctypes.POINTER(SystemLayout)]
+        L.kkt_plan_factor_offset.argtypes = [vp]
+        L.kkt_plan_factor_offset.restype = i64
+        L.kkt_workspace_init.argtypes = [vp, vp, vp]
+        L.kkt_factor.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.kkt_solve.argtypes = [vp, vp, vp, vp]
+        L.kkt_factor_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.kkt_solve_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.kkt_status_string.restype = ctypes.c_char_p
+        L.kkt_status_string.argtypes = [ctypes.c_int]
+        for name in ("kkt_plan_create", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
+                     "kkt_workspace_init", "kkt_factor", "kkt_solve", "kkt_factor_solve", "kkt_solve_adjoint"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("kkt_plan_create", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
+            "kkt_plan_factor_offset", "kkt_workspace_init", "kkt_factor", "kkt_solve",
+            "kkt_factor_solve", "kkt_solve_adjoint", "kkt_status_string")
+
+
+def _check(rc, what):
+    if rc != KKT_OK:
+        raise KKTError("%s failed: %s (%d)" % (what, lib().kkt_status_string(rc).decode(), rc))
+
+
+def _ptr(t):
+    """Device pointer of a float64 / int32 / uint8 CUDA tensor, or None for an empty one."""
+    if t is None or t.numel() == 0:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A plan for a batch of systems: ``dims`` is a list of (N, b, ng[, p[, N1]])."""
+
+    def __init__(self, dims, nrhs=1):
+        dims = [tuple(d) for d in dims]
+        arr = (Dims * len(dims))()
+        for i, d in enumerate(dims):
+            N, b, ng = int(d[0]), int(d[1]), int(d[2])
+            p = int(d[3]) if len(d) > 3 else 1
+            N1 = int(d[4]) if len(d) > 4 else 0
+            arr[i] = Dims(N, b, ng, p, N1)
+        h = ctypes.c_void_p()
+        _check(lib().kkt_plan_create(ctypes.byref(h), len(dims), arr, int(nrhs)), "kkt_plan_create")
+        self._h = h
+        self.nrhs = int(nrhs)
+        self.S = len(dims)
+        info = PlanInfo()
+        _check(lib().kkt_plan_get_info(h, ctypes.byref(info)), "kkt_plan_get_info")
+        self.info = info
+        self.factor_offset = int(lib().kkt_plan_factor_offset(h))
+        self.layouts = []
+        for s in range(self.S):
+            lay = SystemLayout()
+            _check(lib().kkt_plan_system(h, s, ctypes.byref(lay)), "kkt_plan_system")
+            self.layouts.append(lay)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.kkt_plan_destroy(h)
+            self._h = None
+
+    # ---- memory
+    def pool_lengths(self):
+        i = self.info
+        return dict(D=i.D_len, C=i.C_len, B=i.B_len, corner=i.corner_len, rhs=i.rhs_len)
+
+    def new_workspace(self, device="cuda", stream=None):
+        import torch
+        ws = torch.empty(int(self.info.workspace_bytes) + 256, dtype=torch.uint8, device=device)
+        off = (-ws.data_ptr()) % 256
+        ws = ws[off:off + int(self.info.workspace_bytes)]
+        self.init_workspace(ws, stream)
+        return ws
+
+    def init_workspace(self, ws, stream=None):
+        self._check_ws(ws)
+        _check(lib().kkt_workspace_init(self._h, _ptr(ws), _stream(stream)), "kkt_workspace_init")
+
+    def _check_ws(self, ws):
+        import torch
+        if ws.dtype != torch.uint8 or ws.numel() < self.info.workspace_bytes:
+            raise ValueError("workspace must be a uint8 device tensor of >= %d bytes" % self.info.workspace_bytes)
+
+    def _check_pool(self, t, name):
+        import torch
+        n = self.pool_lengths()[name]
+        if n == 0:
+            return
+        if t is None or t.dtype != torch.float64 or t.numel() < n:
+            raise ValueError("%s must be a float64 device tensor with >= %d elements" % (name, n))
+
+    # ---- calls
+    def factor(self, D, C, B, corner, ws, info, stream=None):
+        for t, n in ((D, "D"), (C, "C"), (B, "B"), (corner, "corner")):
+            self._check_pool(t, n)
+        self._check_ws(ws)
+        _check(lib().kkt_factor(self._h, _ptr(D), _ptr(C), _ptr(B), _ptr(corner), _ptr(ws), _ptr(info),
+                                _stream(stream)), "kkt_factor")
+
+    def factor_solve(self, D, C, B, corner, ws, rhs, info, stream=None):
+        for t, n in ((D, "D"), (C, "C"), (B, "B"), (corner, "corner"), (rhs, "rhs")):
+            self._check_pool(t, n)
+        self._check_ws(ws)
+        _check(lib().kkt_factor_solve(self._h, _ptr(D), _ptr(C), _ptr(B), _ptr(corner), _ptr(ws), _ptr(rhs),
+                                      _ptr(info), _stream(stream)), "kkt_factor_solve")
+
+    def solve(self, ws, rhs, stream=None):
+        self._check_pool(rhs, "rhs")
+        self._check_ws(ws)
+        _check(lib().kkt_solve(self._h, _ptr(ws), _ptr(rhs), _stream(stream)), "kkt_solve")
+
+    def solve_adjoint(self, ws, x, gx, dD, dC, dB, dcorner, stream=None):
+        for t, n in ((x, "rhs"), (gx, "rhs"), (dD, "D"), (dC, "C"), (dB, "B"), (dcorner, "corner")):
+            self._check_pool(t, n)
+        self._check_ws(ws)
+        _check(lib().kkt_solve_adjoint(self._h, _ptr(ws), _ptr(x), _ptr(gx), _ptr(dD), _ptr(dC), _ptr(dB),
+                                       _ptr(dcorner), _stream(stream)), "kkt_solve_adjoint")
+
+    # ---- reading the factor back (host side, for inspection and tests)
+    def factor_blocks(self, ws_host, s):
+        """Dict {(row, col): block} of hat L for system s, from a host copy (numpy
+        uint8 array) of the workspace.  Labels are natural 0-based stage indices,
+        'g' for the global block."""
+        lay = self.layouts[s]
+        F = np.frombuffer(ws_host[self.factor_offset:].tobytes(), dtype=np.float64)
+        N, b, ng, p, N1, Nk = lay.N, lay.b, lay.ng, lay.p, lay.N1, lay.Nk
+        b2 = b * b
+        seps = [N1 + (k - 2) * (Nk + 1) for k in range(2, p + 1)]
+        sepset = set(seps)
+        out = {}
+        for st in range(N):
+            out[(st, st)] = F[lay.off_Ld + st * b2: lay.off_Ld + (st + 1) * b2].reshape(b, b)
+            if ng:
+                out[("g", st)] = F[lay.off_Lb + st * ng * b: lay.off_Lb + (st + 1) * ng * b].reshape(ng, b)
+        for st in range(N - 1):
+            blk = F[lay.off_Lc + st * b2: lay.off_Lc + (st + 1) * b2].reshape(b, b)
+            out[(st, st + 1) if st in sepset else (st + 1, st)] = blk
+        for k in range(2, p + 1):
+            sep = seps[k - 2]
+            first = sep + 1
+            for i in range(2, Nk + 1):
+                o = lay.off_fill + ((k - 2) * (Nk - 1) + (i - 2)) * b2
+                out[(sep, first + i - 1)] = F[o:o + b2].reshape(b, b)
+            if k < p:
+                o = lay.off_H + (k - 2) * b2
+                out[(seps[k - 1], sep)] = F[o:o + b2].reshape(b, b)
+        if ng:
+            out[("g", "g")] = F[lay.off_Lg: lay.off_Lg + ng * ng].reshape(ng, ng)
+        return out
+
+    def segment_lengths(self, s):
+        lay = self.layouts[s]
+        return [lay.N1] + [lay.Nk] * (lay.p - 1)
+
+
+def pack_to_device(pools, device="cuda"):
+    """Move numpy pools (from ``workloads.pack``) to device float64 tensors."""
+    import torch
+    return {k: torch.from_numpy(np.ascontiguousarray(v)).to(device=device, dtype=torch.float64)
+            for k, v in pools.items()}
