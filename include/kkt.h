@@ -144,6 +144,26 @@ int kkt_factor_solve(const kkt_plan *plan, const double *D, const double *C, con
 int kkt_solve_adjoint(const kkt_plan *plan, void *workspace, const double *x, double *gx,
                       double *dD, double *dC, double *dB, double *dcorner, hipStream_t stream);
 
+/* Scheduler health of the last call on this workspace: *flag = 0 if every
+ * backward-sweep item of a segmented system was handed over in time, nonzero if
+ * a worker gave up waiting (its spin limit, kkt_plan_set_spin_limit, ran out);
+ * the solutions of that call are then not valid.  Synchronises the stream. */
+int kkt_workspace_error(const kkt_plan *plan, const void *workspace, hipStream_t stream, int32_t *flag);
+
+/* Upper bound on the polls a worker makes while waiting for a backward-sweep
+ * item (each poll sleeps briefly); default 4 Mi.  For tests of the error path. */
+int kkt_plan_set_spin_limit(kkt_plan *plan, int32_t limit);
+
+/* Block-size class c of the plan (0 <= c < num_classes): padded block size,
+ * number of work items, threads per workgroup and LDS bytes of its launch. */
+int kkt_plan_class_info(const kkt_plan *plan, int32_t c, int32_t *block_pad, int32_t *num_items,
+                        int32_t *threads, int64_t *lds_bytes);
+
+/* Record start / stop on the caller's stream around the persistent launch of
+ * class c in every later call (NULL, NULL turns it off).  For measurement: the
+ * events are the caller's and must outlive the calls that record them. */
+int kkt_plan_set_class_events(kkt_plan *plan, int32_t c, hipEvent_t start, hipEvent_t stop);
+
 const char *kkt_status_string(int status);
 
 #ifdef __cplusplus

@@ -420,6 +420,12 @@ struct kkt_plan {
     kkt_plan_info info{};
     int spin_limit = 1 << 22;
     mutable const void *factored_ws = nullptr;
+    // launch configuration per (class, mode), filled on first use so that later
+    // calls (and graph capture) make no device queries
+    mutable int grid[4][4] = {{0}};
+    // optional per-class timing events (kkt_plan_set_class_events)
+    hipEvent_t ev_start[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_stop[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -453,10 +459,6 @@ int launch_mode(const kkt_plan *plan, int mode, const Args &base, hipStream_t st
                        base.ctr, nctr, base.arrive, (mode <= M_FACTOR_SOLVE) ? base.failidx : nullptr, plan->S,
                        base.s3_ready - 0, (int)plan->info.num_items, (mode <= M_FACTOR_SOLVE) ? info : nullptr);
     if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return KKT_ELAUNCH;
-    int ncu = 0;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return KKT_ELAUNCH;
     for (size_t ci = 0; ci < plan->cls.size(); ++ci) {
         const kkt_plan::Cls &c = plan->cls[ci];
         if (c.item_cnt == 0) continue;
@@ -468,17 +470,25 @@ int launch_mode(const kkt_plan *plan, int mode, const Args &base, hipStream_t st
         a.n_s3 = c.s3_cnt;
         a.ctr = base.ctr + 4 * ci;
         kfun_t fn = kernel_for_class(c.cls, mode);
-        if (c.lds > 65536) {
-            if (hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds) !=
-                hipSuccess)
+        int &grid = plan->grid[ci][mode];
+        if (grid == 0) {
+            int dev = 0, ncu = 0, occ = 0;
+            if (hipGetDevice(&dev) != hipSuccess) return KKT_ELAUNCH;
+            if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
                 return KKT_ELAUNCH;
+            if (c.lds > 65536 &&
+                hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds) !=
+                    hipSuccess)
+                return KKT_ELAUNCH;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, c.nt, c.lds) != hipSuccess ||
+                occ < 1)
+                occ = 1;
+            grid = std::max(1, std::min(c.item_cnt, occ * ncu));
         }
-        int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, c.nt, c.lds) != hipSuccess || occ < 1)
-            occ = 1;
-        const int grid = std::max(1, std::min(c.item_cnt, occ * ncu));
+        if (plan->ev_start[ci] && hipEventRecord(plan->ev_start[ci], stream) != hipSuccess) return KKT_ELAUNCH;
         hipLaunchKernelGGL(fn, dim3(grid), dim3(c.nt), c.lds, stream, a);
         if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
+        if (plan->ev_stop[ci] && hipEventRecord(plan->ev_stop[ci], stream) != hipSuccess) return KKT_ELAUNCH;
     }
     return KKT_OK;
 }
@@ -740,6 +750,51 @@ int kkt_solve_adjoint(const kkt_plan *plan, void *workspace, const double *x, do
     Args a = base_args(plan, workspace);
     a.rhs = gx; a.xp = x; a.dD = dD; a.dC = dC; a.dB = dB; a.dcorner = dcorner;
     return launch_mode(plan, M_ADJOINT, a, stream, nullptr);
+}
+
+int kkt_workspace_error(const kkt_plan *plan, const void *workspace, hipStream_t stream, int32_t *flag)
+{
+    if (!plan || !workspace || !flag) return KKT_EPOINTER;
+    std::vector<int> ctr(4 * plan->cls.size(), 0);
+    if (ctr.empty()) { *flag = 0; return KKT_OK; }
+    if (hipMemcpyAsync(ctr.data(), (const char *)workspace + plan->o_ctr, sizeof(int) * ctr.size(),
+                       hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return KKT_ELAUNCH;
+    int f = 0;
+    for (size_t c = 0; c < plan->cls.size(); ++c) f |= ctr[4 * c + 3];
+    *flag = f;
+    return KKT_OK;
+}
+
+int kkt_plan_set_spin_limit(kkt_plan *plan, int32_t limit)
+{
+    if (!plan) return KKT_EPOINTER;
+    if (limit < 1) return KKT_EDIMS;
+    plan->spin_limit = limit;
+    return KKT_OK;
+}
+
+int kkt_plan_class_info(const kkt_plan *plan, int32_t c, int32_t *block_pad, int32_t *num_items,
+                        int32_t *threads, int64_t *lds_bytes)
+{
+    if (!plan) return KKT_EPOINTER;
+    if (c < 0 || c >= (int)plan->cls.size()) return KKT_EDIMS;
+    const kkt_plan::Cls &C = plan->cls[c];
+    if (block_pad) *block_pad = C.bp;
+    if (num_items) *num_items = C.item_cnt;
+    if (threads) *threads = C.nt;
+    if (lds_bytes) *lds_bytes = (int64_t)C.lds;
+    return KKT_OK;
+}
+
+int kkt_plan_set_class_events(kkt_plan *plan, int32_t c, hipEvent_t start, hipEvent_t stop)
+{
+    if (!plan) return KKT_EPOINTER;
+    if (c < 0 || c >= (int)plan->cls.size()) return KKT_EDIMS;
+    plan->ev_start[c] = start;
+    plan->ev_stop[c] = stop;
+    return KKT_OK;
 }
 
 const char *kkt_status_string(int status)

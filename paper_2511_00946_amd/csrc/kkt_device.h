@@ -189,28 +189,77 @@ __device__ __forceinline__ double dot_col(const double (&v)[BP], const double *_
     return a0 + a1;
 }
 
-// Copy a rows x cols row-major global block into LDS with a row pitch (coalesced
-// reads), optionally subtracting a second block.
-template <int NT>
-__device__ __forceinline__ void load_block(double *dst, int pitch, const double *src, const double *sub, int rows, int cols)
+// Row of a flat index e of a row-major block of width w (e < 2^16, w <= 64):
+// (e + 0.5) / w in float is never within 0.5 / w of an integer, and its rounding
+// error is far below that, so truncation gives floor(e / w) exactly.
+__device__ __forceinline__ int row_of(int e, float invw) { return (int)(((float)e + 0.5f) * invw); }
+
+// Copy a rows x cols row-major global block (rows * cols <= MAXE) into LDS with a
+// row pitch, optionally subtracting a second block: every load is issued before
+// the first LDS store, so the block costs one memory latency, not one per element.
+template <int NT, int MAXE>
+__device__ __forceinline__ void load_block(double *dst, int pitch, const double *src, const double *sub, int rows,
+                                           int cols)
 {
+    constexpr int M = (MAXE + NT - 1) / NT;
     const int n = rows * cols;
-    for (int e = threadIdx.x; e < n; e += NT) {
-        const int r = e / cols, c = e - r * cols;
-        double v = src[e];
-        if (sub) v -= sub[e];
-        dst[r * pitch + c] = v;
+    double v[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int e = threadIdx.x + m * NT;
+        v[m] = 0.0;
+        if (e < n) {
+            v[m] = src[e];
+            if (sub) v[m] -= sub[e];
+        }
+    }
+    const float invc = 1.0f / (float)cols;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int e = threadIdx.x + m * NT;
+        if (e < n) {
+            const int r = row_of(e, invc);
+            dst[r * pitch + (e - r * cols)] = v[m];
+        }
     }
 }
 
-// rhs rows (rows x nr, contiguous) into LDS (pitch nr), optionally plus a second block.
-template <int NT>
+// rhs rows (n <= MAXE contiguous doubles) into LDS, optionally plus a second block.
+template <int NT, int MAXE>
 __device__ __forceinline__ void load_rhs(double *dst, const double *src, const double *add, int n)
 {
-    for (int e = threadIdx.x; e < n; e += NT) {
-        double v = src[e];
-        if (add) v += add[e];
-        dst[e] = v;
+    constexpr int M = (MAXE + NT - 1) / NT;
+    double v[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int e = threadIdx.x + m * NT;
+        v[m] = 0.0;
+        if (e < n) {
+            v[m] = src[e];
+            if (add) v[m] += add[e];
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int e = threadIdx.x + m * NT;
+        if (e < n) dst[e] = v[m];
+    }
+}
+
+// Coalesced store of rows [0, rows) x [0, cols) of an LDS block with a row pitch
+// to a row-major global block (rows * cols <= MAXE).
+template <int NT, int MAXE>
+__device__ __forceinline__ void store_block(double *dst, const double *lds, int pitch, int rows, int cols)
+{
+    const int n = rows * cols;
+    const float invc = 1.0f / (float)cols;
+#pragma unroll
+    for (int m = 0; m < (MAXE + NT - 1) / NT; ++m) {
+        const int e = threadIdx.x + m * NT;
+        if (e < n) {
+            const int r = row_of(e, invc);
+            dst[e] = lds[r * pitch + (e - r * cols)];
+        }
     }
 }
 

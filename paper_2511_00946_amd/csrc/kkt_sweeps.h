@@ -31,16 +31,16 @@ struct Chain {
         const int b = sd.b, ng = sd.ng, nr = a.nr, s = stage(i);
         const long long b2 = (long long)b * b;
         if (!RED) {
-            load_block<NT>(L.P, P, a.D + sd.oD + s * b2, nullptr, b, b);
-            if (has_next(i)) load_block<NT>(L.P + BP * P, P, a.C + sd.oC + s * b2, nullptr, b, b);
-            if (ng) load_block<NT>(L.P + 2 * BP * P, P, a.B + sd.oB + (long long)s * ng * b, nullptr, ng, b);
-            if (fwd) load_rhs<NT>(L.W, a.rhs + sd.oRhs + (long long)s * b * nr, nullptr, b * nr);
+            load_block<NT, BP * BP>(L.P, P, a.D + sd.oD + s * b2, nullptr, b, b);
+            if (has_next(i)) load_block<NT, BP * BP>(L.P + BP * P, P, a.C + sd.oC + s * b2, nullptr, b, b);
+            if (ng) load_block<NT, NGM * BP>(L.P + 2 * BP * P, P, a.B + sd.oB + (long long)s * ng * b, nullptr, ng, b);
+            if (fwd) load_rhs<NT, BP * 8>(L.W, a.rhs + sd.oRhs + (long long)s * b * nr, nullptr, b * nr);
         } else {
             const double *sc = scr(i + 1);
-            load_block<NT>(L.P, P, a.F + sd.oLd + s * b2, sc + scr_dA(b, ng, nr), b, b);
-            if (has_next(i)) load_block<NT>(L.P + BP * P, P, a.F + sd.oH + i * b2, nullptr, b, b);
-            if (ng) load_block<NT>(L.P + 2 * BP * P, P, a.F + sd.oLb + (long long)s * ng * b, sc + scr_dQ(b, ng, nr), ng, b);
-            if (fwd) load_rhs<NT>(L.W, a.rhs + sd.oRhs + (long long)s * b * nr, sc + scr_dy(b, ng, nr), b * nr);
+            load_block<NT, BP * BP>(L.P, P, a.F + sd.oLd + s * b2, sc + scr_dA(b, ng, nr), b, b);
+            if (has_next(i)) load_block<NT, BP * BP>(L.P + BP * P, P, a.F + sd.oH + i * b2, nullptr, b, b);
+            if (ng) load_block<NT, NGM * BP>(L.P + 2 * BP * P, P, a.F + sd.oLb + (long long)s * ng * b, sc + scr_dQ(b, ng, nr), ng, b);
+            if (fwd) load_rhs<NT, BP * 8>(L.W, a.rhs + sd.oRhs + (long long)s * b * nr, sc + scr_dy(b, ng, nr), b * nr);
         }
     }
 };
@@ -84,7 +84,7 @@ __device__ __forceinline__ int sweep_factor(const Args &a, const SysDesc &sd, in
             const int r = e / b, c = e - r * b;
             L.A[r * P + c] = 0.5 * (Ds[e] + Ds[c * b + r]);
         }
-        if (ng) load_block<NT>(L.Q, P, a.B + sd.oB + (long long)sep * ng * b, nullptr, ng, b);
+        if (ng) load_block<NT, NGM * BP>(L.Q, P, a.B + sd.oB + (long long)sep * ng * b, nullptr, ng, b);
     }
     __syncthreads();
     ch.stage_factor_inputs(0, L, FWD);
@@ -125,22 +125,22 @@ __device__ __forceinline__ int sweep_factor(const Args &a, const SysDesc &sd, in
         __syncthreads();
         {
             double *o = F + sd.oLd + gs * b2;
-            for (int e = tid; e < b * b; e += NT) { const int r = e / b; o[e] = L.P[r * P + (e - r * b)]; }
+            store_block<NT, BP * BP>(o, L.P, P, b, b);
         }
         if (FWD)
             for (int e = tid; e < b * nr; e += NT) a.rhs[sd.oRhs + (long long)gs * b * nr + e] = L.Y[e];
         if (hasE) {
             double *o = RED ? F + sd.oH + i * b2 : F + sd.oLc + gs * b2;
-            for (int e = tid; e < b * b; e += NT) { const int r = e / b; o[e] = L.P[(E0 + r) * P + (e - r * b)]; }
+            store_block<NT, BP * BP>(o, L.P + E0 * P, P, b, b);
         }
         if (ng) {
             double *o = F + sd.oLb + (long long)gs * ng * b;
-            for (int e = tid; e < ng * b; e += NT) { const int r = e / b; o[e] = L.P[(G0 + r) * P + (e - r * b)]; }
+            store_block<NT, NGM * BP>(o, L.P + G0 * P, P, ng, b);
         }
         if (hasF) {
             double *o = (i == 0) ? F + sd.oLc + sep * b2
                                  : F + sd.oFill + ((long long)(k - 2) * (sd.Nk - 1) + (i - 1)) * b2;
-            for (int e = tid; e < b * b; e += NT) { const int r = e / b; o[e] = L.P[(F0 + r) * P + (e - r * b)]; }
+            store_block<NT, BP * BP>(o, L.P + F0 * P, P, b, b);
         }
 
         // Gram of the panel rows (Eqs. 6, 8a, 8b).  D lanes take the coupling row of
@@ -271,18 +271,18 @@ __device__ __forceinline__ void sweep_forward(const Args &a, const SysDesc &sd, 
     {
         const int s0 = ch.stage(0);
         const double *add = RED ? ch.scr(1) + scr_dy(b, ng, nr) : nullptr;
-        load_rhs<NT>(L.W, a.rhs + sd.oRhs + (long long)s0 * b * nr, add, b * nr);
+        load_rhs<NT, BP * 8>(L.W, a.rhs + sd.oRhs + (long long)s0 * b * nr, add, b * nr);
     }
     for (int i = 0; i < len; ++i) {
         const int gs = ch.stage(i);
         const bool hasE = ch.has_next(i);
-        load_block<NT>(stD, P, F + sd.oLd + gs * b2, nullptr, b, b);
-        if (hasE) load_block<NT>(stE, P, RED ? F + sd.oH + i * b2 : F + sd.oLc + gs * b2, nullptr, b, b);
-        if (ng) load_block<NT>(stG, P, F + sd.oLb + (long long)gs * ng * b, nullptr, ng, b);
+        load_block<NT, BP * BP>(stD, P, F + sd.oLd + gs * b2, nullptr, b, b);
+        if (hasE) load_block<NT, BP * BP>(stE, P, RED ? F + sd.oH + i * b2 : F + sd.oLc + gs * b2, nullptr, b, b);
+        if (ng) load_block<NT, NGM * BP>(stG, P, F + sd.oLb + (long long)gs * ng * b, nullptr, ng, b);
         if (hasF) {
             const double *src = (i == 0) ? F + sd.oLc + sep * b2
                                          : F + sd.oFill + ((long long)(k - 2) * (sd.Nk - 1) + (i - 1)) * b2;
-            load_block<NT>(stF, P, src, nullptr, b, b);
+            load_block<NT, BP * BP>(stF, P, src, nullptr, b, b);
         }
         __syncthreads();
         if (tid < 64) {
@@ -343,124 +343,130 @@ __device__ __forceinline__ void sweep_forward(const Args &a, const SysDesc &sd, 
     __syncthreads();
 }
 
-// Backward substitution of one chain (Algorithm 3, Eqs. 11, 12), run by wave 0:
-// lane c owns column c of every block.  The current solution (x, or lambda in
-// the adjoint) is read from and written to rhs in place.  With ADJ the gradient
-// blocks of the stages visited are written as well.
+// Backward substitution of one chain (Algorithm 3, Eqs. 11, 12).  All threads
+// stage each stage's blocks (hat D, coupling block, hat G, fill block) and its y
+// rows into LDS with coalesced loads; wave 0 computes, lane c owning column c.
+// The current solution (x, or lambda in the adjoint) is read from and written to
+// rhs in place.  With ADJ the gradient blocks of the stages visited are written.
 template <int BP, bool ADJ, bool RED>
 __device__ __forceinline__ void sweep_backward(const Args &a, const SysDesc &sd, int k, const Lds &L)
 {
-    const int lane = threadIdx.x;
-    if (lane >= 64) return;
+    constexpr int NT = K<BP>::NT, P = K<BP>::PITCH;
     const Chain<BP, RED> ch{a, sd, k};
+    const int tid = threadIdx.x;
     const int b = sd.b, ng = sd.ng, nr = a.nr, N = sd.N;
     const long long b2 = (long long)b * b;
     const double *F = a.F;
     const bool hasF = !RED && k > 1;
     const int len = ch.length();
     const int sep = hasF ? sep_of(sd, k) : -1;
-    const int c = lane;
+    const int c = tid;
     const bool cv = c < b;
     double *X = a.rhs + sd.oRhs;
+    const double *xp = ADJ ? a.xp + sd.oRhs : nullptr;
+    double *stD = L.P, *stE = L.P + BP * P, *stG = L.P + 2 * BP * P, *stF = L.A;
 
-    // solution (and primal) at g and at the separator
-    for (int e = lane; e < ng * nr; e += 64) {
+    // solution (and primal) at g, at the separator, and at the stage after the chain
+    for (int e = tid; e < ng * nr; e += NT) {
         L.XG[e] = X[(long long)N * b * nr + e];
-        if (ADJ) L.PG[e] = a.xp[sd.oRhs + (long long)N * b * nr + e];
+        if (ADJ) L.PG[e] = xp[(long long)N * b * nr + e];
     }
     if (hasF)
-        for (int e = lane; e < b * nr; e += 64) {
+        for (int e = tid; e < b * nr; e += NT) {
             L.XS[e] = X[(long long)sep * b * nr + e];
-            if (ADJ) L.PS[e] = a.xp[sd.oRhs + (long long)sep * b * nr + e];
+            if (ADJ) L.PS[e] = xp[(long long)sep * b * nr + e];
         }
-    {
-        const int s_last = ch.stage(len - 1);
-        if (ch.has_next(len - 1)) {
-            const int nxt = RED ? sep_of(sd, len + 2) : s_last + 1;
-            for (int e = lane; e < b * nr; e += 64) {
-                L.XN[e] = X[(long long)nxt * b * nr + e];
-                if (ADJ) L.PN[e] = a.xp[sd.oRhs + (long long)nxt * b * nr + e];
-            }
+    if (!RED && ch.has_next(len - 1)) {
+        const int nxt = ch.stage(len - 1) + 1;
+        for (int e = tid; e < b * nr; e += NT) {
+            L.XN[e] = X[(long long)nxt * b * nr + e];
+            if (ADJ) L.PN[e] = xp[(long long)nxt * b * nr + e];
         }
     }
-    wave_sync();
 
     for (int i = len - 1; i >= 0; --i) {
         const int gs = ch.stage(i);
         const bool hasE = ch.has_next(i);
-        const double *Ld = F + sd.oLd + gs * b2;
-        double dcol[BP];
+        __syncthreads();   // previous stage done with the staging area and XC
+        load_block<NT, BP * BP>(stD, P, F + sd.oLd + gs * b2, nullptr, b, b);
+        if (hasE) load_block<NT, BP * BP>(stE, P, RED ? F + sd.oH + i * b2 : F + sd.oLc + gs * b2, nullptr, b, b);
+        if (ng) load_block<NT, NGM * BP>(stG, P, F + sd.oLb + (long long)gs * ng * b, nullptr, ng, b);
+        if (hasF) {
+            const double *src = (i == 0) ? F + sd.oLc + sep * b2
+                                         : F + sd.oFill + ((long long)(k - 2) * (sd.Nk - 1) + (i - 1)) * b2;
+            load_block<NT, BP * BP>(stF, P, src, nullptr, b, b);
+        }
+        load_rhs<NT, BP * 8>(L.XC, X + (long long)gs * b * nr, nullptr, b * nr);   // y of this stage
+        if (ADJ) load_rhs<NT, BP * 8>(L.PC, xp + (long long)gs * b * nr, nullptr, b * nr);
+        __syncthreads();
+        if (tid < 64) {
+            double dcol[BP];
 #pragma unroll
-        for (int l = 0; l < BP; ++l) dcol[l] = (cv && l < b) ? Ld[l * b + c] : (l == c ? 1.0 : 0.0);
-        const double dinv = cv ? 1.0 / Ld[c * b + c] : 1.0;
-        const double *E = hasE ? (RED ? F + sd.oH + i * b2 : F + sd.oLc + gs * b2) : nullptr;
-        const double *G = ng ? F + sd.oLb + (long long)gs * ng * b : nullptr;
-        const double *Fb = hasF ? ((i == 0) ? F + sd.oLc + sep * b2
-                                            : F + sd.oFill + ((long long)(k - 2) * (sd.Nk - 1) + (i - 1)) * b2)
-                                : nullptr;
-        for (int j = 0; j < nr; ++j) {
-            double acc = cv ? X[((long long)gs * b + c) * nr + j] : 0.0;
-            if (E)
-                for (int r = 0; r < b; ++r) acc = fma(-(cv ? E[r * b + c] : 0.0), L.XN[r * nr + j], acc);
-            if (G)
-                for (int q = 0; q < ng; ++q) acc = fma(-(cv ? G[q * b + c] : 0.0), L.XG[q * nr + j], acc);
-            if (Fb)
-                for (int r = 0; r < b; ++r) acc = fma(-(cv ? Fb[r * b + c] : 0.0), L.XS[r * nr + j], acc);
-            const double xv = back_subst<BP>(dcol, acc, dinv);
-            if (cv) {
-                X[((long long)gs * b + c) * nr + j] = xv;
-                L.XC[c * nr + j] = xv;
-            }
-        }
-        if (ADJ && cv)
-            for (int j = 0; j < nr; ++j) L.PC[c * nr + j] = a.xp[sd.oRhs + ((long long)gs * b + c) * nr + j];
-        wave_sync();
-        if (ADJ && cv) {
-            // dD_gs = -sym(lambda x^T); dB_gs = -(lambda_g x^T + x_g lambda^T); dC_gs (stage couplings only)
-            double *dD = a.dD + sd.oD + gs * b2;
-            for (int r = 0; r < b; ++r) {
-                double s = 0.0;
-                for (int j = 0; j < nr; ++j)
-                    s += L.XC[r * nr + j] * L.PC[c * nr + j] + L.PC[r * nr + j] * L.XC[c * nr + j];
-                dD[r * b + c] = -0.5 * s;
-            }
-            if (ng) {
-                double *dB = a.dB + sd.oB + (long long)gs * ng * b;
-                for (int q = 0; q < ng; ++q) {
-                    double s = 0.0;
-                    for (int j = 0; j < nr; ++j)
-                        s += L.XG[q * nr + j] * L.PC[c * nr + j] + L.PG[q * nr + j] * L.XC[c * nr + j];
-                    dB[q * b + c] = -s;
-                }
-            }
-            if (!RED && hasE) {
-                double *dC = a.dC + sd.oC + gs * b2;
-                for (int r = 0; r < b; ++r) {
-                    double s = 0.0;
-                    for (int j = 0; j < nr; ++j)
-                        s += L.XN[r * nr + j] * L.PC[c * nr + j] + L.PN[r * nr + j] * L.XC[c * nr + j];
-                    dC[r * b + c] = -s;
-                }
-            }
-            if (hasF && i == 0) {
-                // C_{sep_k} = Psi_{first(k), sep_k}: rows of the first stage, columns of the separator
-                double *dC = a.dC + sd.oC + sep * b2;
-                for (int r = 0; r < b; ++r) {
-                    double s = 0.0;
-                    for (int j = 0; j < nr; ++j)
-                        s += L.XC[r * nr + j] * L.PS[c * nr + j] + L.PC[r * nr + j] * L.XS[c * nr + j];
-                    dC[r * b + c] = -s;
-                }
-            }
-        }
-        wave_sync();
-        if (cv)
+            for (int l = 0; l < BP; ++l) dcol[l] = (cv && l < b) ? stD[l * P + c] : (l == c ? 1.0 : 0.0);
+            const double dinv = cv ? 1.0 / stD[c * P + c] : 1.0;
             for (int j = 0; j < nr; ++j) {
-                L.XN[c * nr + j] = L.XC[c * nr + j];
-                if (ADJ) L.PN[c * nr + j] = L.PC[c * nr + j];
+                double acc = cv ? L.XC[c * nr + j] : 0.0;
+                if (hasE)
+                    for (int r = 0; r < b; ++r) acc = fma(-(cv ? stE[r * P + c] : 0.0), L.XN[r * nr + j], acc);
+                for (int q = 0; q < ng; ++q) acc = fma(-(cv ? stG[q * P + c] : 0.0), L.XG[q * nr + j], acc);
+                if (hasF)
+                    for (int r = 0; r < b; ++r) acc = fma(-(cv ? stF[r * P + c] : 0.0), L.XS[r * nr + j], acc);
+                const double xv = back_subst<BP>(dcol, acc, dinv);
+                wave_sync();
+                if (cv) {
+                    X[((long long)gs * b + c) * nr + j] = xv;
+                    L.XC[c * nr + j] = xv;
+                }
+                wave_sync();
             }
-        wave_sync();
+            if (ADJ && cv) {
+                // dD_gs = -sym(lambda x^T); dB_gs = -(lambda_g x^T + x_g lambda^T); dC_gs (stage couplings only)
+                double *dD = a.dD + sd.oD + gs * b2;
+                for (int r = 0; r < b; ++r) {
+                    double s = 0.0;
+                    for (int j = 0; j < nr; ++j)
+                        s += L.XC[r * nr + j] * L.PC[c * nr + j] + L.PC[r * nr + j] * L.XC[c * nr + j];
+                    dD[r * b + c] = -0.5 * s;
+                }
+                if (ng) {
+                    double *dB = a.dB + sd.oB + (long long)gs * ng * b;
+                    for (int q = 0; q < ng; ++q) {
+                        double s = 0.0;
+                        for (int j = 0; j < nr; ++j)
+                            s += L.XG[q * nr + j] * L.PC[c * nr + j] + L.PG[q * nr + j] * L.XC[c * nr + j];
+                        dB[q * b + c] = -s;
+                    }
+                }
+                if (!RED && hasE) {
+                    double *dC = a.dC + sd.oC + gs * b2;
+                    for (int r = 0; r < b; ++r) {
+                        double s = 0.0;
+                        for (int j = 0; j < nr; ++j)
+                            s += L.XN[r * nr + j] * L.PC[c * nr + j] + L.PN[r * nr + j] * L.XC[c * nr + j];
+                        dC[r * b + c] = -s;
+                    }
+                }
+                if (hasF && i == 0) {
+                    // C_{sep_k} = Psi_{first(k), sep_k}: rows of the first stage, columns of the separator
+                    double *dC = a.dC + sd.oC + sep * b2;
+                    for (int r = 0; r < b; ++r) {
+                        double s = 0.0;
+                        for (int j = 0; j < nr; ++j)
+                            s += L.XC[r * nr + j] * L.PS[c * nr + j] + L.PC[r * nr + j] * L.XS[c * nr + j];
+                        dC[r * b + c] = -s;
+                    }
+                }
+            }
+            wave_sync();
+            if (cv)
+                for (int j = 0; j < nr; ++j) {
+                    L.XN[c * nr + j] = L.XC[c * nr + j];
+                    if (ADJ) L.PN[c * nr + j] = L.PC[c * nr + j];
+                }
+            wave_sync();
+        }
     }
+    __syncthreads();
 }
 
 }  // namespace kkt_dev

@@ -65,10 +65,17 @@ def lib():
         L.kkt_solve.argtypes = [vp, vp, vp, vp]
         L.kkt_factor_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.kkt_solve_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.kkt_plan_class_info.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                          ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        L.kkt_plan_set_class_events.argtypes = [vp, i32, vp, vp]
+        L.kkt_workspace_error.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
+        L.kkt_plan_set_spin_limit.argtypes = [vp, i32]
         L.kkt_status_string.restype = ctypes.c_char_p
         L.kkt_status_string.argtypes = [ctypes.c_int]
         for name in ("kkt_plan_create", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
-                     "kkt_workspace_init", "kkt_factor", "kkt_solve", "kkt_factor_solve", "kkt_solve_adjoint"):
+                     "kkt_workspace_init", "kkt_factor", "kkt_solve", "kkt_factor_solve", "kkt_solve_adjoint",
+                     "kkt_plan_class_info", "kkt_plan_set_class_events", "kkt_workspace_error",
+                     "kkt_plan_set_spin_limit"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -76,7 +83,8 @@ def lib():
 
 EXPORTED = ("kkt_plan_create", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
             "kkt_plan_factor_offset", "kkt_workspace_init", "kkt_factor", "kkt_solve",
-            "kkt_factor_solve", "kkt_solve_adjoint", "kkt_status_string")
+            "kkt_factor_solve", "kkt_solve_adjoint", "kkt_status_string", "kkt_plan_class_info",
+            "kkt_plan_set_class_events", "kkt_workspace_error", "kkt_plan_set_spin_limit")
 
 
 def _check(rc, what):
@@ -221,6 +229,30 @@ class Plan:
         if ng:
             out[("g", "g")] = F[lay.off_Lg: lay.off_Lg + ng * ng].reshape(ng, ng)
         return out
+
+    def classes(self):
+        """[(padded block size, items, threads, lds bytes)] per persistent launch."""
+        out = []
+        for c in range(self.info.num_classes):
+            bp, it, nt, lds = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+            _check(lib().kkt_plan_class_info(self._h, c, ctypes.byref(bp), ctypes.byref(it), ctypes.byref(nt),
+                                             ctypes.byref(lds)), "kkt_plan_class_info")
+            out.append((bp.value, it.value, nt.value, lds.value))
+        return out
+
+    def workspace_error(self, ws, stream=None):
+        """Nonzero if a worker of the last call gave up waiting for a handover (results invalid)."""
+        f = ctypes.c_int32()
+        _check(lib().kkt_workspace_error(self._h, _ptr(ws), _stream(stream), ctypes.byref(f)), "kkt_workspace_error")
+        return int(f.value)
+
+    def set_spin_limit(self, limit):
+        _check(lib().kkt_plan_set_spin_limit(self._h, int(limit)), "kkt_plan_set_spin_limit")
+
+    def set_class_events(self, c, start, stop):
+        """start / stop: raw hipEvent_t handles (ints) or None."""
+        _check(lib().kkt_plan_set_class_events(self._h, c, ctypes.c_void_p(start), ctypes.c_void_p(stop)),
+               "kkt_plan_set_class_events")
 
     def segment_lengths(self, s):
         lay = self.layouts[s]

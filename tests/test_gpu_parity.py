@@ -48,6 +48,7 @@ def run(systems, ps, nrhs, mode="fused"):
         plan.factor(pools["D"], pools["C"], pools["B"], pools["corner"], ws, info)
         plan.solve(ws, x)
     torch.cuda.synchronize()
+    assert plan.workspace_error(ws) == 0, "a worker gave up waiting for a backward-sweep handover"
     return plan, pools, ws, x, info.cpu().numpy()
 
 
@@ -217,3 +218,25 @@ def test_adjoint_matches_oracle(p):
                 continue
             err = float(np.max(np.abs(g - r)) / max(1e-300, np.max(np.abs(r))))
             assert err < 1e-9, (name, s, err)
+
+
+def test_spin_limit_error_is_reported():
+    """A worker whose bounded wait runs out raises the workspace error flag instead of hanging."""
+    kkt = _kkt()
+    systems = gen(31, [(64, 8, 2)])
+    plan = kkt.Plan([(64, 8, 2, 16)], nrhs=1)
+    plan.set_spin_limit(1)
+    pools = kkt.pack_to_device(workloads.pack(systems))
+    ws = plan.new_workspace()
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    x = pools["r"].clone()
+    _say("gpu case: spin limit 1, N=64 b=8 ng=2 p=16")
+    plan.factor_solve(pools["D"], pools["C"], pools["B"], pools["corner"], ws, x, info)
+    torch.cuda.synchronize()
+    assert plan.workspace_error(ws) != 0
+    plan.set_spin_limit(1 << 22)
+    x = pools["r"].clone()
+    plan.factor_solve(pools["D"], pools["C"], pools["B"], pools["corner"], ws, x, info)
+    torch.cuda.synchronize()
+    assert plan.workspace_error(ws) == 0
+    check_solution(plan, x, systems)
