@@ -13,9 +13,10 @@
  * Precision: FP64 throughout.
  *
  * Memory: every data pointer is a DEVICE pointer owned by the caller.  The
- * library never allocates device memory and never synchronises the host: all
- * work is enqueued on the caller's stream, so calls can be captured in a HIP
- * graph.  Scratch lives in the caller's workspace (kkt_plan_info.workspace_bytes,
+ * library never allocates device memory.  Factor and solve calls only enqueue
+ * work on the caller's stream (no host synchronisation), so they can be
+ * captured in a HIP graph; kkt_workspace_init and kkt_workspace_error
+ * synchronise the stream.  Scratch lives in the caller's workspace (kkt_plan_info.workspace_bytes,
  * 256-byte aligned); kkt_workspace_init must be enqueued once on a workspace
  * before its first use with a plan.  Calls that share a workspace must not
  * overlap in time.
@@ -109,16 +110,37 @@ typedef struct {
 } kkt_system_layout;
 
 /* Plan a batch of num_systems systems (dims: host array), nrhs right-hand sides
- * each.  Fails with KKT_EDIMS on an unsupported shape. */
+ * each.  Fails with KKT_EDIMS on an unsupported shape.  Systems with p = 0 get
+ * their segment count from the default cost model (see kkt_cost_model). */
 int kkt_plan_create(kkt_plan **plan, int32_t num_systems, const kkt_dims *dims, int32_t nrhs);
+
+/* Cost model used to choose p for systems given with p = 0.  Per padded
+ * block-size class (8, 16, 24, 32): the time of one stage of a first segment
+ * (t_first), of a segment carrying fill rows (t_fill, segments 2..p), of one
+ * reduced-chain stage (t_red), the fixed cost of an item (t_item), and the
+ * number of items the device runs at once (workers).  Units are arbitrary but
+ * common.  Segment lengths follow Eq. 13's balance with sigma = t_fill / t_first.
+ * Starting from p = 1, the plan repeatedly adds a segment to the system with the
+ * longest estimated item while that lowers the estimated makespan
+ * max(total work / workers, longest item) of its class.  A default model
+ * follows the flop ratios of Table 1 (7/3, 19/3 and 10/3 b^3 per stage); a
+ * measured one (paper_2511_00946_amd/autotune.py) can be passed here. */
+typedef struct {
+    double t_first[4], t_fill[4], t_red[4], t_item[4];
+    double workers[4];
+} kkt_cost_model;
+
+int kkt_plan_create_tuned(kkt_plan **plan, int32_t num_systems, const kkt_dims *dims, int32_t nrhs,
+                          const kkt_cost_model *model);
 int kkt_plan_destroy(kkt_plan *plan);
 int kkt_plan_get_info(const kkt_plan *plan, kkt_plan_info *info);
 int kkt_plan_system(const kkt_plan *plan, int32_t s, kkt_system_layout *out);
 /* Byte offset of the factor region inside the workspace. */
 int64_t kkt_plan_factor_offset(const kkt_plan *plan);
 
-/* Copy the plan's tables into the workspace (enqueued on stream; the host copy
- * is pageable, so the call returns once the copy is staged).  Once per workspace. */
+/* Copy the plan's tables into the workspace and synchronise the stream.  Once
+ * per workspace, before its first use; the plan then forgets any factor it held
+ * in this workspace. */
 int kkt_workspace_init(const kkt_plan *plan, void *workspace, hipStream_t stream);
 
 /* Factorization (Algorithm 1).  info: device int32[S]. */
@@ -126,7 +148,9 @@ int kkt_factor(const kkt_plan *plan, const double *D, const double *C, const dou
                const double *corner, void *workspace, int32_t *info, hipStream_t stream);
 
 /* Forward and backward substitution (Algorithms 2, 3) with a factor already in
- * the workspace; rhs (device, rhs pool layout) is overwritten by x. */
+ * the workspace; rhs (device, rhs pool layout) is overwritten by x.  Returns
+ * KKT_ENOTFACTORED if this plan has not factored into the workspace since its
+ * kkt_workspace_init (the same holds for kkt_solve_adjoint). */
 int kkt_solve(const kkt_plan *plan, void *workspace, double *rhs, hipStream_t stream);
 
 /* Factorization fused with the forward substitution, then the backward
@@ -155,9 +179,10 @@ int kkt_workspace_error(const kkt_plan *plan, const void *workspace, hipStream_t
 int kkt_plan_set_spin_limit(kkt_plan *plan, int32_t limit);
 
 /* Block-size class c of the plan (0 <= c < num_classes): padded block size,
- * number of work items, threads per workgroup and LDS bytes of its launch. */
+ * number of work items, threads per workgroup, LDS bytes of its launch and the
+ * number of resident workgroups launched (0 before the first call). */
 int kkt_plan_class_info(const kkt_plan *plan, int32_t c, int32_t *block_pad, int32_t *num_items,
-                        int32_t *threads, int64_t *lds_bytes);
+                        int32_t *threads, int64_t *lds_bytes, int32_t *grid);
 
 /* Record start / stop on the caller's stream around the persistent launch of
  * class c in every later call (NULL, NULL turns it off).  For measurement: the

@@ -1,0 +1,99 @@
+"""Measured cost model for choosing the segment count p (the plan's autotuner).
+
+For every padded block-size class the device is timed on small synthetic
+batches (the library's own kernels, one persistent launch per class):
+  workers   resident workgroups of the class's launch (read back from the plan)
+  t_first   per-stage time of a first segment under full load
+            (a batch of `workers` systems, p = 1, timed at horizons 8 and 24)
+  t_fill    per-stage time of a segment carrying fill rows under full load
+            (systems with p = 2 and a one-stage first segment)
+  t_red     per-stage time of the reduced chain (a single system at large p,
+            minus its segments), floored at t_first
+  t_item    fixed cost of an item (intercept of the p = 1 fit)
+The result is cached as JSON per GPU architecture.  The chooser itself
+(makespan = max(total work / workers, longest item)) runs in the C library.
+"""
+import json
+import os
+import time
+
+import numpy as np
+
+from . import kkt, workloads
+
+CLASSES = (8, 16, 24, 32)
+
+
+def _cache_path(arch):
+    base = os.environ.get("KKT_CACHE_DIR", os.path.join(os.path.expanduser("~"), ".cache", "kkt_mi355x"))
+    return os.path.join(base, "cost_model_%s.json" % arch)
+
+
+def _time_batch(dims, reps=3):
+    import torch
+    rng = np.random.default_rng(7)
+    drawn = {}
+    for d in dims:                      # one system per distinct shape, repeated
+        if d[:3] not in drawn:
+            drawn[d[:3]] = workloads.draw_system(rng, d[0], d[1], d[2], alpha=d[1])
+    systems = [drawn[d[:3]] for d in dims]
+    plan = kkt.Plan(dims, nrhs=1)
+    d = kkt.pack_to_device(workloads.pack(systems))
+    ws = plan.new_workspace()
+    info = torch.zeros(len(dims), dtype=torch.int32, device="cuda")
+    x = torch.empty_like(d["r"])
+
+    def run():
+        x.copy_(d["r"])
+        plan.factor_solve(d["D"], d["C"], d["B"], d["corner"], ws, x, info)
+
+    run()
+    torch.cuda.synchronize()
+    a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        run()
+    b2.record()
+    torch.cuda.synchronize()
+    grid = max(g for *_, g in plan.classes(with_grid=True))
+    return a.elapsed_time(b2) / reps, grid
+
+
+def calibrate(verbose=False):
+    model = {k: [0.0] * 4 for k in ("t_first", "t_fill", "t_red", "t_item", "workers")}
+    for c, bp in enumerate(CLASSES):
+        b = bp
+        _, W = _time_batch([(1, b, 2, 1)] * 8192, reps=1)          # more items than slots: the full grid
+        W = max(1, W)
+        t1, _ = _time_batch([(8, b, 2, 1)] * W)
+        t2, _ = _time_batch([(24, b, 2, 1)] * W)
+        t_first = max((t2 - t1) / 16.0, 1e-6)
+        t_item = max(t1 - 8 * t_first, 0.0)
+        tf, _ = _time_batch([(18, b, 2, 2, 1)] * W)                 # N1 = 1, Nk = 16 with fill rows
+        t_fill = max((tf - t_item) / 16.0, t_first)
+        ts, _ = _time_batch([(65, b, 2, 32)])                       # 32 short segments, 31 reduced stages
+        t_red = max((ts - t_item - 2 * t_fill) / 31.0, t_first)
+        model["t_first"][c], model["t_fill"][c], model["t_red"][c] = t_first, t_fill, t_red
+        model["t_item"][c], model["workers"][c] = t_item, float(W)
+        if verbose:
+            print("class %2d: workers %d t_first %.4f t_fill %.4f t_red %.4f t_item %.4f (ms)"
+                  % (bp, W, t_first, t_fill, t_red, t_item), flush=True)
+    return model
+
+
+def cost_model(refresh=False, verbose=False):
+    """The cached measured model for this GPU, calibrating it if needed."""
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    path = _cache_path(arch)
+    if not refresh and os.path.exists(path):
+        with open(path) as fh:
+            return json.load(fh)
+    t0 = time.time()
+    m = calibrate(verbose=verbose)
+    m["arch"] = arch
+    m["seconds"] = round(time.time() - t0, 2)
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as fh:
+        json.dump(m, fh)
+    return m

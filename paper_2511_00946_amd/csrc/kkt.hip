@@ -21,7 +21,9 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <unordered_set>
 #include <vector>
 
 #include "kkt.h"
@@ -399,6 +401,105 @@ bool partition_eq13(int N, int p, int *N1, int *Nk)
     return true;
 }
 
+// Segment lengths balancing a first segment at t1 per stage against the others at
+// tk per stage (Eq. 13 with sigma = tk / t1); false if N < 2p - 1.
+bool partition_sigma(int N, int p, double t1, double tk, int *N1, int *Nk)
+{
+    if (p == 1) { *N1 = N; *Nk = 0; return true; }
+    const double sigma = tk / t1;
+    const double nbar = (double)(N - p + 1) / ((double)(p - 1) + sigma);
+    const long long cand[2] = {(long long)std::floor(nbar), (long long)std::ceil(nbar)};
+    bool have = false;
+    double best = 0;
+    for (int t = 0; t < 2; ++t) {
+        const long long nk = cand[t];
+        if (t == 1 && cand[1] == cand[0]) break;
+        const long long n1 = N - (p - 1) - (p - 1) * nk;
+        if (nk < 1 || n1 < 1) continue;
+        const double cost = std::max(n1 * t1, nk * tk);
+        if (!have || cost < best) { have = true; best = cost; *N1 = (int)n1; *Nk = (int)nk; }
+    }
+    return have;
+}
+
+struct ItemEst {
+    double longest, total;
+};
+
+// Estimated longest item and total work of one system split into p segments.
+ItemEst estimate(int N, int p, int cls, const kkt_cost_model &m)
+{
+    int N1 = N, Nk = 0;
+    if (p > 1 && !partition_sigma(N, p, m.t_first[cls], m.t_fill[cls], &N1, &Nk)) return {1e300, 1e300};
+    const double seg1 = m.t_item[cls] + N1 * m.t_first[cls];
+    const double segk = p > 1 ? m.t_item[cls] + Nk * m.t_fill[cls] : 0.0;
+    const double red = (p - 1) * m.t_red[cls];
+    return {std::max(seg1, segk) + red, seg1 + (p - 1) * segk + red};
+}
+
+// Choose p for the systems of one class with dims[s].p == 0: start from p = 1 and
+// keep splitting the system that bounds the makespan max(total / workers, longest)
+// while that lowers it.
+void choose_segments(std::vector<kkt_dims> &dims, const std::vector<int> &cls_of, int cls, const kkt_cost_model &m)
+{
+    std::vector<int> tun;
+    double total = 0.0, fixed_longest = 0.0;
+    for (size_t s = 0; s < dims.size(); ++s) {
+        if (cls_of[s] != cls) continue;
+        if (dims[s].p == 0) {
+            dims[s].p = 1;
+            tun.push_back((int)s);
+        } else {
+            const ItemEst e = estimate(dims[s].N, dims[s].p, cls, m);
+            total += e.total;
+            fixed_longest = std::max(fixed_longest, e.longest);
+        }
+    }
+    if (tun.empty()) return;
+    std::vector<ItemEst> est(tun.size());
+    for (size_t i = 0; i < tun.size(); ++i) {
+        est[i] = estimate(dims[tun[i]].N, 1, cls, m);
+        total += est[i].total;
+    }
+    const double W = std::max(1.0, m.workers[cls]);
+    long long max_iter = 0;                        // every step raises one p, p <= (N + 1) / 2
+    for (int s : tun) max_iter += (dims[s].N + 1) / 2;
+    for (long long iter = 0; iter < max_iter; ++iter) {
+        size_t worst = 0;
+        for (size_t i = 1; i < tun.size(); ++i)
+            if (est[i].longest > est[worst].longest) worst = i;
+        const double longest = std::max(fixed_longest, est[worst].longest);
+        const double makespan = std::max(total / W, longest);
+        if (est[worst].longest < total / W || est[worst].longest < fixed_longest) break;
+        kkt_dims &d = dims[tun[worst]];
+        const int pn = d.p + 1;
+        if (d.N < 2 * pn - 1) break;
+        const ItemEst en = estimate(d.N, pn, cls, m);
+        const double total_n = total - est[worst].total + en.total;
+        double longest_n = std::max(fixed_longest, en.longest);
+        for (size_t i = 0; i < tun.size(); ++i)
+            if (i != worst) longest_n = std::max(longest_n, est[i].longest);
+        if (std::max(total_n / W, longest_n) >= makespan) break;
+        d.p = pn;
+        total = total_n;
+        est[worst] = en;
+    }
+}
+
+kkt_cost_model default_cost_model()
+{
+    kkt_cost_model m;
+    for (int c = 0; c < 4; ++c) {
+        const double b3 = (double)CLS_BP[c] * CLS_BP[c] * CLS_BP[c];
+        m.t_first[c] = 7.0 / 3.0 * b3;
+        m.t_fill[c] = 19.0 / 3.0 * b3;
+        m.t_red[c] = 10.0 / 3.0 * b3;
+        m.t_item[c] = 0.0;
+        m.workers[c] = 512.0;
+    }
+    return m;
+}
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
@@ -419,7 +520,17 @@ struct kkt_plan {
     long long nF = 0;
     kkt_plan_info info{};
     int spin_limit = 1 << 22;
-    mutable const void *factored_ws = nullptr;
+    // Workspaces this plan has factored into (a host-side guard against solving
+    // with no factor; kkt_workspace_init forgets a workspace again).
+    mutable std::mutex factored_mu;
+    mutable std::unordered_set<const void *> factored;
+    void mark_factored(const void *ws) const { std::lock_guard<std::mutex> g(factored_mu); factored.insert(ws); }
+    void forget(const void *ws) const { std::lock_guard<std::mutex> g(factored_mu); factored.erase(ws); }
+    bool is_factored(const void *ws) const
+    {
+        std::lock_guard<std::mutex> g(factored_mu);
+        return factored.count(ws) != 0;
+    }
     // launch configuration per (class, mode), filled on first use so that later
     // calls (and graph capture) make no device queries
     mutable int grid[4][4] = {{0}};
@@ -520,10 +631,26 @@ extern "C" {
 
 int kkt_plan_create(kkt_plan **out, int32_t S, const kkt_dims *dims, int32_t nrhs)
 {
+    return kkt_plan_create_tuned(out, S, dims, nrhs, nullptr);
+}
+
+int kkt_plan_create_tuned(kkt_plan **out, int32_t S, const kkt_dims *dims_in, int32_t nrhs,
+                          const kkt_cost_model *model)
+{
     if (!out) return KKT_EPOINTER;
     *out = nullptr;
-    if (S < 1 || !dims) return S < 1 ? KKT_EDIMS : KKT_EPOINTER;
+    if (S < 1 || !dims_in) return S < 1 ? KKT_EDIMS : KKT_EPOINTER;
     if (nrhs < 1 || nrhs > KKT_MAX_NRHS) return KKT_EDIMS;
+    std::vector<kkt_dims> dims(dims_in, dims_in + S);
+    {
+        std::vector<int> cls0(S);
+        for (int s = 0; s < S; ++s) {
+            if (!valid_dims(dims[s])) return KKT_EDIMS;
+            cls0[s] = class_of(dims[s].b);
+        }
+        const kkt_cost_model m = model ? *model : default_cost_model();
+        for (int c = 0; c < NCLS; ++c) choose_segments(dims, cls0, c, m);
+    }
     kkt_plan *P = new (std::nothrow) kkt_plan;
     if (!P) return KKT_EINTERNAL;
     P->S = S;
@@ -537,7 +664,7 @@ int kkt_plan_create(kkt_plan **out, int32_t S, const kkt_dims *dims, int32_t nrh
     for (int s = 0; s < S; ++s) {
         kkt_dims d = dims[s];
         if (!valid_dims(d)) { delete P; return KKT_EDIMS; }
-        int p = d.p == 0 ? 1 : d.p;
+        const int p = d.p;
         int N1 = 0, Nk = 0;
         if (p == 1) {
             N1 = d.N;
@@ -692,7 +819,7 @@ int kkt_workspace_init(const kkt_plan *plan, void *workspace, hipStream_t stream
     if (hipMemcpyAsync(ws + plan->o_tag, tag, sizeof(tag), hipMemcpyHostToDevice, stream) != hipSuccess)
         return KKT_ELAUNCH;
     if (hipStreamSynchronize(stream) != hipSuccess) return KKT_ELAUNCH;
-    plan->factored_ws = nullptr;
+    plan->forget(workspace);
     return KKT_OK;
 }
 
@@ -707,7 +834,7 @@ int kkt_factor(const kkt_plan *plan, const double *D, const double *C, const dou
     Args a = base_args(plan, workspace);
     a.D = D; a.C = C; a.B = B; a.corner = corner; a.info = info;
     const int rc = launch_mode(plan, M_FACTOR, a, stream, info);
-    if (rc == KKT_OK) plan->factored_ws = workspace;
+    if (rc == KKT_OK) plan->mark_factored(workspace);
     return rc;
 }
 
@@ -723,7 +850,7 @@ int kkt_factor_solve(const kkt_plan *plan, const double *D, const double *C, con
     Args a = base_args(plan, workspace);
     a.D = D; a.C = C; a.B = B; a.corner = corner; a.info = info; a.rhs = rhs;
     const int rc = launch_mode(plan, M_FACTOR_SOLVE, a, stream, info);
-    if (rc == KKT_OK) plan->factored_ws = workspace;
+    if (rc == KKT_OK) plan->mark_factored(workspace);
     return rc;
 }
 
@@ -731,7 +858,7 @@ int kkt_solve(const kkt_plan *plan, void *workspace, double *rhs, hipStream_t st
 {
     if (!plan || !workspace || !rhs) return KKT_EPOINTER;
     if (((uintptr_t)workspace & 255) || !aligned8(rhs)) return KKT_EPOINTER;
-    if (plan->factored_ws != workspace) return KKT_ENOTFACTORED;
+    if (!plan->is_factored(workspace)) return KKT_ENOTFACTORED;
     Args a = base_args(plan, workspace);
     a.rhs = rhs;
     return launch_mode(plan, M_SOLVE, a, stream, nullptr);
@@ -746,7 +873,7 @@ int kkt_solve_adjoint(const kkt_plan *plan, void *workspace, const double *x, do
     if (((uintptr_t)workspace & 255) || !aligned8(x) || !aligned8(gx) || !aligned8(dD) || !aligned8(dC) ||
         !aligned8(dB) || !aligned8(dcorner))
         return KKT_EPOINTER;
-    if (plan->factored_ws != workspace) return KKT_ENOTFACTORED;
+    if (!plan->is_factored(workspace)) return KKT_ENOTFACTORED;
     Args a = base_args(plan, workspace);
     a.rhs = gx; a.xp = x; a.dD = dD; a.dC = dC; a.dB = dB; a.dcorner = dcorner;
     return launch_mode(plan, M_ADJOINT, a, stream, nullptr);
@@ -776,8 +903,13 @@ int kkt_plan_set_spin_limit(kkt_plan *plan, int32_t limit)
 }
 
 int kkt_plan_class_info(const kkt_plan *plan, int32_t c, int32_t *block_pad, int32_t *num_items,
-                        int32_t *threads, int64_t *lds_bytes)
+                        int32_t *threads, int64_t *lds_bytes, int32_t *grid)
 {
+    if (grid && plan && c >= 0 && c < (int)plan->cls.size()) {
+        int g = 0;
+        for (int m = 0; m < 4; ++m) g = std::max(g, plan->grid[c][m]);
+        *grid = g;
+    }
     if (!plan) return KKT_EPOINTER;
     if (c < 0 || c >= (int)plan->cls.size()) return KKT_EDIMS;
     const kkt_plan::Cls &C = plan->cls[c];

@@ -39,6 +39,22 @@ class SystemLayout(ctypes.Structure):
                 ("off_Lg", ctypes.c_int64), ("off_fill", ctypes.c_int64), ("off_H", ctypes.c_int64)]
 
 
+class CostModel(ctypes.Structure):
+    """Per padded block-size class (8, 16, 24, 32): stage times of first segments,
+    fill-carrying segments and reduced stages, item overhead, concurrent workers."""
+    _fields_ = [("t_first", ctypes.c_double * 4), ("t_fill", ctypes.c_double * 4),
+                ("t_red", ctypes.c_double * 4), ("t_item", ctypes.c_double * 4),
+                ("workers", ctypes.c_double * 4)]
+
+    @classmethod
+    def from_dict(cls, d):
+        m = cls()
+        for k in ("t_first", "t_fill", "t_red", "t_item", "workers"):
+            for i, v in enumerate(d[k]):
+                getattr(m, k)[i] = float(v)
+        return m
+
+
 class KKTError(RuntimeError):
     pass
 
@@ -55,6 +71,8 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.kkt_plan_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(Dims), i32]
+        L.kkt_plan_create_tuned.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(Dims), i32,
+                                            ctypes.POINTER(CostModel)]
         L.kkt_plan_destroy.argtypes = [vp]
         L.kkt_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         L.kkt_plan_system.argtypes = [vp, i32, ctypes.POINTER(SystemLayout)]
@@ -66,13 +84,13 @@ def lib():
         L.kkt_factor_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.kkt_solve_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.kkt_plan_class_info.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                          ctypes.POINTER(i32), ctypes.POINTER(i64)]
+                                          ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32)]
         L.kkt_plan_set_class_events.argtypes = [vp, i32, vp, vp]
         L.kkt_workspace_error.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
         L.kkt_plan_set_spin_limit.argtypes = [vp, i32]
         L.kkt_status_string.restype = ctypes.c_char_p
         L.kkt_status_string.argtypes = [ctypes.c_int]
-        for name in ("kkt_plan_create", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
+        for name in ("kkt_plan_create", "kkt_plan_create_tuned", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
                      "kkt_workspace_init", "kkt_factor", "kkt_solve", "kkt_factor_solve", "kkt_solve_adjoint",
                      "kkt_plan_class_info", "kkt_plan_set_class_events", "kkt_workspace_error",
                      "kkt_plan_set_spin_limit"):
@@ -81,7 +99,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ("kkt_plan_create", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
+EXPORTED = ("kkt_plan_create", "kkt_plan_create_tuned", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
             "kkt_plan_factor_offset", "kkt_workspace_init", "kkt_factor", "kkt_solve",
             "kkt_factor_solve", "kkt_solve_adjoint", "kkt_status_string", "kkt_plan_class_info",
             "kkt_plan_set_class_events", "kkt_workspace_error", "kkt_plan_set_spin_limit")
@@ -110,9 +128,12 @@ def _stream(stream):
 
 
 class Plan:
-    """A plan for a batch of systems: ``dims`` is a list of (N, b, ng[, p[, N1]])."""
+    """A plan for a batch of systems: ``dims`` is a list of (N, b, ng[, p[, N1]]).
 
-    def __init__(self, dims, nrhs=1):
+    p = 0 lets the plan choose the segment count from ``cost_model`` (a
+    ``CostModel`` or a dict of its fields; None = the default model)."""
+
+    def __init__(self, dims, nrhs=1, cost_model=None):
         dims = [tuple(d) for d in dims]
         arr = (Dims * len(dims))()
         for i, d in enumerate(dims):
@@ -121,7 +142,12 @@ class Plan:
             N1 = int(d[4]) if len(d) > 4 else 0
             arr[i] = Dims(N, b, ng, p, N1)
         h = ctypes.c_void_p()
-        _check(lib().kkt_plan_create(ctypes.byref(h), len(dims), arr, int(nrhs)), "kkt_plan_create")
+        if cost_model is None:
+            _check(lib().kkt_plan_create(ctypes.byref(h), len(dims), arr, int(nrhs)), "kkt_plan_create")
+        else:
+            cm = cost_model if isinstance(cost_model, CostModel) else CostModel.from_dict(cost_model)
+            _check(lib().kkt_plan_create_tuned(ctypes.byref(h), len(dims), arr, int(nrhs), ctypes.byref(cm)),
+                   "kkt_plan_create_tuned")
         self._h = h
         self.nrhs = int(nrhs)
         self.S = len(dims)
@@ -230,14 +256,16 @@ class Plan:
             out[("g", "g")] = F[lay.off_Lg: lay.off_Lg + ng * ng].reshape(ng, ng)
         return out
 
-    def classes(self):
-        """[(padded block size, items, threads, lds bytes)] per persistent launch."""
+    def classes(self, with_grid=False):
+        """[(padded block size, items, threads, lds bytes[, launched workgroups])] per persistent launch."""
         out = []
         for c in range(self.info.num_classes):
-            bp, it, nt, lds = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+            bp, it, nt, lds, gr = (ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(),
+                                   ctypes.c_int32())
             _check(lib().kkt_plan_class_info(self._h, c, ctypes.byref(bp), ctypes.byref(it), ctypes.byref(nt),
-                                             ctypes.byref(lds)), "kkt_plan_class_info")
-            out.append((bp.value, it.value, nt.value, lds.value))
+                                             ctypes.byref(lds), ctypes.byref(gr)), "kkt_plan_class_info")
+            t = (bp.value, it.value, nt.value, lds.value)
+            out.append(t + (gr.value,) if with_grid else t)
         return out
 
     def workspace_error(self, ws, stream=None):
@@ -253,6 +281,10 @@ class Plan:
         """start / stop: raw hipEvent_t handles (ints) or None."""
         _check(lib().kkt_plan_set_class_events(self._h, c, ctypes.c_void_p(start), ctypes.c_void_p(stop)),
                "kkt_plan_set_class_events")
+
+    def segments(self):
+        """Segment count p chosen for every system."""
+        return [lay.p for lay in self.layouts]
 
     def segment_lengths(self, s):
         lay = self.layouts[s]

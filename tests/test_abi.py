@@ -84,3 +84,78 @@ def test_factor_words_count_fill():
     fill = (p - 1) * (nk - 1) * b * b + (p - 2) * b * b
     assert plan.info.input_words == k_words
     assert plan.info.factor_words == k_words + fill
+
+
+# ---- segment-count choice from a cost model (host logic of the plan)
+
+def _model(W=512.0):
+    b3 = [float(bp) ** 3 for bp in (8, 16, 24, 32)]
+    return {"t_first": [7 / 3 * x for x in b3], "t_fill": [19 / 3 * x for x in b3],
+            "t_red": [10 / 3 * x for x in b3], "t_item": [0.0] * 4, "workers": [W] * 4}
+
+
+def _est(N, p, c, m):
+    """Longest item and total work of one system under the model, written out here."""
+    t1, tk, tr = m["t_first"][c], m["t_fill"][c], m["t_red"][c]
+    if p == 1:
+        return m["t_item"][c] + N * t1, m["t_item"][c] + N * t1
+    best = None
+    nbar = (N - p + 1) / ((p - 1) + tk / t1)
+    for nk in {int(np.floor(nbar)), int(np.ceil(nbar))}:
+        n1 = N - (p - 1) * (nk + 1)
+        if nk >= 1 and n1 >= 1:
+            cost = max(n1 * t1, nk * tk)
+            if best is None or cost < best[0]:
+                best = (cost, n1, nk)
+    assert best is not None
+    _, n1, nk = best
+    s1, sk = m["t_item"][c] + n1 * t1, m["t_item"][c] + nk * tk
+    return max(s1, sk) + (p - 1) * tr, s1 + (p - 1) * sk + (p - 1) * tr
+
+
+@pytest.mark.parametrize("N,b,ng", [(2048, 6, 8), (128, 32, 0), (256, 16, 4), (40, 24, 2)])
+def test_cost_model_single_system_near_optimal(N, b, ng):
+    kkt = _kkt()
+    m = _model()
+    plan = kkt.Plan([(N, b, ng, 0)], cost_model=m)
+    (p,) = plan.segments()
+    c = [8, 16, 24, 32].index(next(bp for bp in (8, 16, 24, 32) if b <= bp))
+    span = {q: max(_est(N, q, c, m)[1] / m["workers"][c], _est(N, q, c, m)[0])
+            for q in range(1, (N + 1) // 2 + 1)}
+    assert p > 1
+    # the greedy stops at a local minimum of the makespan, within a few percent of the global one
+    assert span[p] <= span.get(p + 1, np.inf) and span[p] <= span[p - 1]
+    assert span[p] <= 1.05 * min(span.values())
+    lay = plan.layouts[0]
+    t = _est(N, p, c, m)
+    assert lay.N1 + (p - 1) * (lay.Nk + 1) == N
+    assert max(lay.N1 * m["t_first"][c], lay.Nk * m["t_fill"][c]) == pytest.approx(
+        min(max(n1 * m["t_first"][c], (N - n1 - (p - 1)) / (p - 1) * m["t_fill"][c])
+            for n1 in range(1, N) if (N - n1 - (p - 1)) % (p - 1) == 0 and N - n1 - (p - 1) >= p - 1))
+    assert t[0] > 0
+
+
+def test_cost_model_saturated_batch_keeps_one_segment():
+    """With far more systems than workers, splitting only adds work: every p stays 1."""
+    kkt = _kkt()
+    dims = [(64, 16, 2, 0)] * 2000
+    plan = kkt.Plan(dims, cost_model=_model(W=64.0))
+    assert set(plan.segments()) == {1}
+
+
+def test_cost_model_splits_only_the_long_system():
+    kkt = _kkt()
+    dims = [(16, 8, 2, 0)] * 31 + [(1024, 8, 2, 0)]
+    plan = kkt.Plan(dims, cost_model=_model(W=512.0))
+    ps = plan.segments()
+    assert ps[:31] == [1] * 31 and ps[31] > 8
+
+
+def test_cost_model_keeps_fixed_segment_counts():
+    kkt = _kkt()
+    dims = [(300, 8, 2, 3), (300, 8, 2, 0), (50, 32, 0, 1)]
+    plan = kkt.Plan(dims, cost_model=_model())
+    ps = plan.segments()
+    assert ps[0] == 3 and ps[2] == 1 and ps[1] > 1
+    d = kkt.Plan(dims)                                   # default model, same choice
+    assert d.segments() == ps

@@ -240,3 +240,29 @@ def test_spin_limit_error_is_reported():
     torch.cuda.synchronize()
     assert plan.workspace_error(ws) == 0
     check_solution(plan, x, systems)
+
+
+def test_workspaces_keep_their_own_factors():
+    """One plan, two workspaces factored with different matrices: each later solve
+    uses its own workspace's factor; a fresh workspace is refused."""
+    kkt = _kkt()
+    dims = [(20, 8, 2), (15, 16, 4)]
+    sa, sb = gen(51, dims), gen(52, dims)
+    plan = kkt.Plan([d + (2,) for d in dims], nrhs=1)
+    _say("gpu case: two workspaces dims=%s p=2" % dims)
+    pa, pb = kkt.pack_to_device(workloads.pack(sa)), kkt.pack_to_device(workloads.pack(sb))
+    wa, wb = plan.new_workspace(), plan.new_workspace()
+    info = torch.zeros(2, dtype=torch.int32, device="cuda")
+    plan.factor(pa["D"], pa["C"], pa["B"], pa["corner"], wa, info)
+    plan.factor(pb["D"], pb["C"], pb["B"], pb["corner"], wb, info)
+    xa, xb = pa["r"].clone(), pb["r"].clone()
+    plan.solve(wa, xa)
+    plan.solve(wb, xb)
+    torch.cuda.synchronize()
+    check_solution(plan, xa, sa)
+    check_solution(plan, xb, sb)
+    with pytest.raises(kkt.KKTError):
+        plan.solve(plan.new_workspace(), pa["r"].clone())
+    plan.init_workspace(wa)
+    with pytest.raises(kkt.KKTError):
+        plan.solve(wa, pa["r"].clone())
