@@ -27,6 +27,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 1 << 30
+SRC_FILES = ("paper_2511_00946_amd/csrc/kkt.hip", "paper_2511_00946_amd/csrc/kkt_sweeps.h",
+             "paper_2511_00946_amd/csrc/kkt_device.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ragged4096.json")
 
 
 def log(*a):
@@ -77,11 +81,118 @@ def alg_bytes(plan, systems):
     return np.asarray(out)
 
 
+def source_digest():
+    """sha256 over the kernel sources: counters taken from other sources do not apply."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in SRC_FILES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(bp, p, S):
+    """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE /
+    WRITE_SIZE passes (scaled by a plain copy's reading), or None when those were
+    taken on other kernel sources or another workload."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != source_digest() or t.get("systems") != S or t.get("p") != p:
+        return None
+    k = t.get("kernels", {}).get(str(bp))
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
 def class_of(b):
     for i, bp in enumerate((8, 16, 24, 32)):
         if b <= bp:
             return bp
     raise ValueError(b)
+
+
+def fd_check(torch, kkt, workloads, dsys, dplan, dev, grads, systems=(0, 511, 1023), per_tensor=4, h=1e-6):
+    """Central differences (step h) of L = sum(w * x) against the adjoint gradients on
+    sampled entries of D, C, B and r; error relative to the largest gradient entry of
+    that tensor in that system."""
+    rng = np.random.default_rng(3)
+    worst = 0.0
+    for s in systems:
+        sy = dsys[s]
+        lay = dplan.layouts[s]
+        plan = kkt.Plan([(sy.N, sy.b, sy.ng, lay.p)], nrhs=1)
+        ws = plan.new_workspace(dev)
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+        base = {k: v.copy() for k, v in workloads.pack([sy]).items()}
+        w = base["w"]
+        offs = {"D": lay.off_D, "C": lay.off_C, "B": lay.off_B, "r": lay.off_rhs}
+        for key in ("D", "C", "B", "r"):
+            n = base[key].size
+            if n == 0:
+                continue
+            g_sys = grads[key][offs[key]:offs[key] + n]
+            scale = float(np.max(np.abs(g_sys)))
+            for idx in rng.choice(n, size=per_tensor, replace=False):
+                vals = []
+                for sign in (1.0, -1.0):
+                    pert = {k: v.copy() for k, v in base.items()}
+                    pert[key].reshape(-1)[idx] += sign * h
+                    d = kkt.pack_to_device(pert, dev)
+                    x = d["r"].clone()
+                    plan.factor_solve(d["D"], d["C"], d["B"], d["corner"], ws, x, info)
+                    vals.append(float(np.sum(x.cpu().numpy() * w)))
+                fd = (vals[0] - vals[1]) / (2 * h)
+                worst = max(worst, abs(fd - float(g_sys[idx])) / scale)
+    return worst
+
+
+SINGLE_P = {"small": (1, 2, 4, 8), "race": (1, 2, 4, 8, 16, 32, 64, 128)}
+
+
+def single_systems(torch, kkt, workloads, okkt, dev, reps=50):
+    """Latency of one factor + solve call on the single-system workloads, per
+    segment count p and with the p the default cost model picks; speedup vs p = 1."""
+    out = {}
+    for name, plist in SINGLE_P.items():
+        sy = workloads.single(name)
+        nrhs = sy.r.shape[1]
+        pools = kkt.pack_to_device(workloads.pack([sy]), dev)
+        auto = kkt.Plan([(sy.N, sy.b, sy.ng, 0)], nrhs=nrhs).segments()[0]
+        res = {}
+        for p in sorted(set(plist) | {auto}):
+            plan = kkt.Plan([(sy.N, sy.b, sy.ng, p)], nrhs=nrhs)
+            ws = plan.new_workspace(dev)
+            info = torch.zeros(1, dtype=torch.int32, device=dev)
+            x = torch.empty_like(pools["r"])
+
+            def call():
+                x.copy_(pools["r"])
+                plan.factor_solve(pools["D"], pools["C"], pools["B"], pools["corner"], ws, x, info)
+
+            for _ in range(5):
+                call()
+            torch.cuda.synchronize()
+            a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                call()
+            b2.record()
+            torch.cuda.synchronize()
+            us = a.elapsed_time(b2) * 1e3 / reps
+            xs = x.cpu().numpy().reshape(sy.n, nrhs)
+            rr = okkt.rel_residual(sy.D, sy.C, sy.B, sy.corner, xs, sy.r)
+            assert plan.workspace_error(ws) == 0 and int(info.item()) == 0 and rr <= 1e-10, (name, p, rr)
+            res[p] = us
+        base = res[1]
+        out[name] = {"shape": "N=%d b=%d ng=%d nrhs=%d" % (sy.N, sy.b, sy.ng, nrhs),
+                     "us_per_factor_solve": {str(p): round(v, 2) for p, v in res.items()},
+                     "speedup_vs_p1": {str(p): round(base / v, 3) for p, v in res.items()},
+                     "cost_model_p": auto}
+        log("single %s: %s" % (name, {p: round(v, 1) for p, v in res.items()}))
+    out["chain"] = "not run: block size 42 is above the supported maximum of 32"
+    return out
 
 
 def main():
@@ -94,6 +205,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--p", type=int, default=1, help="segments per system (1 = sequential, 0 = cost model)")
     ap.add_argument("--skip-diff", action="store_true")
+    ap.add_argument("--skip-single", action="store_true", help="skip the single-system latency section")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay measurement")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus)
@@ -106,6 +221,16 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     ev = HipEvents()
+
+    if args.copy_calibration:
+        n = COPY_BYTES // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "launches": 3}))
+        return
 
     # ------------------------------------------------------------ ragged batch workload
     t0 = time.time()
@@ -157,6 +282,8 @@ def main():
     # graph replay of the same step
     graph_ms = None
     try:
+        if args.no_graph:
+            raise RuntimeError("skipped (--no-graph)")
         g = torch.cuda.CUDAGraph()
         s2 = torch.cuda.Stream()
         s2.wait_stream(torch.cuda.current_stream())
@@ -211,7 +338,8 @@ def main():
     dom_bytes = float(sum(bytes_sys[s] for s, sy in enumerate(systems) if class_of(sy.b) == dom_bp))
     achieved = dom_bytes / (cls_ms[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": measured_traffic(dom_bp, args.p, S),
                 "kernel": "kkt_persistent<%d, factor_solve>" % dom_bp,
                 "kernel_ms": round(float(cls_ms[dom]), 4), "alg_bytes": dom_bytes}
 
@@ -230,17 +358,19 @@ def main():
         for pl, pp, w1, i1, x1 in plain:
             x1.copy_(pp["r"])
             pl.factor_solve(pp["D"], pp["C"], pp["B"], pp["corner"], w1, x1, i1)
-    plain_pass()
-    torch.cuda.synchronize()
-    a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    plain_pass()
-    b2.record()
-    torch.cuda.synchronize()
-    plain_ms = a.elapsed_time(b2)
-    plain_sps = len(plain) / (plain_ms * 1e-3)
+    plain_sps = None
+    if plain:
+        plain_pass()
+        torch.cuda.synchronize()
+        a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        plain_pass()
+        b2.record()
+        torch.cuda.synchronize()
+        plain_ms = a.elapsed_time(b2)
+        plain_sps = len(plain) / (plain_ms * 1e-3)
+        log("plain path: %d systems in %.2f ms -> %.0f systems/s" % (len(samp), plain_ms, plain_sps))
     del plain
-    log("plain path: %d systems in %.2f ms -> %.0f systems/s" % (len(samp), plain_ms, plain_sps))
 
     # oracle on the host (bounded sample)
     csamp = np.random.default_rng(2).choice(S, size=min(args.cpu_sample, S), replace=False)
@@ -249,11 +379,13 @@ def main():
         sy = systems[s]
         okkt.solve(sy.D, sy.C, sy.B, sy.corner, sy.r)
     cpu_s = time.perf_counter() - t1
-    cpu_sps = len(csamp) / cpu_s
-    log("oracle: %d systems in %.1fs -> %.1f systems/s" % (len(csamp), cpu_s, cpu_sps))
+    cpu_sps = len(csamp) / cpu_s if len(csamp) else None
+    log("oracle: %d systems in %.1fs -> %s systems/s" % (len(csamp), cpu_s, cpu_sps))
 
     del dp, ws, x, info
     torch.cuda.empty_cache()
+
+    single = None if args.skip_single else single_systems(torch, kkt, workloads, okkt, dev)
 
     # differentiation workload: forward factor + solve, adjoint backward
     diff = None
@@ -297,8 +429,12 @@ def main():
             gerr = max(gerr, float(np.max(np.abs(got - ref[1])) / np.max(np.abs(ref[1]))))
             gl = lam_h[lay.off_rhs:lay.off_rhs + sy.n].reshape(sy.n, 1)
             gerr = max(gerr, float(np.max(np.abs(gl - ref[0])) / np.max(np.abs(ref[0]))))
+        fd_err = fd_check(torch, kkt, workloads, dsys, dplan, dev,
+                          {"D": gD.cpu().numpy(), "C": gC.cpu().numpy(), "B": gB.cpu().numpy(), "r": lam_h})
         diff = {"workload": "1024 x (N=64, b=24, ng=4)", "fwd_bwd_systems_per_s": round(len(dsys) / (dms * 1e-3), 1),
-                "ms_per_step": round(dms, 4), "grad_max_rel_err_vs_oracle": gerr}
+                "ms_per_step": round(dms, 4), "grad_max_rel_err_vs_oracle": gerr,
+                "grad_max_rel_err_vs_central_fd_h1e-6": fd_err}
+        assert fd_err <= 1e-6, "finite-difference gradient check failed: %.3e" % fd_err
         log("diff workload: %.3f ms per fwd+bwd -> %.0f systems/s, grad err %.2e" % (dms, len(dsys) / (dms * 1e-3), gerr))
 
     value = S / (ms_per_step * 1e-3)
@@ -317,16 +453,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": "ragged batch: %d systems, N~U{16..256}, b~U{8,16,32}, ng~U{0,2,4}, 1 rhs, seed 4"
                                % S, "segments": "p=%d" % args.p if args.p else "cost model"},
-        "plain_systems_per_s": round(plain_sps, 1),
+        "plain_systems_per_s": None if plain_sps is None else round(plain_sps, 1),
         "plain_sample": int(len(samp)),
-        "batched_vs_plain": round(value / plain_sps, 2),
+        "batched_vs_plain": None if plain_sps is None else round(value / plain_sps, 2),
         "graph_ms_per_step": None if graph_ms is None else round(graph_ms, 4),
         "max_rel_residual": worst,
         "sampled_parity_vs_oracle": par,
         "per_class_kernel_ms": {str(classes[c][0]): round(float(cls_ms[c]), 4) for c in range(len(classes))},
         "differentiation": diff,
+        "single_system": single,
         "roofline": roofline,
-        "cpu_baseline": {"value": round(cpu_sps, 2), "unit": "systems/s", "cores": 1, "kind": "oracle",
+        "cpu_baseline": {"value": None if cpu_sps is None else round(cpu_sps, 2), "unit": "systems/s", "cores": 1,
+                         "kind": "oracle",
                          "sample": "%d random systems of the batch, factor + solve each" % len(csamp)},
     }
     print(json.dumps(out), flush=True)
