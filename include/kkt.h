@@ -82,7 +82,7 @@ typedef struct {
     int32_t num_systems;
     int32_t nrhs;
     int32_t num_items;        /* (system, segment) work items                      */
-    int32_t num_classes;      /* block-size classes = persistent launches per call */
+    int32_t num_classes;      /* launch classes = persistent launches per call (at most 7) */
     int64_t D_len, C_len, B_len, corner_len, rhs_len;   /* pool lengths, doubles   */
     int64_t workspace_bytes;
     double  factor_flops;     /* standard flop count of one factorization          */
@@ -178,9 +178,13 @@ int kkt_workspace_error(const kkt_plan *plan, const void *workspace, hipStream_t
  * item (each poll sleeps briefly); default 4 Mi.  For tests of the error path. */
 int kkt_plan_set_spin_limit(kkt_plan *plan, int32_t limit);
 
-/* Block-size class c of the plan (0 <= c < num_classes): padded block size,
- * number of work items, threads per workgroup, LDS bytes of its launch and the
- * number of resident workgroups launched (0 before the first call). */
+/* Launch class c of the plan (0 <= c < num_classes): padded block size, number
+ * of work items, threads per workgroup and LDS bytes of its factor-mode launch,
+ * and the largest number of resident workgroups launched so far (0 before the
+ * first call).  Systems are grouped by padded block size (8, 16, 24, 32); in the
+ * 16, 24 and 32 groups the unsegmented systems (p = 1) form a class of their own
+ * whose factor-mode launch runs one 64-lane wave per system (a dense stage sweep
+ * on the FP64 matrix cores). */
 int kkt_plan_class_info(const kkt_plan *plan, int32_t c, int32_t *block_pad, int32_t *num_items,
                         int32_t *threads, int64_t *lds_bytes, int32_t *grid);
 

@@ -29,6 +29,7 @@
 #include "kkt.h"
 #include "kkt_device.h"
 #include "kkt_sweeps.h"
+#include "kkt_dense.h"
 
 using namespace kkt_dev;
 
@@ -44,10 +45,10 @@ __device__ __forceinline__ const double *seg_scr(const Args &a, const SysDesc &s
 // tilde R = sym(corner) + sum_k tilde R_k (+ reduced-chain part), then
 // hat R = chol(tilde R) (Algorithm 1, last two lines; Eq. 8d).  With FWD also
 // hat y_g = hat R^{-1} tilde y_g and x_g = hat R^{-T} hat y_g (Algorithms 2, 3).
-template <int BP, bool FWD>
+template <int BP, bool FWD, int NTT = K<BP>::NT>
 __device__ __forceinline__ bool corner_factor(const Args &a, const SysDesc &sd, const Lds &L, bool red)
 {
-    constexpr int NT = K<BP>::NT, G0 = K<BP>::G0, PC = NGM + 1;
+    constexpr int NT = NTT, G0 = K<BP>::G0, PC = NGM + 1;
     static_assert(K<BP>::NROWS * (BP + 1) >= NGM * PC || BP >= NGM, "corner staging must fit");
     const int ng = sd.ng, nr = a.nr, tid = threadIdx.x, b = sd.b, N = sd.N;
     if (ng == 0) return false;
@@ -323,6 +324,43 @@ __global__ void __launch_bounds__(K<BP>::NT) kkt_persistent(Args a)
     }
 }
 
+// Whole (p = 1) systems of the 16- and 32-wide classes in the factor modes: one
+// wave per system, dense stage sweep on the matrix cores, then the corner and the
+// backward substitution (Algorithms 1-3 with p = 1).
+template <int DB, int MODE>
+__global__ void __launch_bounds__(64, 2) kkt_dense(Args a)
+{
+    extern __shared__ double lds_raw[];
+    const Lds L = make_lds_dense(lds_raw, DB, a.nr);
+    int *sh = L.misc;
+    const int tid = threadIdx.x;
+    constexpr bool FWD = MODE == M_FACTOR_SOLVE;
+    for (;;) {
+        if (tid == 0) sh[0] = atomicAdd(&a.ctr[0], 1);
+        __syncthreads();
+        const int it = sh[0];
+        __syncthreads();
+        if (it >= a.n_items) break;
+        const int2 w = a.items[it];
+        const SysDesc sd = a.sys[w.x];
+        const int f = dense_factor<DB, FWD>(a, sd, L);
+        const bool cf = corner_factor<DB, FWD, 64>(a, sd, L, false);
+        if (tid == 0) {
+            const int info = f ? f : (cf ? sd.N + 1 : 0);
+            a.status[w.x] = info;
+            if (a.info) a.info[w.x] = info;
+            sh[2] = info;
+        }
+        __syncthreads();
+        if (FWD) {
+            sweep_backward<DB, false, false, 64>(a, sd, 1, L);
+            __syncthreads();
+            if (sh[2] != 0) fill_nan<64>(a, sd, 0, sd.N, true);
+            __syncthreads();
+        }
+    }
+}
+
 __global__ void kkt_reset(int *ctr, int nctr, int *arrive, int *failidx, int S, int *ready, int nready,
                           int *info)
 {
@@ -359,6 +397,19 @@ kfun_t kernel_for(int mode)
     default: return kkt_persistent<BP, M_ADJOINT>;
     }
 }
+
+template <int DB>
+kfun_t dense_kernel_for(int mode)
+{
+    return mode == M_FACTOR ? kkt_dense<DB, M_FACTOR> : kkt_dense<DB, M_FACTOR_SOLVE>;
+}
+
+kfun_t dense_kernel_for(int bp, int mode)
+{
+    return bp <= 16 ? dense_kernel_for<16>(mode) : dense_kernel_for<32>(mode);
+}
+
+int dense_width(int bp) { return bp <= 16 ? 16 : 32; }
 
 kfun_t kernel_for_class(int cls, int mode)
 {
@@ -512,6 +563,8 @@ struct kkt_plan {
         int cls = 0, bp = 0, nt = 0;
         int item_off = 0, item_cnt = 0, s3_off = 0, s3_cnt = 0;
         size_t lds = 0;
+        bool dense = false;       // whole (p = 1) systems, dense sweep in the factor modes
+        size_t lds_dense = 0;     // LDS of the dense launch
     };
     std::vector<Cls> cls;
     std::vector<int2> items;
@@ -533,10 +586,11 @@ struct kkt_plan {
     }
     // launch configuration per (class, mode), filled on first use so that later
     // calls (and graph capture) make no device queries
-    mutable int grid[4][4] = {{0}};
+    static constexpr int MAXC = 8;
+    mutable int grid[MAXC][4] = {{0}};
     // optional per-class timing events (kkt_plan_set_class_events)
-    hipEvent_t ev_start[4] = {nullptr, nullptr, nullptr, nullptr};
-    hipEvent_t ev_stop[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_start[MAXC] = {nullptr};
+    hipEvent_t ev_stop[MAXC] = {nullptr};
 };
 
 namespace {
@@ -580,24 +634,27 @@ int launch_mode(const kkt_plan *plan, int mode, const Args &base, hipStream_t st
         a.s3_ready = base.s3_ready + c.s3_off;
         a.n_s3 = c.s3_cnt;
         a.ctr = base.ctr + 4 * ci;
-        kfun_t fn = kernel_for_class(c.cls, mode);
+        const bool dense = c.dense && mode <= M_FACTOR_SOLVE;
+        kfun_t fn = dense ? dense_kernel_for(c.bp, mode) : kernel_for_class(c.cls, mode);
+        const int nt = dense ? 64 : c.nt;
+        const size_t lds = dense ? c.lds_dense : c.lds;
         int &grid = plan->grid[ci][mode];
         if (grid == 0) {
             int dev = 0, ncu = 0, occ = 0;
             if (hipGetDevice(&dev) != hipSuccess) return KKT_ELAUNCH;
             if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
                 return KKT_ELAUNCH;
-            if (c.lds > 65536 &&
-                hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds) !=
+            if (lds > 65536 &&
+                hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
                     hipSuccess)
                 return KKT_ELAUNCH;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, c.nt, c.lds) != hipSuccess ||
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, nt, lds) != hipSuccess ||
                 occ < 1)
                 occ = 1;
             grid = std::max(1, std::min(c.item_cnt, occ * ncu));
         }
         if (plan->ev_start[ci] && hipEventRecord(plan->ev_start[ci], stream) != hipSuccess) return KKT_ELAUNCH;
-        hipLaunchKernelGGL(fn, dim3(grid), dim3(c.nt), c.lds, stream, a);
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(nt), lds, stream, a);
         if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
         if (plan->ev_stop[ci] && hipEventRecord(plan->ev_stop[ci], stream) != hipSuccess) return KKT_ELAUNCH;
     }
@@ -721,12 +778,18 @@ int kkt_plan_create_tuned(kkt_plan **out, int32_t S, const kkt_dims *dims_in, in
     P->nF = oF;
     // items grouped by class, LPT (longest first) inside a class
     int nitems = 0, ns3 = 0;
-    for (int c = 0; c < NCLS; ++c) {
+    for (int cc = 0; cc < 2 * NCLS; ++cc) {
+        // per block-size class: whole systems of the 16/24/32 classes first (dense
+        // launch in the factor modes), then everything else
+        const int c = cc >> 1;
+        const bool dense = (cc & 1) == 0 && CLS_BP[c] >= 16;
+        if ((cc & 1) == 0 && !dense) continue;
         std::vector<std::pair<double, int2>> its;
         int s3 = 0;
         for (int s = 0; s < S; ++s) {
             if (cls_of[s] != c) continue;
             const SysDesc &sd = P->sys[s];
+            if (CLS_BP[c] >= 16 && (sd.p == 1) != dense) continue;
             for (int k = 1; k <= sd.p; ++k) its.push_back({item_cost(sd, k), make_int2(s, k)});
             if (sd.p > 1) s3 += sd.p - 1;
         }
@@ -743,6 +806,8 @@ int kkt_plan_create_tuned(kkt_plan **out, int32_t S, const kkt_dims *dims_in, in
         C.s3_off = ns3;
         C.s3_cnt = s3;
         C.lds = (size_t)lds_offsets(C.bp, nrhs).total * sizeof(double);
+        C.dense = dense;
+        if (dense) C.lds_dense = (size_t)lds_offsets_dense(dense_width(C.bp), nrhs).total * sizeof(double);
         for (auto &x : its) P->items.push_back(x.second);
         nitems += C.item_cnt;
         ns3 += s3;
@@ -915,8 +980,8 @@ int kkt_plan_class_info(const kkt_plan *plan, int32_t c, int32_t *block_pad, int
     const kkt_plan::Cls &C = plan->cls[c];
     if (block_pad) *block_pad = C.bp;
     if (num_items) *num_items = C.item_cnt;
-    if (threads) *threads = C.nt;
-    if (lds_bytes) *lds_bytes = (int64_t)C.lds;
+    if (threads) *threads = C.dense ? 64 : C.nt;
+    if (lds_bytes) *lds_bytes = (int64_t)(C.dense ? C.lds_dense : C.lds);
     return KKT_OK;
 }
 

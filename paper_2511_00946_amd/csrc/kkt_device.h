@@ -32,6 +32,7 @@
 namespace kkt_dev {
 
 constexpr int NGM = 16;          // maximum global block size
+constexpr int MAX_NRHS_DEV = 8;  // maximum right-hand sides per call
 
 struct SysDesc {
     int N, b, ng, p, N1, Nk, cls, pad;

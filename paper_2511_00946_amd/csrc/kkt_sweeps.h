@@ -348,10 +348,10 @@ __device__ __forceinline__ void sweep_forward(const Args &a, const SysDesc &sd, 
 // rows into LDS with coalesced loads; wave 0 computes, lane c owning column c.
 // The current solution (x, or lambda in the adjoint) is read from and written to
 // rhs in place.  With ADJ the gradient blocks of the stages visited are written.
-template <int BP, bool ADJ, bool RED>
+template <int BP, bool ADJ, bool RED, int NTT = K<BP>::NT>
 __device__ __forceinline__ void sweep_backward(const Args &a, const SysDesc &sd, int k, const Lds &L)
 {
-    constexpr int NT = K<BP>::NT, P = K<BP>::PITCH;
+    constexpr int NT = NTT, P = K<BP>::PITCH;
     const Chain<BP, RED> ch{a, sd, k};
     const int tid = threadIdx.x;
     const int b = sd.b, ng = sd.ng, nr = a.nr, N = sd.N;
