@@ -106,6 +106,20 @@ def measured_traffic(bp, p, S):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
+def is_dense(cls):
+    """A launch class of whole (p = 1) systems run by the single-wave dense sweep."""
+    return cls[0] >= 16 and cls[2] == 64
+
+
+def in_class(cls, b, p):
+    """Whether a system of block size b split into p segments belongs to a launch class."""
+    if class_of(b) != cls[0]:
+        return False
+    if cls[0] < 16:
+        return True
+    return (p == 1) == is_dense(cls)
+
+
 def class_of(b):
     for i, bp in enumerate((8, 16, 24, 32)):
         if b <= bp:
@@ -334,13 +348,15 @@ def main():
     # roofline of the dominant class kernel
     bytes_sys = alg_bytes(plan, systems)
     dom = int(np.argmax(cls_ms))
-    dom_bp = classes[dom][0]
-    dom_bytes = float(sum(bytes_sys[s] for s, sy in enumerate(systems) if class_of(sy.b) == dom_bp))
+    dom_bp, dom_dense = classes[dom][0], is_dense(classes[dom])
+    dom_bytes = float(sum(bytes_sys[s] for s, sy in enumerate(systems)
+                          if in_class(classes[dom], sy.b, plan.layouts[s].p)))
     achieved = dom_bytes / (cls_ms[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic(dom_bp, args.p, S),
-                "kernel": "kkt_persistent<%d, factor_solve>" % dom_bp,
+                "traffic": measured_traffic(("d%d" if dom_dense else "%d") % dom_bp, args.p, S),
+                "kernel": ("kkt_dense<%d, factor_solve>" % (16 if dom_bp <= 16 else 32)) if dom_dense
+                          else "kkt_persistent<%d, factor_solve>" % dom_bp,
                 "kernel_ms": round(float(cls_ms[dom]), 4), "alg_bytes": dom_bytes}
 
     # plain single-system path: one call (one launch) per system, on a sample
@@ -459,7 +475,8 @@ def main():
         "graph_ms_per_step": None if graph_ms is None else round(graph_ms, 4),
         "max_rel_residual": worst,
         "sampled_parity_vs_oracle": par,
-        "per_class_kernel_ms": {str(classes[c][0]): round(float(cls_ms[c]), 4) for c in range(len(classes))},
+        "per_class_kernel_ms": {("dense%d" if is_dense(classes[c]) else "%d") % classes[c][0]: round(float(cls_ms[c]), 4)
+                                for c in range(len(classes))},
         "differentiation": diff,
         "single_system": single,
         "roofline": roofline,

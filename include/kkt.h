@@ -14,9 +14,12 @@
  *
  * Memory: every data pointer is a DEVICE pointer owned by the caller.  The
  * library never allocates device memory.  Factor and solve calls only enqueue
- * work on the caller's stream (no host synchronisation), so they can be
- * captured in a HIP graph; kkt_workspace_init and kkt_workspace_error
- * synchronise the stream.  Scratch lives in the caller's workspace (kkt_plan_info.workspace_bytes,
+ * work (no host synchronisation), so they can be captured in a HIP graph;
+ * kkt_workspace_init and kkt_workspace_error synchronise the stream.  When a plan
+ * has more than one launch class, the classes of a call run concurrently on
+ * streams the plan creates on first use (one per class and device), forked from
+ * and joined back into the caller's stream with events: the call stays ordered
+ * on the caller's stream.  Scratch lives in the caller's workspace (kkt_plan_info.workspace_bytes,
  * 256-byte aligned); kkt_workspace_init must be enqueued once on a workspace
  * before its first use with a plan.  Calls that share a workspace must not
  * overlap in time.

@@ -108,10 +108,10 @@ __device__ __forceinline__ bool corner_factor(const Args &a, const SysDesc &sd, 
 }
 
 // Corner solve with the factor in place: tilde y_g, hat y_g, x_g.
-template <int BP>
+template <int BP, int NTT = K<BP>::NT>
 __device__ __forceinline__ void corner_solve(const Args &a, const SysDesc &sd, const Lds &L, bool red)
 {
-    constexpr int NT = K<BP>::NT, G0 = K<BP>::G0;
+    constexpr int NT = NTT, G0 = K<BP>::G0;
     const int ng = sd.ng, nr = a.nr, tid = threadIdx.x, b = sd.b, N = sd.N;
     if (ng == 0) return;
     double *rg = a.rhs + sd.oRhs + (long long)N * b * nr;
@@ -324,17 +324,18 @@ __global__ void __launch_bounds__(K<BP>::NT) kkt_persistent(Args a)
     }
 }
 
-// Whole (p = 1) systems of the 16- and 32-wide classes in the factor modes: one
-// wave per system, dense stage sweep on the matrix cores, then the corner and the
-// backward substitution (Algorithms 1-3 with p = 1).
+// Whole (p = 1) systems of the 16-, 24- and 32-wide classes: one wave per
+// system, dense stage sweeps (factor on the matrix cores, forward and backward
+// substitution with the next stage's blocks in flight), then the corner
+// (Algorithms 1-3 with p = 1).
 template <int DB, int MODE>
-__global__ void __launch_bounds__(64, 2) kkt_dense(Args a)
+__global__ void __launch_bounds__(64, DB == 16 ? 2 : 1) kkt_dense(Args a)
 {
     extern __shared__ double lds_raw[];
     const Lds L = make_lds_dense(lds_raw, DB, a.nr);
     int *sh = L.misc;
     const int tid = threadIdx.x;
-    constexpr bool FWD = MODE == M_FACTOR_SOLVE;
+    constexpr bool FACT = MODE == M_FACTOR || MODE == M_FACTOR_SOLVE;
     for (;;) {
         if (tid == 0) sh[0] = atomicAdd(&a.ctr[0], 1);
         __syncthreads();
@@ -343,17 +344,25 @@ __global__ void __launch_bounds__(64, 2) kkt_dense(Args a)
         if (it >= a.n_items) break;
         const int2 w = a.items[it];
         const SysDesc sd = a.sys[w.x];
-        const int f = dense_factor<DB, FWD>(a, sd, L);
-        const bool cf = corner_factor<DB, FWD, 64>(a, sd, L, false);
-        if (tid == 0) {
-            const int info = f ? f : (cf ? sd.N + 1 : 0);
-            a.status[w.x] = info;
-            if (a.info) a.info[w.x] = info;
-            sh[2] = info;
+        if (FACT) {
+            constexpr bool FWD = MODE == M_FACTOR_SOLVE;
+            const int f = dense_factor<DB, FWD>(a, sd, L);
+            const bool cf = corner_factor<DB, FWD, 64>(a, sd, L, false);
+            if (tid == 0) {
+                const int info = f ? f : (cf ? sd.N + 1 : 0);
+                a.status[w.x] = info;
+                if (a.info) a.info[w.x] = info;
+                sh[2] = info;
+            }
+        } else {
+            dense_forward<DB>(a, sd, L);
+            corner_solve<DB, 64>(a, sd, L, false);
+            if (MODE == M_ADJOINT) corner_grad<DB>(a, sd, L);
+            if (tid == 0) sh[2] = load_status(&a.status[w.x]);
         }
         __syncthreads();
-        if (FWD) {
-            sweep_backward<DB, false, false, 64>(a, sd, 1, L);
+        if (MODE != M_FACTOR) {
+            dense_backward<DB, MODE == M_ADJOINT>(a, sd, L);
             __syncthreads();
             if (sh[2] != 0) fill_nan<64>(a, sd, 0, sd.N, true);
             __syncthreads();
@@ -401,7 +410,12 @@ kfun_t kernel_for(int mode)
 template <int DB>
 kfun_t dense_kernel_for(int mode)
 {
-    return mode == M_FACTOR ? kkt_dense<DB, M_FACTOR> : kkt_dense<DB, M_FACTOR_SOLVE>;
+    switch (mode) {
+    case M_FACTOR: return kkt_dense<DB, M_FACTOR>;
+    case M_FACTOR_SOLVE: return kkt_dense<DB, M_FACTOR_SOLVE>;
+    case M_SOLVE: return kkt_dense<DB, M_SOLVE>;
+    default: return kkt_dense<DB, M_ADJOINT>;
+    }
 }
 
 kfun_t dense_kernel_for(int bp, int mode)
@@ -591,6 +605,40 @@ struct kkt_plan {
     // optional per-class timing events (kkt_plan_set_class_events)
     hipEvent_t ev_start[MAXC] = {nullptr};
     hipEvent_t ev_stop[MAXC] = {nullptr};
+    // With several classes, each class runs on a stream of its own, forked from and
+    // joined back into the caller's stream through events (created on first use on
+    // the current device; the mutex keeps concurrent callers' fork/join sequences
+    // from interleaving).
+    mutable std::mutex side_mu;
+    mutable int side_dev = -1;
+    mutable hipStream_t side[MAXC] = {nullptr};
+    mutable hipEvent_t fork_ev = nullptr;
+    mutable hipEvent_t join_ev[MAXC] = {nullptr};
+    void release_side() const
+    {
+        for (int c = 0; c < MAXC; ++c) {
+            if (side[c]) hipStreamDestroy(side[c]);
+            if (join_ev[c]) hipEventDestroy(join_ev[c]);
+            side[c] = nullptr;
+            join_ev[c] = nullptr;
+        }
+        if (fork_ev) hipEventDestroy(fork_ev);
+        fork_ev = nullptr;
+        side_dev = -1;
+    }
+    bool ensure_side(int dev) const
+    {
+        if (side_dev == dev) return true;
+        release_side();
+        if (hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming) != hipSuccess) return false;
+        for (size_t c = 0; c < cls.size() && c < (size_t)MAXC; ++c) {
+            if (hipStreamCreateWithFlags(&side[c], hipStreamNonBlocking) != hipSuccess) return false;
+            if (hipEventCreateWithFlags(&join_ev[c], hipEventDisableTiming) != hipSuccess) return false;
+        }
+        side_dev = dev;
+        return true;
+    }
+    ~kkt_plan() { release_side(); }
 };
 
 namespace {
@@ -624,9 +672,21 @@ int launch_mode(const kkt_plan *plan, int mode, const Args &base, hipStream_t st
                        base.ctr, nctr, base.arrive, (mode <= M_FACTOR_SOLVE) ? base.failidx : nullptr, plan->S,
                        base.s3_ready - 0, (int)plan->info.num_items, (mode <= M_FACTOR_SOLVE) ? info : nullptr);
     if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
+    int ncls = 0;
+    for (const kkt_plan::Cls &c : plan->cls) ncls += c.item_cnt > 0;
+    const bool fork = ncls > 1;
+    std::unique_lock<std::mutex> side_lock(plan->side_mu, std::defer_lock);
+    if (fork) {
+        side_lock.lock();
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || !plan->ensure_side(dev)) return KKT_ELAUNCH;
+        if (hipEventRecord(plan->fork_ev, stream) != hipSuccess) return KKT_ELAUNCH;
+    }
     for (size_t ci = 0; ci < plan->cls.size(); ++ci) {
         const kkt_plan::Cls &c = plan->cls[ci];
         if (c.item_cnt == 0) continue;
+        hipStream_t st = fork ? plan->side[ci] : stream;
+        if (fork && hipStreamWaitEvent(st, plan->fork_ev, 0) != hipSuccess) return KKT_ELAUNCH;
         Args a = base;
         a.items = base.items + c.item_off;
         a.n_items = c.item_cnt;
@@ -634,7 +694,7 @@ int launch_mode(const kkt_plan *plan, int mode, const Args &base, hipStream_t st
         a.s3_ready = base.s3_ready + c.s3_off;
         a.n_s3 = c.s3_cnt;
         a.ctr = base.ctr + 4 * ci;
-        const bool dense = c.dense && mode <= M_FACTOR_SOLVE;
+        const bool dense = c.dense;
         kfun_t fn = dense ? dense_kernel_for(c.bp, mode) : kernel_for_class(c.cls, mode);
         const int nt = dense ? 64 : c.nt;
         const size_t lds = dense ? c.lds_dense : c.lds;
@@ -653,10 +713,13 @@ int launch_mode(const kkt_plan *plan, int mode, const Args &base, hipStream_t st
                 occ = 1;
             grid = std::max(1, std::min(c.item_cnt, occ * ncu));
         }
-        if (plan->ev_start[ci] && hipEventRecord(plan->ev_start[ci], stream) != hipSuccess) return KKT_ELAUNCH;
-        hipLaunchKernelGGL(fn, dim3(grid), dim3(nt), lds, stream, a);
+        if (plan->ev_start[ci] && hipEventRecord(plan->ev_start[ci], st) != hipSuccess) return KKT_ELAUNCH;
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(nt), lds, st, a);
         if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
-        if (plan->ev_stop[ci] && hipEventRecord(plan->ev_stop[ci], stream) != hipSuccess) return KKT_ELAUNCH;
+        if (plan->ev_stop[ci] && hipEventRecord(plan->ev_stop[ci], st) != hipSuccess) return KKT_ELAUNCH;
+        if (fork && (hipEventRecord(plan->join_ev[ci], st) != hipSuccess ||
+                     hipStreamWaitEvent(stream, plan->join_ev[ci], 0) != hipSuccess))
+            return KKT_ELAUNCH;
     }
     return KKT_OK;
 }

@@ -34,21 +34,18 @@ __device__ __forceinline__ dx4 mfma4(double a, double b, dx4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// sqrt(x) and 1/sqrt(x) from the hardware reciprocal square root refined by two
-// Goldschmidt iterations (g -> sqrt(x), h -> 1/(2 sqrt(x))); for x > 0 finite the
-// result is within a few ulp of the correctly rounded values.
-__device__ __forceinline__ void sqrt_rsqrt(double x, double &d, double &inv)
+// sum_k row[k] * v[k * stride] over k < DB (two partial sums, fully unrolled so
+// every LDS read is issued ahead of the chain).
+template <int DB>
+__device__ __forceinline__ double dot_strided(const double *row, const double *v, int stride)
 {
-    const double y0 = __builtin_amdgcn_rsq(x);
-    double g = x * y0, h = 0.5 * y0;
-    double r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    d = g;
-    inv = h + h;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < DB; k += 2) {
+        s0 = fma(row[k], v[k * stride], s0);
+        s1 = fma(row[k + 1], v[(k + 1) * stride], s1);
+    }
+    return s0 + s1;
 }
 
 // Dense LDS layout: a panel area of (2 DB + 16) rows with pitch DB + 1 (the
@@ -60,7 +57,7 @@ __host__ __device__ __forceinline__ LdsOff lds_offsets_dense(int DB, int nr)
     LdsOff o;
     const int PITCH = DB + 1;
     int t = 0;
-    o.col = t; t += 2 * (DB > NGM ? DB : NGM);
+    o.col = t; t += 2 * (DB > NGM ? DB : NGM) + 64;   // + one dummy slot per lane
     o.P = t;   t += (2 * DB + NGM) * PITCH;
     o.A = o.P; o.Q = o.P; o.RP = o.P;
     o.R = t;   t += NGM * NGM;
@@ -142,7 +139,17 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         const bool isI = lane_s >= DB && lane_s < 2 * DB;
         const int ri = isP ? lane_s : lane_s - DB;
 
-        // ---- (0) C_i in MFMA operand layout, in flight during the factorization
+        // ---- (0) r_{i+1} and C_i (MFMA operand layout), in flight during the factorization
+        constexpr int RM = (DB * MAX_NRHS_DEV + NTL - 1) / NTL;
+        double rn[RM];
+        if (FWD) {
+            const double *rs = a.rhs + sd.oRhs + (long long)(i + 1) * b * nr;
+#pragma unroll
+            for (int m = 0; m < RM; ++m) {
+                const int e = lane_s + m * NTL;
+                rn[m] = (hasN && e < b * nr) ? rs[e] : 0.0;
+            }
+        }
         double cA[TB][KS];
         const double *Ci = a.C + sd.oC + (long long)i * b2;
 #pragma unroll
@@ -164,31 +171,37 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             }
         }
         bool bad = false;
-        if (isP) buf0[ri] = vec[0];
+        // Every lane writes its column entry each step, the lanes that hold no
+        // entry of the column into a slot of their own: the step stays one basic
+        // block, so all its LDS reads are issued together ahead of their use.
+        double *const dummy = L.col + 2 * DB + lane_s;
+        *(isP ? buf0 + ri : dummy) = vec[0];
         wave_sync();
 #pragma unroll
         for (int c = 0; c < DB; ++c) {
-            double *cur = (c & 1) ? buf1 : buf0;
+            const double *cur = (c & 1) ? buf1 : buf0;
             double *nxt = (c & 1) ? buf0 : buf1;
-            const double dcc = cur[c];
+            double col[DB];
+#pragma unroll
+            for (int l = c; l < DB; ++l) col[l] = cur[l];
+            const double dcc = col[c];
             bad |= !(dcc > 0.0) || !isfinite(dcc);
             double d, inv;
             sqrt_rsqrt(dcc, d, inv);
-            double f = 0.0;
-            if (isP) {
-                if (ri == c) vec[c] = d;
-                else if (ri > c) { const double v = vec[c] * inv; vec[c] = v; f = v * inv; }
-            } else if (isI && ri <= c) {
-                const double x = vec[c] * inv;
-                vec[c] = x;
-                f = x * inv;
-            }
+            // row lanes below the pivot scale their entry of column c to L[ri][c];
+            // inverse lanes at or left of the pivot form X[c][ri] = acc[c] / L[c][c]
+            const double v = vec[c] * inv;
+            const bool act = isP ? (ri > c) : (isI && ri <= c);
+            const double f = act ? v * inv : 0.0;
+            vec[c] = (isP && ri == c) ? d : (act ? v : vec[c]);
             if (c + 1 < DB) {
                 // the next pivot column first, so its broadcast overlaps the rest
-                vec[c + 1] = fma(-f, cur[c + 1], vec[c + 1]);
-                if (isP && ri >= c + 1) nxt[ri] = vec[c + 1];
+                vec[c + 1] = fma(-f, col[c + 1], vec[c + 1]);
+                *((isP && ri >= c + 1) ? nxt + ri : dummy) = vec[c + 1];
+                // keep the remaining updates behind the write, so they overlap its round trip
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int l = c + 2; l < DB; ++l) vec[l] = fma(-f, cur[l], vec[l]);
+                for (int l = c + 2; l < DB; ++l) vec[l] = fma(-f, col[l], vec[l]);
             }
             pin_row<DB>(vec);
             wave_sync();
@@ -276,43 +289,35 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                 const int q = 4 * v + lk, c = 16 * ct + li;
                 bn[ct][v] = (hasN && q < ng && c < b) ? Bn[q * b + c] : 0.0;
             }
-        constexpr int RM = (DB * MAX_NRHS_DEV + NTL - 1) / NTL;
-        double rn[RM];
-        if (FWD) {
-            const double *rs = a.rhs + sd.oRhs + (long long)(i + 1) * b * nr;
-#pragma unroll
-            for (int m = 0; m < RM; ++m) {
-                const int e = lane + m * NTL;
-                rn[m] = (hasN && e < b * nr) ? rs[e] : 0.0;
-            }
-        }
 
 
         phase_fence();
         // ---- (4) forward substitution: y = L^{-1} w, w' = r_{i+1} - hat E y, y_g -= hat G y
         if (FWD) {
-            for (int e = lane; e < DB * nr; e += NTL) {
-                const int r = e / nr, j = e - r * nr;
-                double s = 0.0;
-                for (int k = 0; k <= r; ++k) s = fma(RB[r * PD + k], L.W[k * nr + j], s);
-                L.Y[e] = s;
-                if (r < b) a.rhs[sd.oRhs + (long long)i * b * nr + e] = s;
-            }
-            wave_sync();
-            for (int e = lane; e < ng * nr; e += NTL) {
-                const int q = e / nr, j = e - q * nr;
-                double s = 0.0;
-                for (int k = 0; k < b; ++k) s = fma(RG[q * PD + k], L.Y[k * nr + j], s);
-                L.XG[e] -= s;
-            }
+            // y = L^{-1} w: one output per lane and round, the dot product unrolled
 #pragma unroll
             for (int m = 0; m < RM; ++m) {
-                const int e = lane + m * NTL;
+                const int e = lane_s + m * NTL;
                 if (e < DB * nr) {
                     const int r = e / nr, j = e - r * nr;
-                    double s = 0.0;
-                    for (int k = 0; k < b; ++k) s = fma(RA[r * PD + k], L.Y[k * nr + j], s);
-                    L.W[e] = (r < b) ? rn[m] - s : 0.0;
+                    const double s = dot_strided<DB>(RB + r * PD, L.W + j, nr);
+                    L.Y[e] = s;
+                    if (r < b) a.rhs[sd.oRhs + (long long)i * b * nr + e] = s;
+                }
+            }
+            wave_sync();
+            // w' = r_{i+1} - hat E y on outputs [0, DB nr), y_g -= hat G y on the next ng nr
+            constexpr int WM = ((DB + NGM) * MAX_NRHS_DEV + NTL - 1) / NTL;
+#pragma unroll
+            for (int m = 0; m < WM; ++m) {
+                const int e = lane_s + m * NTL;
+                if (e < DB * nr) {
+                    const int r = e / nr, j = e - r * nr;
+                    const double s = dot_strided<DB>(RA + r * PD, L.Y + j, nr);
+                    L.W[e] = (r < b) ? (m < RM ? rn[m < RM ? m : 0] : 0.0) - s : 0.0;
+                } else if (e < (DB + ng) * nr) {
+                    const int e2 = e - DB * nr, q = e2 / nr, j = e2 - q * nr;
+                    L.XG[e2] -= dot_strided<DB>(RG + q * PD, L.Y + j, nr);
                 }
             }
         }
@@ -387,6 +392,276 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
     }
     wave_sync();
     return failed;
+}
+
+// Factor blocks and y of stage i, fetched into registers (element e = lane + 64 m
+// of each row-major block).
+template <int DB>
+struct BwdStage {
+    static constexpr int NTL = 64, MD = DB * DB / NTL, MG = NGM * DB / NTL,
+                         MY = (DB * MAX_NRHS_DEV + NTL - 1) / NTL;
+    double d[MD], e[MD], g[MG], y[MY], px[MY];
+
+    // with PRIMAL, also the primal solution of stage i (adjoint gradients)
+    template <bool PRIMAL = false>
+    __device__ __forceinline__ void fetch(const Args &a, const SysDesc &sd, int i, int lane)
+    {
+        const int b = sd.b, ng = sd.ng, nr = a.nr;
+        const long long b2 = (long long)b * b;
+        const bool hasE = i + 1 < sd.N;
+        const double *Ld = a.F + sd.oLd + (long long)i * b2, *Lc = a.F + sd.oLc + (long long)i * b2;
+        const double *Lb = a.F + sd.oLb + (long long)i * ng * b, *Y = a.rhs + sd.oRhs + (long long)i * b * nr;
+#pragma unroll
+        for (int m = 0; m < MD; ++m) {
+            const int x = lane + m * NTL;
+            d[m] = (x < b * b) ? Ld[x] : 0.0;
+            e[m] = (hasE && x < b * b) ? Lc[x] : 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < MG; ++m) {
+            const int x = lane + m * NTL;
+            g[m] = (x < ng * b) ? Lb[x] : 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < MY; ++m) {
+            const int x = lane + m * NTL;
+            y[m] = (x < b * nr) ? Y[x] : 0.0;
+        }
+        if (PRIMAL) {
+            const double *XP = a.xp + sd.oRhs + (long long)i * b * nr;
+#pragma unroll
+            for (int m = 0; m < MY; ++m) {
+                const int x = lane + m * NTL;
+                px[m] = (x < b * nr) ? XP[x] : 0.0;
+            }
+        }
+    }
+
+    // into the staging area (rows of pitch DB + 1) and XC
+    __device__ __forceinline__ void stage(const SysDesc &sd, int nr, double *stD, double *stE, double *stG, double *XC,
+                                          int lane) const
+    {
+        constexpr int PD = DB + 1;
+        const int b = sd.b, ng = sd.ng;
+        const float invb = 1.0f / (float)b;
+#pragma unroll
+        for (int m = 0; m < MD; ++m) {
+            const int x = lane + m * NTL;
+            if (x < b * b) {
+                const int r = row_of(x, invb), c = x - r * b;
+                stD[r * PD + c] = d[m];
+                stE[r * PD + c] = e[m];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < MG; ++m) {
+            const int x = lane + m * NTL;
+            if (x < ng * b) {
+                const int r = row_of(x, invb), c = x - r * b;
+                stG[r * PD + c] = g[m];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < MY; ++m) {
+            const int x = lane + m * NTL;
+            if (x < b * nr) XC[x] = y[m];
+        }
+    }
+
+    __device__ __forceinline__ void stage_primal(const SysDesc &sd, int nr, double *PC, int lane) const
+    {
+#pragma unroll
+        for (int m = 0; m < MY; ++m) {
+            const int x = lane + m * NTL;
+            if (x < sd.b * nr) PC[x] = px[m];
+        }
+    }
+};
+
+// Forward substitution of a whole system with one wave and the factor in place
+// (Algorithm 2 with p = 1): y_i = L_ii^{-1} w_i, w_{i+1} = r_{i+1} - hat E_i y_i,
+// y_g partial -= hat G_i y_i; y overwrites the rhs, the y_g partial goes to the
+// scratch of segment 1.  The blocks and rhs of stage i + 1 are in flight while
+// stage i is solved.
+template <int DB>
+__device__ __forceinline__ void dense_forward(const Args &a, const SysDesc &sd, const Lds &L)
+{
+    constexpr int PD = DB + 1, NTL = 64, MY = BwdStage<DB>::MY;
+    constexpr int GM = (NGM * MAX_NRHS_DEV + NTL - 1) / NTL;
+    const int lane = threadIdx.x;
+    const int b = sd.b, ng = sd.ng, nr = a.nr, N = sd.N;
+    double *X = a.rhs + sd.oRhs;
+    double *stD = L.P, *stE = L.P + DB * PD, *stG = L.P + 2 * DB * PD;
+    for (int e = lane; e < DB * nr; e += NTL) L.W[e] = (e < b * nr) ? X[e] : 0.0;
+    for (int e = lane; e < NGM * nr; e += NTL) L.XG[e] = 0.0;
+    BwdStage<DB> pf;
+    pf.fetch(a, sd, 0, lane);
+    for (int i = 0; i < N; ++i) {
+        int lane_s = lane;
+        asm volatile("" : "+v"(lane_s));
+        const int r = lane_s;
+        const bool rv = r < b;
+        const bool hasN = i + 1 < N;
+        wave_sync();
+        pf.stage(sd, nr, stD, stE, stG, L.Y, lane_s);   // Y receives r_i (unused; w_i is in W)
+        wave_sync();
+        if (hasN) pf.fetch(a, sd, i + 1, lane_s);
+        double drow[DB];
+#pragma unroll
+        for (int c = 0; c < DB; ++c) {
+            const double v = stD[(rv ? r : 0) * PD + c];
+            drow[c] = (rv && c < b) ? (c <= r ? v : 0.0) : (c == r ? 1.0 : 0.0);
+        }
+        const double dinv = rv ? 1.0 / stD[r * PD + r] : 1.0;
+        for (int j = 0; j < nr; ++j) {
+            const double w = rv ? L.W[r * nr + j] : 0.0;
+            const double yv = fwd_subst<DB>(drow, w, dinv);
+            wave_sync();
+            if (rv) {
+                X[((long long)i * b + r) * nr + j] = yv;
+                L.Y[r * nr + j] = yv;
+            } else if (r < DB) {
+                L.Y[r * nr + j] = 0.0;
+            }
+            wave_sync();
+        }
+        // y_g -= hat G y (outputs e < ng nr), w_{i+1} = r_{i+1} - hat E y (outputs e < DB nr)
+#pragma unroll
+        for (int m = 0; m < GM; ++m) {
+            const int e = lane_s + m * NTL;
+            if (e < ng * nr) {
+                const int q = e / nr, j = e - q * nr;
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < DB; ++k) s = fma((k < b) ? stG[q * PD + k] : 0.0, L.Y[k * nr + j], s);
+                L.XG[e] -= s;
+            }
+        }
+        if (hasN) {
+#pragma unroll
+            for (int m = 0; m < MY; ++m) {
+                const int e = lane_s + m * NTL;
+                if (e < DB * nr) {
+                    const int rr = e / nr, j = e - rr * nr;
+                    double s = 0.0;
+#pragma unroll
+                    for (int k = 0; k < DB; ++k)
+                        s = fma((rr < b && k < b) ? stE[(rr < b ? rr : 0) * PD + k] : 0.0, L.Y[k * nr + j], s);
+                    L.W[e] = (rr < b) ? pf.y[m] - s : 0.0;
+                }
+            }
+        }
+    }
+    wave_sync();
+    if (ng)
+        for (int e = lane; e < ng * nr; e += NTL) a.F[sd.oScr + scr_yg(b, ng, nr) + e] = L.XG[e];
+    wave_sync();
+}
+
+// Backward substitution of a whole system with one wave (Algorithm 3 with p = 1):
+// x_i = L_ii^{-T} (y_i - hat E_i^T x_{i+1} - hat G_i^T x_g) for i = N-1 .. 0, with
+// the blocks of stage i - 1 in flight while stage i is solved.  x_g is in place.
+// With ADJ the solution is lambda and the gradient blocks of every stage are
+// written: dD_i = -sym(lambda_i x_i^T), dB_i = -(lambda_g x_i^T + x_g lambda_i^T),
+// dC_i = -(lambda_{i+1} x_i^T + x_{i+1} lambda_i^T), summed over the rhs columns.
+template <int DB, bool ADJ>
+__device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd, const Lds &L)
+{
+    constexpr int PD = DB + 1, NTL = 64;
+    const int lane = threadIdx.x;
+    const int b = sd.b, ng = sd.ng, nr = a.nr, N = sd.N;
+    const long long b2 = (long long)b * b;
+    double *X = a.rhs + sd.oRhs;
+    double *stD = L.P, *stE = L.P + DB * PD, *stG = L.P + 2 * DB * PD;
+    for (int e = lane; e < NGM * nr; e += NTL) {
+        L.XG[e] = (e < ng * nr) ? X[(long long)N * b * nr + e] : 0.0;
+        if (ADJ) L.PG[e] = (e < ng * nr) ? a.xp[sd.oRhs + (long long)N * b * nr + e] : 0.0;
+    }
+    for (int e = lane; e < DB * nr; e += NTL) {
+        L.XN[e] = 0.0;
+        if (ADJ) L.PN[e] = 0.0;
+    }
+    BwdStage<DB> pf;
+    pf.template fetch<ADJ>(a, sd, N - 1, lane);
+    for (int i = N - 1; i >= 0; --i) {
+        int lane_s = lane;
+        asm volatile("" : "+v"(lane_s));
+        const int c = lane_s;
+        const bool cv = c < b;
+        const bool hasE = i + 1 < N;
+        wave_sync();
+        pf.stage(sd, nr, stD, stE, stG, L.XC, lane_s);
+        if (ADJ) pf.stage_primal(sd, nr, L.PC, lane_s);
+        wave_sync();
+        if (i > 0) pf.template fetch<ADJ>(a, sd, i - 1, lane_s);
+        double dcol[DB];
+#pragma unroll
+        for (int l = 0; l < DB; ++l) {
+            const double v = stD[l * PD + (cv ? c : 0)];
+            dcol[l] = (cv && l < b) ? v : (l == c ? 1.0 : 0.0);
+        }
+        const double dinv = cv ? 1.0 / stD[c * PD + c] : 1.0;
+        for (int j = 0; j < nr; ++j) {
+            double acc0 = cv ? L.XC[c * nr + j] : 0.0, acc1 = 0.0;
+            if (hasE) {
+#pragma unroll
+                for (int r = 0; r < DB; r += 2) {
+                    const double e0 = stE[r * PD + (cv ? c : 0)], e1 = stE[(r + 1) * PD + (cv ? c : 0)];
+                    acc0 = fma((cv && r < b) ? -e0 : 0.0, L.XN[r * nr + j], acc0);
+                    acc1 = fma((cv && r + 1 < b) ? -e1 : 0.0, L.XN[(r + 1) * nr + j], acc1);
+                }
+            }
+            if (ng) {
+#pragma unroll
+                for (int q = 0; q < NGM; q += 2) {
+                    const double g0 = stG[q * PD + (cv ? c : 0)], g1 = stG[(q + 1) * PD + (cv ? c : 0)];
+                    acc0 = fma((cv && q < ng) ? -g0 : 0.0, L.XG[q * nr + j], acc0);
+                    acc1 = fma((cv && q + 1 < ng) ? -g1 : 0.0, L.XG[(q + 1) * nr + j], acc1);
+                }
+            }
+            const double xv = back_subst<DB>(dcol, acc0 + acc1, dinv);
+            wave_sync();
+            if (cv) {
+                X[((long long)i * b + c) * nr + j] = xv;
+                L.XC[c * nr + j] = xv;
+            }
+            wave_sync();
+        }
+        if (ADJ && cv) {
+            double *dD = a.dD + sd.oD + (long long)i * b2;
+            for (int r = 0; r < b; ++r) {
+                double s = 0.0;
+                for (int j = 0; j < nr; ++j)
+                    s += L.XC[r * nr + j] * L.PC[c * nr + j] + L.PC[r * nr + j] * L.XC[c * nr + j];
+                dD[r * b + c] = -0.5 * s;
+            }
+            if (ng) {
+                double *dB = a.dB + sd.oB + (long long)i * ng * b;
+                for (int q = 0; q < ng; ++q) {
+                    double s = 0.0;
+                    for (int j = 0; j < nr; ++j)
+                        s += L.XG[q * nr + j] * L.PC[c * nr + j] + L.PG[q * nr + j] * L.XC[c * nr + j];
+                    dB[q * b + c] = -s;
+                }
+            }
+            if (hasE) {
+                double *dC = a.dC + sd.oC + (long long)i * b2;
+                for (int r = 0; r < b; ++r) {
+                    double s = 0.0;
+                    for (int j = 0; j < nr; ++j)
+                        s += L.XN[r * nr + j] * L.PC[c * nr + j] + L.PN[r * nr + j] * L.XC[c * nr + j];
+                    dC[r * b + c] = -s;
+                }
+            }
+        }
+        wave_sync();
+        if (cv)
+            for (int j = 0; j < nr; ++j) {
+                L.XN[c * nr + j] = L.XC[c * nr + j];
+                if (ADJ) L.PN[c * nr + j] = L.PC[c * nr + j];
+            }
+    }
+    wave_sync();
 }
 
 }  // namespace kkt_dev

@@ -150,6 +150,23 @@ __device__ __forceinline__ double readlane_d(double v, int lane)
     return __hiloint2double(hi, lo);
 }
 
+// sqrt(x) and 1/sqrt(x) from the hardware reciprocal square root refined by two
+// Goldschmidt iterations (g -> sqrt(x), h -> 1/(2 sqrt(x))); for x > 0 finite the
+// result is within a few ulp of the correctly rounded values.
+__device__ __forceinline__ void sqrt_rsqrt(double x, double &d, double &inv)
+{
+    const double y0 = __builtin_amdgcn_rsq(x);
+    double g = x * y0, h = 0.5 * y0;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    d = g;
+    inv = h + h;
+}
+
 // Keeps the compiler from moving LDS accesses across this point; LDS operations of
 // one wavefront execute in order, so lanes of the same wave then see each other's writes.
 __device__ __forceinline__ void wave_sync()
@@ -284,8 +301,8 @@ __device__ __forceinline__ bool eliminate(double (&row)[BP], const Lds &L, int n
         __syncthreads();
         const double dcc = buf[c];
         bad |= !(dcc > 0.0) || !isfinite(dcc);
-        const double d = sqrt(dcc);
-        const double inv = 1.0 / d;
+        double d, inv;
+        sqrt_rsqrt(dcc, d, inv);
         const bool act = tid > c;                 // diagonal rows below the pivot, every panel row
         const double v = row[c] * inv;            // hat D[tid][c] or hat P[row][c]
         if (tid == c) row[c] = d;

@@ -190,8 +190,9 @@ def test_repeat_runs_bitwise_identical():
 @pytest.mark.parametrize("p", [1, 3])
 def test_adjoint_matches_oracle(p):
     kkt = _kkt()
-    systems = gen(21, [(12, 6, 3), (9, 8, 0)], nrhs=2, with_w=True)
-    ps = [p, min(p, 2)]
+    # the last three are whole (p = 1) systems of the dense classes
+    systems = gen(21, [(12, 6, 3), (9, 8, 0), (7, 16, 2), (6, 24, 4), (5, 32, 0)], nrhs=2, with_w=True)
+    ps = [p, min(p, 2), 1, 1, 1]
     plan, pools, ws, x, info = run(systems, ps, 2)
     assert (info == 0).all()
     gx = torch.from_numpy(workloads.pack(systems)["w"]).cuda()
