@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 30
 SRC_FILES = ("paper_2511_00946_amd/csrc/kkt.hip", "paper_2511_00946_amd/csrc/kkt_sweeps.h",
+             "paper_2511_00946_amd/csrc/kkt_dense.h",
              "paper_2511_00946_amd/csrc/kkt_device.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ragged4096.json")
 
