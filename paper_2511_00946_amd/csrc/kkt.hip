@@ -361,12 +361,33 @@ __global__ void __launch_bounds__(64, DB == 16 ? 2 : 1) kkt_dense(Args a)
             if (tid == 0) sh[2] = load_status(&a.status[w.x]);
         }
         __syncthreads();
-        if (MODE != M_FACTOR) {
-            dense_backward<DB, MODE == M_ADJOINT>(a, sd, L);
-            __syncthreads();
-            if (sh[2] != 0) fill_nan<64>(a, sd, 0, sd.N, true);
-            __syncthreads();
-        }
+    }
+}
+
+// Backward substitution (and with ADJ the adjoint gradients) of the whole systems
+// of a dense class, after kkt_dense has run the factor or forward sweep and the
+// corner of every one of them; a launch of its own, so that each of the two
+// sweeps gets the registers it needs.  Items come from the second queue counter.
+template <int DB, bool ADJ>
+__global__ void __launch_bounds__(64, 2) kkt_dense_bwd(Args a)
+{
+    extern __shared__ double lds_raw[];
+    const Lds L = make_lds_dense(lds_raw, DB, a.nr);
+    int *sh = L.misc;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) sh[0] = atomicAdd(&a.ctr[1], 1);
+        __syncthreads();
+        const int it = sh[0];
+        __syncthreads();
+        if (it >= a.n_items) break;
+        const int2 w = a.items[it];
+        const SysDesc sd = a.sys[w.x];
+        dense_backward<DB, ADJ>(a, sd, L);
+        if (tid == 0) sh[2] = load_status(&a.status[w.x]);
+        __syncthreads();
+        if (sh[2] != 0) fill_nan<64>(a, sd, 0, sd.N, true);
+        __syncthreads();
     }
 }
 
@@ -421,6 +442,12 @@ kfun_t dense_kernel_for(int mode)
 kfun_t dense_kernel_for(int bp, int mode)
 {
     return bp <= 16 ? dense_kernel_for<16>(mode) : dense_kernel_for<32>(mode);
+}
+
+kfun_t dense_bwd_kernel_for(int bp, int mode)
+{
+    if (mode == M_ADJOINT) return bp <= 16 ? kkt_dense_bwd<16, true> : kkt_dense_bwd<32, true>;
+    return bp <= 16 ? kkt_dense_bwd<16, false> : kkt_dense_bwd<32, false>;
 }
 
 int dense_width(int bp) { return bp <= 16 ? 16 : 32; }
@@ -601,7 +628,7 @@ struct kkt_plan {
     // launch configuration per (class, mode), filled on first use so that later
     // calls (and graph capture) make no device queries
     static constexpr int MAXC = 8;
-    mutable int grid[MAXC][4] = {{0}};
+    mutable int grid[MAXC][6] = {{0}};   // per mode; [4], [5]: backward launch of a dense class
     // optional per-class timing events (kkt_plan_set_class_events)
     hipEvent_t ev_start[MAXC] = {nullptr};
     hipEvent_t ev_stop[MAXC] = {nullptr};
@@ -695,27 +722,32 @@ int launch_mode(const kkt_plan *plan, int mode, const Args &base, hipStream_t st
         a.n_s3 = c.s3_cnt;
         a.ctr = base.ctr + 4 * ci;
         const bool dense = c.dense;
-        kfun_t fn = dense ? dense_kernel_for(c.bp, mode) : kernel_for_class(c.cls, mode);
         const int nt = dense ? 64 : c.nt;
         const size_t lds = dense ? c.lds_dense : c.lds;
-        int &grid = plan->grid[ci][mode];
-        if (grid == 0) {
-            int dev = 0, ncu = 0, occ = 0;
-            if (hipGetDevice(&dev) != hipSuccess) return KKT_ELAUNCH;
-            if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-                return KKT_ELAUNCH;
-            if (lds > 65536 &&
-                hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-                    hipSuccess)
-                return KKT_ELAUNCH;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, nt, lds) != hipSuccess ||
-                occ < 1)
-                occ = 1;
-            grid = std::max(1, std::min(c.item_cnt, occ * ncu));
-        }
+        // a dense class with a backward sweep takes a second launch (kkt_dense_bwd)
+        const int nlaunch = (dense && mode != M_FACTOR) ? 2 : 1;
         if (plan->ev_start[ci] && hipEventRecord(plan->ev_start[ci], st) != hipSuccess) return KKT_ELAUNCH;
-        hipLaunchKernelGGL(fn, dim3(grid), dim3(nt), lds, st, a);
-        if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
+        for (int l = 0; l < nlaunch; ++l) {
+            kfun_t fn = !dense ? kernel_for_class(c.cls, mode)
+                               : (l == 0 ? dense_kernel_for(c.bp, mode) : dense_bwd_kernel_for(c.bp, mode));
+            int &grid = plan->grid[ci][l == 0 ? mode : 4 + (mode == M_ADJOINT)];
+            if (grid == 0) {
+                int dev = 0, ncu = 0, occ = 0;
+                if (hipGetDevice(&dev) != hipSuccess) return KKT_ELAUNCH;
+                if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+                    return KKT_ELAUNCH;
+                if (lds > 65536 &&
+                    hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+                        hipSuccess)
+                    return KKT_ELAUNCH;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, nt, lds) != hipSuccess ||
+                    occ < 1)
+                    occ = 1;
+                grid = std::max(1, std::min(c.item_cnt, occ * ncu));
+            }
+            hipLaunchKernelGGL(fn, dim3(grid), dim3(nt), lds, st, a);
+            if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
+        }
         if (plan->ev_stop[ci] && hipEventRecord(plan->ev_stop[ci], st) != hipSuccess) return KKT_ELAUNCH;
         if (fork && (hipEventRecord(plan->join_ev[ci], st) != hipSuccess ||
                      hipStreamWaitEvent(stream, plan->join_ev[ci], 0) != hipSuccess))
@@ -1035,7 +1067,7 @@ int kkt_plan_class_info(const kkt_plan *plan, int32_t c, int32_t *block_pad, int
 {
     if (grid && plan && c >= 0 && c < (int)plan->cls.size()) {
         int g = 0;
-        for (int m = 0; m < 4; ++m) g = std::max(g, plan->grid[c][m]);
+        for (int m = 0; m < 6; ++m) g = std::max(g, plan->grid[c][m]);
         *grid = g;
     }
     if (!plan) return KKT_EPOINTER;

@@ -48,6 +48,26 @@ __device__ __forceinline__ double dot_strided(const double *row, const double *v
     return s0 + s1;
 }
 
+// acc[rt] += A B on the FP64 matrix cores for the 16-row tiles rt < RT of A
+// (KD columns) and B = KD x nr (nr <= 16, row pitch nr, columns >= nr taken as
+// zero): A[r][k] = A[r * pa + k], or A[k * pa + r] with TA.  Element v of lane l
+// of acc[rt] is row 16 rt + 4 v + l / 16, column l % 16 of the product.
+template <int RT, int KD, bool TA>
+__device__ __forceinline__ void mm_rhs(const double *A, int pa, const double *B, int nr, dx4 (&acc)[RT], int li,
+                                       int lk)
+{
+#pragma unroll
+    for (int kk = 0; kk < KD / 4; ++kk) {
+        const int k = 4 * kk + lk;
+        const double bv = (li < nr) ? B[k * nr + (li < nr ? li : 0)] : 0.0;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int r = 16 * rt + li;
+            acc[rt] = mfma4(TA ? A[k * pa + r] : A[r * pa + k], bv, acc[rt]);
+        }
+    }
+}
+
 // Dense LDS layout: a panel area of (2 DB + 16) rows with pitch DB + 1 (the
 // backward sweep and the corner reuse it as their staging area), then the same
 // small vectors as the general layout.  Regions the p = 1 path never touches
@@ -140,15 +160,16 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         const int ri = isP ? lane_s : lane_s - DB;
 
         // ---- (0) r_{i+1} and C_i (MFMA operand layout), in flight during the factorization
-        constexpr int RM = (DB * MAX_NRHS_DEV + NTL - 1) / NTL;
-        double rn[RM];
+        double rn[TB][4];   // r_{i+1} in product layout (row 16 rt + 4 v + lk, rhs li)
         if (FWD) {
             const double *rs = a.rhs + sd.oRhs + (long long)(i + 1) * b * nr;
 #pragma unroll
-            for (int m = 0; m < RM; ++m) {
-                const int e = lane_s + m * NTL;
-                rn[m] = (hasN && e < b * nr) ? rs[e] : 0.0;
-            }
+            for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * rt + 4 * v + lk;
+                    rn[rt][v] = (hasN && r < b && li < nr) ? rs[r * nr + li] : 0.0;
+                }
         }
         double cA[TB][KS];
         const double *Ci = a.C + sd.oC + (long long)i * b2;
@@ -294,30 +315,41 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         phase_fence();
         // ---- (4) forward substitution: y = L^{-1} w, w' = r_{i+1} - hat E y, y_g -= hat G y
         if (FWD) {
-            // y = L^{-1} w: one output per lane and round, the dot product unrolled
+            // y = L^{-1} w, then hat E y and hat G y, all rhs at once on the matrix cores
+            dx4 accY[TB];
 #pragma unroll
-            for (int m = 0; m < RM; ++m) {
-                const int e = lane_s + m * NTL;
-                if (e < DB * nr) {
-                    const int r = e / nr, j = e - r * nr;
-                    const double s = dot_strided<DB>(RB + r * PD, L.W + j, nr);
-                    L.Y[e] = s;
-                    if (r < b) a.rhs[sd.oRhs + (long long)i * b * nr + e] = s;
-                }
+            for (int rt = 0; rt < TB; ++rt) accY[rt] = dx4{0.0, 0.0, 0.0, 0.0};
+            mm_rhs<TB, DB, false>(RB, PD, L.W, nr, accY, li, lk);
+            if (li < nr) {
+#pragma unroll
+                for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * rt + 4 * v + lk;
+                        L.Y[r * nr + li] = accY[rt][v];
+                        if (r < b) a.rhs[sd.oRhs + ((long long)i * b + r) * nr + li] = accY[rt][v];
+                    }
             }
             wave_sync();
-            // w' = r_{i+1} - hat E y on outputs [0, DB nr), y_g -= hat G y on the next ng nr
-            constexpr int WM = ((DB + NGM) * MAX_NRHS_DEV + NTL - 1) / NTL;
+            dx4 accW[TB], accG1[1];
 #pragma unroll
-            for (int m = 0; m < WM; ++m) {
-                const int e = lane_s + m * NTL;
-                if (e < DB * nr) {
-                    const int r = e / nr, j = e - r * nr;
-                    const double s = dot_strided<DB>(RA + r * PD, L.Y + j, nr);
-                    L.W[e] = (r < b) ? (m < RM ? rn[m < RM ? m : 0] : 0.0) - s : 0.0;
-                } else if (e < (DB + ng) * nr) {
-                    const int e2 = e - DB * nr, q = e2 / nr, j = e2 - q * nr;
-                    L.XG[e2] -= dot_strided<DB>(RG + q * PD, L.Y + j, nr);
+            for (int rt = 0; rt < TB; ++rt) accW[rt] = dx4{0.0, 0.0, 0.0, 0.0};
+            accG1[0] = dx4{0.0, 0.0, 0.0, 0.0};
+            if (hasN) mm_rhs<TB, DB, false>(RA, PD, L.Y, nr, accW, li, lk);
+            if (ng) mm_rhs<1, DB, false>(RG, PD, L.Y, nr, accG1, li, lk);
+            wave_sync();
+            if (li < nr) {
+#pragma unroll
+                for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * rt + 4 * v + lk;
+                        L.W[r * nr + li] = (r < b) ? rn[rt][v] - accW[rt][v] : 0.0;
+                    }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int q = 4 * v + lk;
+                    if (q < ng) L.XG[q * nr + li] -= accG1[0][v];
                 }
             }
         }
@@ -487,13 +519,14 @@ template <int DB>
 __device__ __forceinline__ void dense_forward(const Args &a, const SysDesc &sd, const Lds &L)
 {
     constexpr int PD = DB + 1, NTL = 64, MY = BwdStage<DB>::MY;
-    constexpr int GM = (NGM * MAX_NRHS_DEV + NTL - 1) / NTL;
     const int lane = threadIdx.x;
     const int b = sd.b, ng = sd.ng, nr = a.nr, N = sd.N;
     double *X = a.rhs + sd.oRhs;
     double *stD = L.P, *stE = L.P + DB * PD, *stG = L.P + 2 * DB * PD;
     for (int e = lane; e < DB * nr; e += NTL) L.W[e] = (e < b * nr) ? X[e] : 0.0;
     for (int e = lane; e < NGM * nr; e += NTL) L.XG[e] = 0.0;
+    // the staging area outside the b x b (ng x b) blocks stays zero for the products
+    for (int e = lane; e < (2 * DB + NGM) * PD; e += NTL) L.P[e] = 0.0;
     BwdStage<DB> pf;
     pf.fetch(a, sd, 0, lane);
     for (int i = 0; i < N; ++i) {
@@ -525,30 +558,36 @@ __device__ __forceinline__ void dense_forward(const Args &a, const SysDesc &sd, 
             }
             wave_sync();
         }
-        // y_g -= hat G y (outputs e < ng nr), w_{i+1} = r_{i+1} - hat E y (outputs e < DB nr)
+        // hat E y and hat G y for all rhs on the matrix cores
+        const int li = lane_s & 15, lk = lane_s >> 4;
+        constexpr int TB = DB / 16;
+        dx4 accW[TB], accG1[1];
 #pragma unroll
-        for (int m = 0; m < GM; ++m) {
-            const int e = lane_s + m * NTL;
-            if (e < ng * nr) {
-                const int q = e / nr, j = e - q * nr;
-                double s = 0.0;
+        for (int rt = 0; rt < TB; ++rt) accW[rt] = dx4{0.0, 0.0, 0.0, 0.0};
+        accG1[0] = dx4{0.0, 0.0, 0.0, 0.0};
+        if (hasN) mm_rhs<TB, DB, false>(stE, PD, L.Y, nr, accW, li, lk);
+        if (ng) mm_rhs<1, DB, false>(stG, PD, L.Y, nr, accG1, li, lk);
+        wave_sync();
+        if (li < nr) {
+            if (hasN) {
 #pragma unroll
-                for (int k = 0; k < DB; ++k) s = fma((k < b) ? stG[q * PD + k] : 0.0, L.Y[k * nr + j], s);
-                L.XG[e] -= s;
+                for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) L.XN[(16 * rt + 4 * v + lk) * nr + li] = accW[rt][v];
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int q = 4 * v + lk;
+                if (q < ng) L.XG[q * nr + li] -= accG1[0][v];
             }
         }
+        wave_sync();
+        // w_{i+1} = r_{i+1} - hat E y (r_{i+1} is in flight in pf.y)
         if (hasN) {
 #pragma unroll
             for (int m = 0; m < MY; ++m) {
                 const int e = lane_s + m * NTL;
-                if (e < DB * nr) {
-                    const int rr = e / nr, j = e - rr * nr;
-                    double s = 0.0;
-#pragma unroll
-                    for (int k = 0; k < DB; ++k)
-                        s = fma((rr < b && k < b) ? stE[(rr < b ? rr : 0) * PD + k] : 0.0, L.Y[k * nr + j], s);
-                    L.W[e] = (rr < b) ? pf.y[m] - s : 0.0;
-                }
+                if (e < DB * nr) L.W[e] = (e < b * nr) ? pf.y[m] - L.XN[e] : 0.0;
             }
         }
     }
@@ -581,6 +620,8 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
         L.XN[e] = 0.0;
         if (ADJ) L.PN[e] = 0.0;
     }
+    // the staging area outside the b x b (ng x b) blocks stays zero for the products
+    for (int e = lane; e < (2 * DB + NGM) * PD; e += NTL) L.P[e] = 0.0;
     BwdStage<DB> pf;
     pf.template fetch<ADJ>(a, sd, N - 1, lane);
     for (int i = N - 1; i >= 0; --i) {
@@ -601,25 +642,26 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
             dcol[l] = (cv && l < b) ? v : (l == c ? 1.0 : 0.0);
         }
         const double dinv = cv ? 1.0 / stD[c * PD + c] : 1.0;
+        {
+            // hat E^T x_{i+1} + hat G^T x_g for all rhs on the matrix cores, into Y
+            const int li = lane_s & 15, lk = lane_s >> 4;
+            constexpr int TB = DB / 16;
+            dx4 accT[TB];
+#pragma unroll
+            for (int rt = 0; rt < TB; ++rt) accT[rt] = dx4{0.0, 0.0, 0.0, 0.0};
+            if (hasE) mm_rhs<TB, DB, true>(stE, PD, L.XN, nr, accT, li, lk);
+            if (ng) mm_rhs<TB, NGM, true>(stG, PD, L.XG, nr, accT, li, lk);
+            if (li < nr) {
+#pragma unroll
+                for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) L.Y[(16 * rt + 4 * v + lk) * nr + li] = accT[rt][v];
+            }
+        }
+        wave_sync();
         for (int j = 0; j < nr; ++j) {
-            double acc0 = cv ? L.XC[c * nr + j] : 0.0, acc1 = 0.0;
-            if (hasE) {
-#pragma unroll
-                for (int r = 0; r < DB; r += 2) {
-                    const double e0 = stE[r * PD + (cv ? c : 0)], e1 = stE[(r + 1) * PD + (cv ? c : 0)];
-                    acc0 = fma((cv && r < b) ? -e0 : 0.0, L.XN[r * nr + j], acc0);
-                    acc1 = fma((cv && r + 1 < b) ? -e1 : 0.0, L.XN[(r + 1) * nr + j], acc1);
-                }
-            }
-            if (ng) {
-#pragma unroll
-                for (int q = 0; q < NGM; q += 2) {
-                    const double g0 = stG[q * PD + (cv ? c : 0)], g1 = stG[(q + 1) * PD + (cv ? c : 0)];
-                    acc0 = fma((cv && q < ng) ? -g0 : 0.0, L.XG[q * nr + j], acc0);
-                    acc1 = fma((cv && q + 1 < ng) ? -g1 : 0.0, L.XG[(q + 1) * nr + j], acc1);
-                }
-            }
-            const double xv = back_subst<DB>(dcol, acc0 + acc1, dinv);
+            const double acc = cv ? L.XC[c * nr + j] - L.Y[c * nr + j] : 0.0;
+            const double xv = back_subst<DB>(dcol, acc, dinv);
             wave_sync();
             if (cv) {
                 X[((long long)i * b + c) * nr + j] = xv;
