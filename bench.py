@@ -107,18 +107,20 @@ def measured_traffic(bp, p, S):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def is_dense(cls):
-    """A launch class of whole (p = 1) systems run by the single-wave dense sweep."""
-    return cls[0] >= 16 and cls[2] == 64
+KIND_GENERAL, KIND_DENSE, KIND_DSEG = 0, 1, 2
 
 
-def in_class(cls, b, p):
+def in_class(bp, kind, b, p):
     """Whether a system of block size b split into p segments belongs to a launch class."""
-    if class_of(b) != cls[0]:
+    if class_of(b) != bp:
         return False
-    if cls[0] < 16:
+    if bp < 16:
         return True
-    return (p == 1) == is_dense(cls)
+    return (p == 1) == (kind == KIND_DENSE)
+
+
+def class_label(bp, kind):
+    return {KIND_DENSE: "dense%d", KIND_DSEG: "dseg%d"}.get(kind, "%d") % bp
 
 
 def class_of(b):
@@ -260,6 +262,7 @@ def main():
     info = torch.zeros(S, dtype=torch.int32, device=dev)
     x = torch.empty_like(dp["r"])
     classes = plan.classes()
+    kinds = plan.class_kinds()
     log("plan: %d items, classes %s, workspace %.2f GB" % (plan.info.num_items, classes,
         plan.info.workspace_bytes / 1e9))
 
@@ -349,15 +352,19 @@ def main():
     # roofline of the dominant class kernel
     bytes_sys = alg_bytes(plan, systems)
     dom = int(np.argmax(cls_ms))
-    dom_bp, dom_dense = classes[dom][0], is_dense(classes[dom])
+    dom_bp, dom_kind = classes[dom][0], kinds[dom]
+    dom_dense = dom_kind == KIND_DENSE
+    dom_db = 16 if dom_bp <= 16 else 32
     dom_bytes = float(sum(bytes_sys[s] for s, sy in enumerate(systems)
-                          if in_class(classes[dom], sy.b, plan.layouts[s].p)))
+                          if in_class(dom_bp, dom_kind, sy.b, plan.layouts[s].p)))
     achieved = dom_bytes / (cls_ms[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": measured_traffic(("d%d" if dom_dense else "%d") % dom_bp, args.p, S),
-                "kernel": ("kkt_dense<%d, factor_solve>" % (16 if dom_bp <= 16 else 32)) if dom_dense
-                          else "kkt_persistent<%d, factor_solve>" % dom_bp,
+                "kernel": {KIND_DENSE: "kkt_dense<%d, factor_solve> + kkt_dense_bwd<%d>" % (dom_db, dom_db),
+                           KIND_DSEG: "kkt_dense_seg<%d> + kkt_reduced<%d> + kkt_dense_seg_bwd<%d>"
+                                      % (dom_db, dom_bp, dom_db)}.get(
+                               dom_kind, "kkt_persistent<%d, factor_solve>" % dom_bp),
                 "kernel_ms": round(float(cls_ms[dom]), 4), "alg_bytes": dom_bytes}
 
     # plain single-system path: one call (one launch) per system, on a sample
@@ -476,7 +483,7 @@ def main():
         "graph_ms_per_step": None if graph_ms is None else round(graph_ms, 4),
         "max_rel_residual": worst,
         "sampled_parity_vs_oracle": par,
-        "per_class_kernel_ms": {("dense%d" if is_dense(classes[c]) else "%d") % classes[c][0]: round(float(cls_ms[c]), 4)
+        "per_class_kernel_ms": {class_label(classes[c][0], kinds[c]): round(float(cls_ms[c]), 4)
                                 for c in range(len(classes))},
         "differentiation": diff,
         "single_system": single,

@@ -185,11 +185,21 @@ int kkt_plan_set_spin_limit(kkt_plan *plan, int32_t limit);
  * of work items, threads per workgroup and LDS bytes of its factor-mode launch,
  * and the largest number of resident workgroups launched so far (0 before the
  * first call).  Systems are grouped by padded block size (8, 16, 24, 32); in the
- * 16, 24 and 32 groups the unsegmented systems (p = 1) form a class of their own
- * whose factor-mode launch runs one 64-lane wave per system (a dense stage sweep
- * on the FP64 matrix cores). */
+ * 16, 24 and 32 groups the unsegmented systems (p = 1) and the segmented ones
+ * form two classes, both run with one 64-lane wave per work item (dense stage
+ * sweeps on the FP64 matrix cores); see kkt_plan_class_kind. */
 int kkt_plan_class_info(const kkt_plan *plan, int32_t c, int32_t *block_pad, int32_t *num_items,
                         int32_t *threads, int64_t *lds_bytes, int32_t *grid);
+
+/* Kind of launch class c: the general persistent kernel (one workgroup of
+ * 3 BP + 16 rounded-up lanes per item), whole systems on the dense single-wave
+ * sweeps, or segmented systems of the 16/24/32 groups on the dense segment sweeps
+ * (their sequential phase runs on the general kernel; in the solve-only and
+ * adjoint modes the whole class runs on the general kernel). */
+#define KKT_CLASS_GENERAL          0
+#define KKT_CLASS_DENSE            1
+#define KKT_CLASS_DENSE_SEGMENTED  2
+int kkt_plan_class_kind(const kkt_plan *plan, int32_t c, int32_t *kind);
 
 /* Record start / stop on the caller's stream around the persistent launch of
  * class c in every later call (NULL, NULL turns it off).  For measurement: the

@@ -391,6 +391,78 @@ __global__ void __launch_bounds__(64, 2) kkt_dense_bwd(Args a)
     }
 }
 
+// Segmented systems of the 16-, 24- and 32-wide classes, factor modes: (1) every
+// segment's factor (+ forward) sweep, one wave per segment (Algorithm 1/2
+// parallel phase); (2) kkt_reduced: each system's reduced chain and corner
+// (sequential phase); (3) every segment's backward sweep (Algorithm 3 parallel
+// phase).  Three launches on one stream: each launch boundary is the
+// synchronisation between the phases.
+template <int DB, bool FWD>
+__global__ void __launch_bounds__(64, DB == 16 ? 2 : 1) kkt_dense_seg(Args a)
+{
+    extern __shared__ double lds_raw[];
+    const Lds L = make_lds_dense(lds_raw, DB, a.nr, true);
+    int *sh = L.misc;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) sh[0] = atomicAdd(&a.ctr[0], 1);
+        __syncthreads();
+        const int it = sh[0];
+        __syncthreads();
+        if (it >= a.n_items) break;
+        const int2 w = a.items[it];
+        const SysDesc sd = a.sys[w.x];
+        const int f = dense_factor<DB, FWD, true>(a, sd, L, w.y);
+        if (tid == 0 && f) atomicMin(&a.failidx[w.x], f);
+        __syncthreads();
+    }
+}
+
+template <int BP, int MODE>
+__global__ void __launch_bounds__(K<BP>::NT) kkt_reduced(Args a)
+{
+    extern __shared__ double lds_raw[];
+    const Lds L = make_lds(lds_raw, BP, a.nr);
+    int *sh = L.misc;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) sh[0] = atomicAdd(&a.ctr[1], 1);
+        __syncthreads();
+        const int it = sh[0];
+        __syncthreads();
+        if (it >= a.n_red) break;
+        const int s = a.red[it];
+        const SysDesc sd = a.sys[s];
+        phase2<BP, MODE>(a, sd, s, L);
+    }
+}
+
+template <int DB>
+__global__ void __launch_bounds__(64, DB == 16 ? 2 : 1) kkt_dense_seg_bwd(Args a)
+{
+    extern __shared__ double lds_raw[];
+    const Lds L = make_lds_dense(lds_raw, DB, a.nr, true);
+    int *sh = L.misc;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) sh[0] = atomicAdd(&a.ctr[2], 1);
+        __syncthreads();
+        const int it = sh[0];
+        __syncthreads();
+        if (it >= a.n_items) break;
+        const int2 w = a.items[it];
+        const SysDesc sd = a.sys[w.x];
+        dense_backward<DB, false, true>(a, sd, L, w.y);
+        if (tid == 0) sh[2] = load_status(&a.status[w.x]);
+        __syncthreads();
+        if (sh[2] != 0) {
+            const int f0 = seg_first(sd, w.y);
+            fill_nan<64>(a, sd, f0, f0 + seg_len(sd, w.y), false);
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void kkt_reset(int *ctr, int nctr, int *arrive, int *failidx, int S, int *ready, int nready,
                           int *info)
 {
@@ -442,6 +514,22 @@ kfun_t dense_kernel_for(int mode)
 kfun_t dense_kernel_for(int bp, int mode)
 {
     return bp <= 16 ? dense_kernel_for<16>(mode) : dense_kernel_for<32>(mode);
+}
+
+kfun_t dseg_kernel_for(int bp, int mode, int l)
+{
+    const bool w16 = bp <= 16;
+    if (l == 0) {
+        if (mode == M_FACTOR) return w16 ? kkt_dense_seg<16, false> : kkt_dense_seg<32, false>;
+        return w16 ? kkt_dense_seg<16, true> : kkt_dense_seg<32, true>;
+    }
+    if (l == 2) return w16 ? kkt_dense_seg_bwd<16> : kkt_dense_seg_bwd<32>;
+    const bool fs = mode == M_FACTOR_SOLVE;
+    switch (bp) {
+    case 16: return fs ? kkt_reduced<16, M_FACTOR_SOLVE> : kkt_reduced<16, M_FACTOR>;
+    case 24: return fs ? kkt_reduced<24, M_FACTOR_SOLVE> : kkt_reduced<24, M_FACTOR>;
+    default: return fs ? kkt_reduced<32, M_FACTOR_SOLVE> : kkt_reduced<32, M_FACTOR>;
+    }
 }
 
 kfun_t dense_bwd_kernel_for(int bp, int mode)
@@ -604,13 +692,16 @@ struct kkt_plan {
         int cls = 0, bp = 0, nt = 0;
         int item_off = 0, item_cnt = 0, s3_off = 0, s3_cnt = 0;
         size_t lds = 0;
-        bool dense = false;       // whole (p = 1) systems, dense sweep in the factor modes
-        size_t lds_dense = 0;     // LDS of the dense launch
+        bool dense = false;       // whole (p = 1) systems: dense single-wave sweeps
+        bool dseg = false;        // segmented systems of the 16/24/32 classes: dense segment sweeps
+        size_t lds_dense = 0;     // LDS of the dense launches
+        int red_off = 0, red_cnt = 0;   // dseg: systems (sequential phase)
     };
     std::vector<Cls> cls;
     std::vector<int2> items;
+    std::vector<int> red;
     size_t o_ctr = 0, o_sys = 0, o_items = 0, o_slot = 0, o_ready = 0, o_arrive = 0, o_fail = 0,
-           o_status = 0, o_tag = 0, o_F = 0, bytes = 0;
+           o_status = 0, o_tag = 0, o_F = 0, o_red = 0, bytes = 0;
     long long nF = 0;
     kkt_plan_info info{};
     int spin_limit = 1 << 22;
@@ -628,7 +719,7 @@ struct kkt_plan {
     // launch configuration per (class, mode), filled on first use so that later
     // calls (and graph capture) make no device queries
     static constexpr int MAXC = 8;
-    mutable int grid[MAXC][6] = {{0}};   // per mode; [4], [5]: backward launch of a dense class
+    mutable int grid[MAXC][12] = {{0}};   // per (mode, launch of the class)
     // optional per-class timing events (kkt_plan_set_class_events)
     hipEvent_t ev_start[MAXC] = {nullptr};
     hipEvent_t ev_stop[MAXC] = {nullptr};
@@ -721,16 +812,36 @@ int launch_mode(const kkt_plan *plan, int mode, const Args &base, hipStream_t st
         a.s3_ready = base.s3_ready + c.s3_off;
         a.n_s3 = c.s3_cnt;
         a.ctr = base.ctr + 4 * ci;
-        const bool dense = c.dense;
-        const int nt = dense ? 64 : c.nt;
-        const size_t lds = dense ? c.lds_dense : c.lds;
-        // a dense class with a backward sweep takes a second launch (kkt_dense_bwd)
-        const int nlaunch = (dense && mode != M_FACTOR) ? 2 : 1;
+        // launches of this class: a dense class runs its (factor or forward) sweep and
+        // then its backward sweep; a segmented dense class in the factor modes runs the
+        // segment sweeps, the sequential phase (general kernel) and the segment
+        // backward sweeps; everything else is one general persistent launch
+        const bool dseg = c.dseg && mode <= M_FACTOR_SOLVE;
+        const int nlaunch = c.dense ? (mode != M_FACTOR ? 2 : 1) : dseg ? (mode == M_FACTOR ? 2 : 3) : 1;
+        if (dseg) {
+            a.red = base.red + c.red_off;
+            a.n_red = c.red_cnt;
+        }
         if (plan->ev_start[ci] && hipEventRecord(plan->ev_start[ci], st) != hipSuccess) return KKT_ELAUNCH;
         for (int l = 0; l < nlaunch; ++l) {
-            kfun_t fn = !dense ? kernel_for_class(c.cls, mode)
-                               : (l == 0 ? dense_kernel_for(c.bp, mode) : dense_bwd_kernel_for(c.bp, mode));
-            int &grid = plan->grid[ci][l == 0 ? mode : 4 + (mode == M_ADJOINT)];
+            kfun_t fn;
+            int nt = 64, work = c.item_cnt;
+            size_t lds = c.lds_dense;
+            if (c.dense) {
+                fn = l == 0 ? dense_kernel_for(c.bp, mode) : dense_bwd_kernel_for(c.bp, mode);
+            } else if (dseg) {
+                fn = dseg_kernel_for(c.bp, mode, l);
+                if (l == 1) {
+                    nt = c.nt;
+                    lds = c.lds;
+                    work = c.red_cnt;
+                }
+            } else {
+                fn = kernel_for_class(c.cls, mode);
+                nt = c.nt;
+                lds = c.lds;
+            }
+            int &grid = plan->grid[ci][mode * 3 + l];
             if (grid == 0) {
                 int dev = 0, ncu = 0, occ = 0;
                 if (hipGetDevice(&dev) != hipSuccess) return KKT_ELAUNCH;
@@ -743,7 +854,7 @@ int launch_mode(const kkt_plan *plan, int mode, const Args &base, hipStream_t st
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, nt, lds) != hipSuccess ||
                     occ < 1)
                     occ = 1;
-                grid = std::max(1, std::min(c.item_cnt, occ * ncu));
+                grid = std::max(1, std::min(work, occ * ncu));
             }
             hipLaunchKernelGGL(fn, dim3(grid), dim3(nt), lds, st, a);
             if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
@@ -764,6 +875,7 @@ Args base_args(const kkt_plan *plan, void *workspace)
     a.F = (double *)(ws + plan->o_F);
     a.sys = (const SysDesc *)(ws + plan->o_sys);
     a.items = (const int2 *)(ws + plan->o_items);
+    a.red = (const int *)(ws + plan->o_red);
     a.s3_slot = (int2 *)(ws + plan->o_slot);
     a.s3_ready = (int *)(ws + plan->o_ready);
     a.ctr = (int *)(ws + plan->o_ctr);
@@ -902,7 +1014,15 @@ int kkt_plan_create_tuned(kkt_plan **out, int32_t S, const kkt_dims *dims_in, in
         C.s3_cnt = s3;
         C.lds = (size_t)lds_offsets(C.bp, nrhs).total * sizeof(double);
         C.dense = dense;
+        C.dseg = !dense && CLS_BP[c] >= 16;
         if (dense) C.lds_dense = (size_t)lds_offsets_dense(dense_width(C.bp), nrhs).total * sizeof(double);
+        if (C.dseg) {
+            C.lds_dense = (size_t)lds_offsets_dense(dense_width(C.bp), nrhs, true).total * sizeof(double);
+            C.red_off = (int)P->red.size();
+            for (int s = 0; s < S; ++s)
+                if (cls_of[s] == c && P->sys[s].p > 1) P->red.push_back(s);
+            C.red_cnt = (int)P->red.size() - C.red_off;
+        }
         for (auto &x : its) P->items.push_back(x.second);
         nitems += C.item_cnt;
         ns3 += s3;
@@ -914,6 +1034,7 @@ int kkt_plan_create_tuned(kkt_plan **out, int32_t S, const kkt_dims *dims_in, in
     P->o_ctr = o; o = align256(o + sizeof(int) * 4 * P->cls.size());
     P->o_sys = o; o = align256(o + sizeof(SysDesc) * S);
     P->o_items = o; o = align256(o + sizeof(int2) * std::max(1, nitems));
+    P->o_red = o; o = align256(o + sizeof(int) * std::max<size_t>(1, P->red.size()));
     P->o_slot = o; o = align256(o + sizeof(int2) * std::max(1, ns3));
     P->o_ready = o; o = align256(o + sizeof(int) * std::max(1, std::max(ns3, nitems)));
     P->o_arrive = o; o = align256(o + sizeof(int) * S);
@@ -969,6 +1090,10 @@ int kkt_workspace_init(const kkt_plan *plan, void *workspace, hipStream_t stream
         return KKT_ELAUNCH;
     if (!plan->items.empty() &&
         hipMemcpyAsync(ws + plan->o_items, plan->items.data(), sizeof(int2) * plan->items.size(), hipMemcpyHostToDevice,
+                       stream) != hipSuccess)
+        return KKT_ELAUNCH;
+    if (!plan->red.empty() &&
+        hipMemcpyAsync(ws + plan->o_red, plan->red.data(), sizeof(int) * plan->red.size(), hipMemcpyHostToDevice,
                        stream) != hipSuccess)
         return KKT_ELAUNCH;
     std::vector<int> st(plan->S, 0);
@@ -1075,8 +1200,17 @@ int kkt_plan_class_info(const kkt_plan *plan, int32_t c, int32_t *block_pad, int
     const kkt_plan::Cls &C = plan->cls[c];
     if (block_pad) *block_pad = C.bp;
     if (num_items) *num_items = C.item_cnt;
-    if (threads) *threads = C.dense ? 64 : C.nt;
-    if (lds_bytes) *lds_bytes = (int64_t)(C.dense ? C.lds_dense : C.lds);
+    if (threads) *threads = (C.dense || C.dseg) ? 64 : C.nt;
+    if (lds_bytes) *lds_bytes = (int64_t)((C.dense || C.dseg) ? C.lds_dense : C.lds);
+    return KKT_OK;
+}
+
+int kkt_plan_class_kind(const kkt_plan *plan, int32_t c, int32_t *kind)
+{
+    if (!plan || !kind) return KKT_EPOINTER;
+    if (c < 0 || c >= (int)plan->cls.size()) return KKT_EDIMS;
+    const kkt_plan::Cls &C = plan->cls[c];
+    *kind = C.dense ? KKT_CLASS_DENSE : C.dseg ? KKT_CLASS_DENSE_SEGMENTED : KKT_CLASS_GENERAL;
     return KKT_OK;
 }
 

@@ -72,19 +72,19 @@ __device__ __forceinline__ void mm_rhs(const double *A, int pa, const double *B,
 // backward sweep and the corner reuse it as their staging area), then the same
 // small vectors as the general layout.  Regions the p = 1 path never touches
 // (fill-row accumulators) alias the panel area.
-__host__ __device__ __forceinline__ LdsOff lds_offsets_dense(int DB, int nr)
+__host__ __device__ __forceinline__ LdsOff lds_offsets_dense(int DB, int nr, bool seg = false)
 {
     LdsOff o;
     const int PITCH = DB + 1;
     int t = 0;
     o.col = t; t += 2 * (DB > NGM ? DB : NGM) + 64;   // + one dummy slot per lane
-    o.P = t;   t += (2 * DB + NGM) * PITCH;
+    o.P = t;   t += (seg ? 4 * DB + 2 * NGM : 2 * DB + NGM) * PITCH;   // segments: + fill rows, hat A, hat Q
     o.A = o.P; o.Q = o.P; o.RP = o.P;
     o.R = t;   t += NGM * NGM;
     o.W = t;   t += (DB > NGM ? DB : NGM) * nr;
     o.Y = t;   t += (DB > NGM ? DB : NGM) * nr;
     o.XN = t;  t += DB * nr;
-    o.XS = t;  t += 0;
+    o.XS = t;  t += seg ? DB * nr : 0;
     o.XC = t;  t += DB * nr;
     o.XG = t;  t += NGM * nr;
     o.PN = t;  t += DB * nr;
@@ -96,9 +96,9 @@ __host__ __device__ __forceinline__ LdsOff lds_offsets_dense(int DB, int nr)
     return o;
 }
 
-__device__ __forceinline__ Lds make_lds_dense(double *base, int DB, int nr)
+__device__ __forceinline__ Lds make_lds_dense(double *base, int DB, int nr, bool seg = false)
 {
-    const LdsOff o = lds_offsets_dense(DB, nr);
+    const LdsOff o = lds_offsets_dense(DB, nr, seg);
     Lds L;
     L.col = base + o.col; L.P = base + o.P; L.A = base + o.A; L.Q = base + o.Q; L.R = base + o.R;
     L.W = base + o.W; L.Y = base + o.Y; L.RP = base + o.RP; L.XN = base + o.XN; L.XS = base + o.XS;
@@ -107,13 +107,18 @@ __device__ __forceinline__ Lds make_lds_dense(double *base, int DB, int nr)
     return L;
 }
 
-// Factor (and with FWD forward-substitute) a whole system with one wave.  Writes
-// the factor blocks, y in place of the rhs, and the arrow partials (-sum hat G
-// hat G^T, -sum hat G y) to the scratch of segment 1, exactly as the general
-// sweep does for p = 1.  Returns the 1-based index of the first stage whose pivot
-// is not positive and finite, 0 if none.
-template <int DB, bool FWD>
-__device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, const Lds &L)
+// Factor (and with FWD forward-substitute) one chain with one wave: a whole
+// system (SEG = false), or segment k of a segmented system (SEG = true; Algorithm 1
+// parallel phase with the fill rows of k >= 2).  Writes the factor blocks, y in
+// place of the rhs and, for segment k, the partials the sequential phase reads:
+// hat A_k, hat Q_k and the separator rhs (k >= 2) in the separator's slots, and in
+// the scratch of segment k the arrow partials (-sum hat G hat G^T, -sum hat G y)
+// and, when the segment ends on a coupling block hat F_k (k < p), hat F_k hat F_k^T,
+// hat G hat F_k^T, -hat F_k y and tilde H_k = -hat F_k hat B^T (Eqs. 8a-8c, 9b-9d).
+// Returns the 1-based natural index of the first stage whose pivot is not
+// positive and finite, 0 if none.
+template <int DB, bool FWD, bool SEG = false>
+__device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, const Lds &L, int k = 1)
 {
     constexpr int PD = DB + 1, TB = DB / 16, KS = DB / 4, NTL = 64;
     static_assert(DB == 16 || DB == 32, "dense sweep tiles are 16 or 32 wide");
@@ -124,31 +129,63 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
     double *RA = L.P;                 // Dw -> L (store staging) -> hat E -> next Dw
     double *RB = L.P + DB * PD;       // L^{-1}
     double *RG = L.P + 2 * DB * PD;   // Gw -> hat G -> next Gw (16 rows)
+    double *RF = RG + NGM * PD;       // SEG, k >= 2: fill rows Fw -> hat B^T -> next Fw
+    double *RAA = RF + DB * PD;       //              hat A_k accumulator
+    double *RQ = RAA + DB * PD;       //              hat Q_k accumulator (16 rows)
     double *buf0 = L.col, *buf1 = L.col + DB;
+    const int s0 = SEG ? seg_first(sd, k) : 0;
+    const int len = SEG ? seg_len(sd, k) : N;
+    const bool hasF = SEG && k > 1;
+    const int sep = hasF ? sep_of(sd, k) : 0;
+    double *sc = F + sd.oScr + (long long)(k - 1) * sd.scrStride;
 
-    // ---- prologue: Dw = sym(D_0), Gw = B_0, w = r_0, y_g partial = 0
+    // ---- prologue: Dw = sym(D_s0), Gw = B_s0, w = r_s0, y_g partial = 0; for k >= 2
+    // hat A_k = sym(D_sep), hat Q_k = B_sep, Fw = C_sep^T, separator rhs = r_sep
     {
-        const double *D0 = a.D + sd.oD;
+        const double *D0 = a.D + sd.oD + (long long)s0 * b2;
         for (int e = lane; e < DB * DB; e += NTL) {
             const int r = e / DB, c = e - r * DB;
             RA[r * PD + c] = (r < b && c < b) ? 0.5 * (D0[r * b + c] + D0[c * b + r]) : (r == c ? 1.0 : 0.0);
         }
-        const double *B0 = a.B + sd.oB;
+        const double *B0 = a.B + sd.oB + (long long)s0 * ng * b;
         for (int e = lane; e < NGM * DB; e += NTL) {
             const int q = e / DB, c = e - q * DB;
             RG[q * PD + c] = (q < ng && c < b) ? B0[q * b + c] : 0.0;
         }
         if (FWD) {
-            for (int e = lane; e < DB * nr; e += NTL) L.W[e] = (e < b * nr) ? a.rhs[sd.oRhs + e] : 0.0;
+            const double *r0 = a.rhs + sd.oRhs + (long long)s0 * b * nr;
+            for (int e = lane; e < DB * nr; e += NTL) L.W[e] = (e < b * nr) ? r0[e] : 0.0;
             for (int e = lane; e < NGM * nr; e += NTL) L.XG[e] = 0.0;
+        }
+        if (hasF) {
+            const double *Ds = a.D + sd.oD + (long long)sep * b2, *Cs = a.C + sd.oC + (long long)sep * b2;
+            const double *Bs = a.B + sd.oB + (long long)sep * ng * b;
+            for (int e = lane; e < DB * DB; e += NTL) {
+                const int r = e / DB, c = e - r * DB;
+                const bool in = r < b && c < b;
+                RAA[r * PD + c] = in ? 0.5 * (Ds[r * b + c] + Ds[c * b + r]) : 0.0;
+                RF[r * PD + c] = in ? Cs[c * b + r] : 0.0;
+            }
+            for (int e = lane; e < NGM * DB; e += NTL) {
+                const int q = e / DB, c = e - q * DB;
+                RQ[q * PD + c] = (q < ng && c < b) ? Bs[q * b + c] : 0.0;
+            }
+            if (FWD) {
+                const double *rs = a.rhs + sd.oRhs + (long long)sep * b * nr;
+                for (int e = lane; e < DB * nr; e += NTL) L.XS[e] = (e < b * nr) ? rs[e] : 0.0;
+            }
         }
     }
     wave_sync();
 
     dx4 accR = {0.0, 0.0, 0.0, 0.0};
     int failed = 0;
-    for (int i = 0; i < N; ++i) {
-        const bool hasN = i + 1 < N;
+    for (int i = 0; i < len; ++i) {
+        const int gs = s0 + i;
+        const bool hasN = gs + 1 < N;
+        // segment k < p ends on the coupling block hat F_k to the next separator
+        const bool endS = SEG && i == len - 1 && hasN;
+        const bool nextD = hasN && !endS;   // the chain continues with a diagonal block
         // lane-derived indices and masks are re-derived every stage: hoisting the
         // unrolled per-element addresses and predicates out of the stage loop would
         // keep hundreds of them live across it
@@ -162,17 +199,17 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         // ---- (0) r_{i+1} and C_i (MFMA operand layout), in flight during the factorization
         double rn[TB][4];   // r_{i+1} in product layout (row 16 rt + 4 v + lk, rhs li)
         if (FWD) {
-            const double *rs = a.rhs + sd.oRhs + (long long)(i + 1) * b * nr;
+            const double *rs = a.rhs + sd.oRhs + (long long)(gs + 1) * b * nr;
 #pragma unroll
             for (int rt = 0; rt < TB; ++rt)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * rt + 4 * v + lk;
-                    rn[rt][v] = (hasN && r < b && li < nr) ? rs[r * nr + li] : 0.0;
+                    rn[rt][v] = (nextD && r < b && li < nr) ? rs[r * nr + li] : 0.0;
                 }
         }
         double cA[TB][KS];
-        const double *Ci = a.C + sd.oC + (long long)i * b2;
+        const double *Ci = a.C + sd.oC + (long long)gs * b2;
 #pragma unroll
         for (int rt = 0; rt < TB; ++rt)
 #pragma unroll
@@ -227,7 +264,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             pin_row<DB>(vec);
             wave_sync();
         }
-        if (bad && !failed) failed = i + 1;
+        if (bad && !failed) failed = gs + 1;
 
         phase_fence();
         // ---- (2) L rows and L^{-1} columns into LDS; store L
@@ -239,11 +276,11 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             for (int r = 0; r < DB; ++r) RB[r * PD + ri] = (r >= ri) ? vec[r] : 0.0;
         }
         wave_sync();
-        store_block<NTL, DB * DB>(F + sd.oLd + (long long)i * b2, RA, PD, b, b);
+        store_block<NTL, DB * DB>(F + sd.oLd + (long long)gs * b2, RA, PD, b, b);
         wave_sync();
 
         phase_fence();
-        // ---- (3) hat E = C L^{-T}, hat G = Gw L^{-T}
+        // ---- (3) hat E = C L^{-T}, hat G = Gw L^{-T} (and hat B^T = Fw L^{-T})
         dx4 accE[TB][TB], accG[TB];
 #pragma unroll
         for (int ct = 0; ct < TB; ++ct) {
@@ -281,15 +318,43 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                 RG[(4 * v + lk) * PD + c] = accG[ct][v];
             }
         wave_sync();
-        if (hasN) store_block<NTL, DB * DB>(F + sd.oLc + (long long)i * b2, RA, PD, b, b);
-        if (ng) store_block<NTL, NGM * DB>(F + sd.oLb + (long long)i * ng * b, RG, PD, ng, b);
+        if (hasN) store_block<NTL, DB * DB>(F + sd.oLc + (long long)gs * b2, RA, PD, b, b);
+        if (ng) store_block<NTL, NGM * DB>(F + sd.oLb + (long long)gs * ng * b, RG, PD, ng, b);
+        if (SEG && hasF) {
+            dx4 accF[TB][TB];
+#pragma unroll
+            for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < TB; ++ct) accF[rt][ct] = dx4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+                for (int ct = 0; ct < TB; ++ct) {
+                    const double bo = RB[(16 * ct + li) * PD + 4 * kk + lk];
+#pragma unroll
+                    for (int rt = 0; rt < TB; ++rt)
+                        accF[rt][ct] = mfma4(RF[(16 * rt + li) * PD + 4 * kk + lk], bo, accF[rt][ct]);
+                }
+            wave_sync();
+#pragma unroll
+            for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < TB; ++ct)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) RF[(16 * rt + 4 * v + lk) * PD + 16 * ct + li] = accF[rt][ct][v];
+            wave_sync();
+            // the first fill block sits in the coupling slot of the separator
+            double *dst = (i == 0) ? F + sd.oLc + (long long)sep * b2
+                                   : F + sd.oFill + ((long long)(k - 2) * (sd.Nk - 1) + (i - 1)) * b2;
+            store_block<NTL, DB * DB>(dst, RF, PD, b, b);
+        }
 
         phase_fence();
         // ---- next stage's blocks, in flight during the forward substitution
         // lower tiles (rt >= ct) of sym(D_{i+1}) in accumulator layout
         constexpr int NLT = TB * (TB + 1) / 2;
         double dn[NLT][4], dt[NLT][4];
-        const double *Dn = a.D + sd.oD + (long long)(i + 1) * b2;
+        const double *Dn = a.D + sd.oD + (long long)(gs + 1) * b2;
 #pragma unroll
         for (int rt = 0, t = 0; rt < TB; ++rt)
 #pragma unroll
@@ -297,23 +362,24 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * rt + 4 * v + lk, c = 16 * ct + li;
-                    const bool in = hasN && r < b && c < b;
+                    const bool in = nextD && r < b && c < b;
                     dn[t][v] = in ? Dn[r * b + c] : 0.0;
                     dt[t][v] = in ? Dn[c * b + r] : 0.0;
                 }
         double bn[TB][4];
-        const double *Bn = a.B + sd.oB + (long long)(i + 1) * ng * b;
+        const double *Bn = a.B + sd.oB + (long long)(gs + 1) * ng * b;
 #pragma unroll
         for (int ct = 0; ct < TB; ++ct)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int q = 4 * v + lk, c = 16 * ct + li;
-                bn[ct][v] = (hasN && q < ng && c < b) ? Bn[q * b + c] : 0.0;
+                bn[ct][v] = (nextD && q < ng && c < b) ? Bn[q * b + c] : 0.0;
             }
-
 
         phase_fence();
         // ---- (4) forward substitution: y = L^{-1} w, w' = r_{i+1} - hat E y, y_g -= hat G y
+        // (at a segment end the scratch gets -hat F_k y instead of w'; with fill rows
+        // the separator rhs -= hat B^T y)
         if (FWD) {
             // y = L^{-1} w, then hat E y and hat G y, all rhs at once on the matrix cores
             dx4 accY[TB];
@@ -327,16 +393,20 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                     for (int v = 0; v < 4; ++v) {
                         const int r = 16 * rt + 4 * v + lk;
                         L.Y[r * nr + li] = accY[rt][v];
-                        if (r < b) a.rhs[sd.oRhs + ((long long)i * b + r) * nr + li] = accY[rt][v];
+                        if (r < b) a.rhs[sd.oRhs + ((long long)gs * b + r) * nr + li] = accY[rt][v];
                     }
             }
             wave_sync();
-            dx4 accW[TB], accG1[1];
+            dx4 accW[TB], accG1[1], accS[TB];
 #pragma unroll
-            for (int rt = 0; rt < TB; ++rt) accW[rt] = dx4{0.0, 0.0, 0.0, 0.0};
+            for (int rt = 0; rt < TB; ++rt) {
+                accW[rt] = dx4{0.0, 0.0, 0.0, 0.0};
+                accS[rt] = dx4{0.0, 0.0, 0.0, 0.0};
+            }
             accG1[0] = dx4{0.0, 0.0, 0.0, 0.0};
             if (hasN) mm_rhs<TB, DB, false>(RA, PD, L.Y, nr, accW, li, lk);
             if (ng) mm_rhs<1, DB, false>(RG, PD, L.Y, nr, accG1, li, lk);
+            if (SEG && hasF) mm_rhs<TB, DB, false>(RF, PD, L.Y, nr, accS, li, lk);
             wave_sync();
             if (li < nr) {
 #pragma unroll
@@ -344,7 +414,12 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int r = 16 * rt + 4 * v + lk;
-                        L.W[r * nr + li] = (r < b) ? rn[rt][v] - accW[rt][v] : 0.0;
+                        if (endS) {
+                            if (r < b) sc[scr_dy(b, ng, nr) + r * nr + li] = -accW[rt][v];
+                        } else {
+                            L.W[r * nr + li] = (r < b) ? rn[rt][v] - accW[rt][v] : 0.0;
+                        }
+                        if (SEG && hasF && r < b) L.XS[r * nr + li] -= accS[rt][v];
                     }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -355,17 +430,23 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         }
 
         phase_fence();
-        // ---- (5) Gram: next Dw and Gw, arrow accumulator
-        dx4 accD[NLT], accB[TB];
+        // ---- (5) Gram: next Dw and Gw (or, at a segment end, the scratch products),
+        // arrow accumulator, fill-row products
+        dx4 accD[TB][TB], accB[TB];
 #pragma unroll
         for (int rt = 0, t = 0; rt < TB; ++rt)
 #pragma unroll
-            for (int ct = 0; ct <= rt; ++ct, ++t)
+            for (int ct = 0; ct < TB; ++ct) {
+                const int tt = ct <= rt ? t : 0;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * rt + 4 * v + lk, c = 16 * ct + li;
-                    accD[t][v] = (r < b && c < b) ? 0.5 * (dn[t][v] + dt[t][v]) : (r == c ? 1.0 : 0.0);
+                    accD[rt][ct][v] = (ct <= rt && !endS)
+                                          ? ((r < b && c < b) ? 0.5 * (dn[tt][v] + dt[tt][v]) : (r == c ? 1.0 : 0.0))
+                                          : 0.0;
                 }
+                if (ct <= rt) ++t;
+            }
 #pragma unroll
         for (int ct = 0; ct < TB; ++ct)
 #pragma unroll
@@ -377,9 +458,10 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
 #pragma unroll
                 for (int t = 0; t < TB; ++t) ek[t] = RA[(16 * t + li) * PD + 4 * kk + lk];
 #pragma unroll
-                for (int rt = 0, t = 0; rt < TB; ++rt)
+                for (int rt = 0; rt < TB; ++rt)
 #pragma unroll
-                    for (int ct = 0; ct <= rt; ++ct, ++t) accD[t] = mfma4(-ek[rt], ek[ct], accD[t]);
+                    for (int ct = 0; ct < TB; ++ct)
+                        if (ct <= rt || (SEG && endS)) accD[rt][ct] = mfma4(-ek[rt], ek[ct], accD[rt][ct]);
             }
         }
         if (ng) {
@@ -394,26 +476,123 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                 accR = mfma4(-gk, gk, accR);
             }
         }
+        if (SEG && hasF) {
+            // hat A_k -= hat B^T hat B, hat Q_k -= hat G hat B, next Fw = -hat B^T hat E^T,
+            // and at a segment end tilde H_k = -hat F_k hat B
+            dx4 accA[TB][TB], accQ[TB];
+#pragma unroll
+            for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < TB; ++ct)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        accA[rt][ct][v] = RAA[(16 * rt + 4 * v + lk) * PD + 16 * ct + li];
+#pragma unroll
+            for (int ct = 0; ct < TB; ++ct)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) accQ[ct][v] = RQ[(4 * v + lk) * PD + 16 * ct + li];
+#pragma unroll
+            for (int kk = 0; kk < KS; ++kk) {
+                double fk[TB];
+#pragma unroll
+                for (int t = 0; t < TB; ++t) fk[t] = RF[(16 * t + li) * PD + 4 * kk + lk];
+                const double gk = RG[li * PD + 4 * kk + lk];
+#pragma unroll
+                for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                    for (int ct = 0; ct < TB; ++ct) accA[rt][ct] = mfma4(-fk[rt], fk[ct], accA[rt][ct]);
+                if (ng) {
+#pragma unroll
+                    for (int ct = 0; ct < TB; ++ct) accQ[ct] = mfma4(-gk, fk[ct], accQ[ct]);
+                }
+            }
+            dx4 accN[TB][TB];   // -hat B^T hat E^T (next Fw), or -hat E hat B^T (tilde H_k)
+#pragma unroll
+            for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < TB; ++ct) accN[rt][ct] = dx4{0.0, 0.0, 0.0, 0.0};
+            if (hasN) {
+#pragma unroll
+                for (int kk = 0; kk < KS; ++kk) {
+                    double fk[TB], ek[TB];
+#pragma unroll
+                    for (int t = 0; t < TB; ++t) {
+                        fk[t] = RF[(16 * t + li) * PD + 4 * kk + lk];
+                        ek[t] = RA[(16 * t + li) * PD + 4 * kk + lk];
+                    }
+#pragma unroll
+                    for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                        for (int ct = 0; ct < TB; ++ct)
+                            accN[rt][ct] = endS ? mfma4(-ek[rt], fk[ct], accN[rt][ct])
+                                                : mfma4(-fk[rt], ek[ct], accN[rt][ct]);
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < TB; ++ct)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * rt + 4 * v + lk, c = 16 * ct + li;
+                        RAA[r * PD + c] = accA[rt][ct][v];
+                        if (endS) {
+                            if (r < b && c < b) F[sd.oH + (long long)(k - 2) * b2 + r * b + c] = accN[rt][ct][v];
+                        } else {
+                            RF[r * PD + c] = accN[rt][ct][v];
+                        }
+                    }
+#pragma unroll
+            for (int ct = 0; ct < TB; ++ct)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) RQ[(4 * v + lk) * PD + 16 * ct + li] = accQ[ct][v];
+        }
+        // the next stage's blocks replace hat E and hat G only now: the fill-row
+        // products above read them
         wave_sync();
-        if (hasN) {
+        if (nextD) {
 #pragma unroll
-            for (int rt = 0, t = 0; rt < TB; ++rt)
+            for (int rt = 0; rt < TB; ++rt)
 #pragma unroll
-                for (int ct = 0; ct <= rt; ++ct, ++t)
+                for (int ct = 0; ct <= rt; ++ct)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) RA[(16 * rt + 4 * v + lk) * PD + 16 * ct + li] = accD[t][v];
+                    for (int v = 0; v < 4; ++v) RA[(16 * rt + 4 * v + lk) * PD + 16 * ct + li] = accD[rt][ct][v];
 #pragma unroll
             for (int ct = 0; ct < TB; ++ct)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) RG[(4 * v + lk) * PD + 16 * ct + li] = accB[ct][v];
+        } else if (SEG && endS) {
+            // hat F_k hat F_k^T and hat G hat F_k^T (accumulated as negatives)
+#pragma unroll
+            for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < TB; ++ct)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * rt + 4 * v + lk, c = 16 * ct + li;
+                        if (r < b && c < b) sc[scr_dA(b, ng, nr) + r * b + c] = -accD[rt][ct][v];
+                    }
+#pragma unroll
+            for (int ct = 0; ct < TB; ++ct)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int q = 4 * v + lk, c = 16 * ct + li;
+                    if (q < ng && c < b) sc[scr_dQ(b, ng, nr) + q * b + c] = -accB[ct][v];
+                }
         }
         wave_sync();
     }
 
-    // ---- epilogue: arrow partials into the scratch of segment 1
+    // ---- epilogue: separator partials (k >= 2) and the arrow partials of segment k
+    if (SEG && hasF) {
+        store_block<NTL, DB * DB>(F + sd.oLd + (long long)sep * b2, RAA, PD, b, b);
+        if (ng) store_block<NTL, NGM * DB>(F + sd.oLb + (long long)sep * ng * b, RQ, PD, ng, b);
+        if (FWD)
+            for (int e = lane; e < b * nr; e += NTL) a.rhs[sd.oRhs + (long long)sep * b * nr + e] = L.XS[e];
+    }
     if (ng) {
         const int li = lane & 15, lk = lane >> 4;
-        double *sc = F + sd.oScr;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int q = 4 * v + lk;
@@ -432,7 +611,36 @@ template <int DB>
 struct BwdStage {
     static constexpr int NTL = 64, MD = DB * DB / NTL, MG = NGM * DB / NTL,
                          MY = (DB * MAX_NRHS_DEV + NTL - 1) / NTL;
-    double d[MD], e[MD], g[MG], y[MY], px[MY];
+    double d[MD], e[MD], g[MG], y[MY], px[MY], f[MD];
+
+    // fill block of stage i of segment k >= 2 (local stage il)
+    __device__ __forceinline__ void fetch_fill(const Args &a, const SysDesc &sd, int k, int il, int lane)
+    {
+        const int b = sd.b;
+        const long long b2 = (long long)b * b;
+        const double *src = (il == 0) ? a.F + sd.oLc + (long long)sep_of(sd, k) * b2
+                                      : a.F + sd.oFill + ((long long)(k - 2) * (sd.Nk - 1) + (il - 1)) * b2;
+#pragma unroll
+        for (int m = 0; m < MD; ++m) {
+            const int x = lane + m * NTL;
+            f[m] = (x < b * b) ? src[x] : 0.0;
+        }
+    }
+
+    __device__ __forceinline__ void stage_fill(const SysDesc &sd, double *stF, int lane) const
+    {
+        constexpr int PD = DB + 1;
+        const int b = sd.b;
+        const float invb = 1.0f / (float)b;
+#pragma unroll
+        for (int m = 0; m < MD; ++m) {
+            const int x = lane + m * NTL;
+            if (x < b * b) {
+                const int r = row_of(x, invb), c = x - r * b;
+                stF[r * PD + c] = f[m];
+            }
+        }
+    }
 
     // with PRIMAL, also the primal solution of stage i (adjoint gradients)
     template <bool PRIMAL = false>
@@ -597,44 +805,59 @@ __device__ __forceinline__ void dense_forward(const Args &a, const SysDesc &sd, 
     wave_sync();
 }
 
-// Backward substitution of a whole system with one wave (Algorithm 3 with p = 1):
-// x_i = L_ii^{-T} (y_i - hat E_i^T x_{i+1} - hat G_i^T x_g) for i = N-1 .. 0, with
-// the blocks of stage i - 1 in flight while stage i is solved.  x_g is in place.
-// With ADJ the solution is lambda and the gradient blocks of every stage are
-// written: dD_i = -sym(lambda_i x_i^T), dB_i = -(lambda_g x_i^T + x_g lambda_i^T),
-// dC_i = -(lambda_{i+1} x_i^T + x_{i+1} lambda_i^T), summed over the rhs columns.
-template <int DB, bool ADJ>
-__device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd, const Lds &L)
+// Backward substitution with one wave (Algorithm 3): a whole system, or (SEG)
+// segment k of a segmented system after the sequential phase has solved its
+// separators.  x_i = L_ii^{-T} (y_i - hat E_i^T x_{i+1} - hat G_i^T x_g
+// [- hat B_i x_sep]) for the chain's stages in reverse, with the blocks of the
+// next stage in flight while a stage is solved; x_g (and x at the separators) is
+// in place.  With ADJ (whole systems) the solution is lambda and the gradient
+// blocks of every stage are written: dD_i = -sym(lambda_i x_i^T),
+// dB_i = -(lambda_g x_i^T + x_g lambda_i^T), dC_i = -(lambda_{i+1} x_i^T + x_{i+1} lambda_i^T),
+// summed over the rhs columns.
+template <int DB, bool ADJ, bool SEG = false>
+__device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd, const Lds &L, int k = 1)
 {
+    static_assert(!(ADJ && SEG), "the adjoint runs on whole systems");
     constexpr int PD = DB + 1, NTL = 64;
     const int lane = threadIdx.x;
     const int b = sd.b, ng = sd.ng, nr = a.nr, N = sd.N;
     const long long b2 = (long long)b * b;
     double *X = a.rhs + sd.oRhs;
-    double *stD = L.P, *stE = L.P + DB * PD, *stG = L.P + 2 * DB * PD;
+    double *stD = L.P, *stE = L.P + DB * PD, *stG = L.P + 2 * DB * PD, *stF = stG + NGM * PD;
+    const int s0 = SEG ? seg_first(sd, k) : 0;
+    const int len = SEG ? seg_len(sd, k) : N;
+    const bool hasF = SEG && k > 1;
+    const int nxt = s0 + len;   // the separator after the chain (segments k < p)
     for (int e = lane; e < NGM * nr; e += NTL) {
         L.XG[e] = (e < ng * nr) ? X[(long long)N * b * nr + e] : 0.0;
         if (ADJ) L.PG[e] = (e < ng * nr) ? a.xp[sd.oRhs + (long long)N * b * nr + e] : 0.0;
     }
     for (int e = lane; e < DB * nr; e += NTL) {
-        L.XN[e] = 0.0;
+        L.XN[e] = (SEG && nxt < N && e < b * nr) ? X[(long long)nxt * b * nr + e] : 0.0;
         if (ADJ) L.PN[e] = 0.0;
+        if (SEG) L.XS[e] = (hasF && e < b * nr) ? X[(long long)sep_of(sd, k) * b * nr + e] : 0.0;
     }
     // the staging area outside the b x b (ng x b) blocks stays zero for the products
-    for (int e = lane; e < (2 * DB + NGM) * PD; e += NTL) L.P[e] = 0.0;
+    for (int e = lane; e < ((SEG ? 3 : 2) * DB + NGM) * PD; e += NTL) L.P[e] = 0.0;
     BwdStage<DB> pf;
-    pf.template fetch<ADJ>(a, sd, N - 1, lane);
-    for (int i = N - 1; i >= 0; --i) {
+    pf.template fetch<ADJ>(a, sd, s0 + len - 1, lane);
+    if (hasF) pf.fetch_fill(a, sd, k, len - 1, lane);
+    for (int i = len - 1; i >= 0; --i) {
         int lane_s = lane;
         asm volatile("" : "+v"(lane_s));
+        const int gs = s0 + i;
         const int c = lane_s;
         const bool cv = c < b;
-        const bool hasE = i + 1 < N;
+        const bool hasE = gs + 1 < N;
         wave_sync();
         pf.stage(sd, nr, stD, stE, stG, L.XC, lane_s);
         if (ADJ) pf.stage_primal(sd, nr, L.PC, lane_s);
+        if (hasF) pf.stage_fill(sd, stF, lane_s);
         wave_sync();
-        if (i > 0) pf.template fetch<ADJ>(a, sd, i - 1, lane_s);
+        if (i > 0) {
+            pf.template fetch<ADJ>(a, sd, gs - 1, lane_s);
+            if (hasF) pf.fetch_fill(a, sd, k, i - 1, lane_s);
+        }
         double dcol[DB];
 #pragma unroll
         for (int l = 0; l < DB; ++l) {
@@ -643,7 +866,7 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
         }
         const double dinv = cv ? 1.0 / stD[c * PD + c] : 1.0;
         {
-            // hat E^T x_{i+1} + hat G^T x_g for all rhs on the matrix cores, into Y
+            // hat E^T x_{i+1} + hat G^T x_g (+ hat B x_sep) for all rhs on the matrix cores, into Y
             const int li = lane_s & 15, lk = lane_s >> 4;
             constexpr int TB = DB / 16;
             dx4 accT[TB];
@@ -651,6 +874,7 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
             for (int rt = 0; rt < TB; ++rt) accT[rt] = dx4{0.0, 0.0, 0.0, 0.0};
             if (hasE) mm_rhs<TB, DB, true>(stE, PD, L.XN, nr, accT, li, lk);
             if (ng) mm_rhs<TB, NGM, true>(stG, PD, L.XG, nr, accT, li, lk);
+            if (SEG && hasF) mm_rhs<TB, DB, true>(stF, PD, L.XS, nr, accT, li, lk);
             if (li < nr) {
 #pragma unroll
                 for (int rt = 0; rt < TB; ++rt)
@@ -664,13 +888,13 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
             const double xv = back_subst<DB>(dcol, acc, dinv);
             wave_sync();
             if (cv) {
-                X[((long long)i * b + c) * nr + j] = xv;
+                X[((long long)gs * b + c) * nr + j] = xv;
                 L.XC[c * nr + j] = xv;
             }
             wave_sync();
         }
         if (ADJ && cv) {
-            double *dD = a.dD + sd.oD + (long long)i * b2;
+            double *dD = a.dD + sd.oD + (long long)gs * b2;
             for (int r = 0; r < b; ++r) {
                 double s = 0.0;
                 for (int j = 0; j < nr; ++j)
@@ -678,7 +902,7 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
                 dD[r * b + c] = -0.5 * s;
             }
             if (ng) {
-                double *dB = a.dB + sd.oB + (long long)i * ng * b;
+                double *dB = a.dB + sd.oB + (long long)gs * ng * b;
                 for (int q = 0; q < ng; ++q) {
                     double s = 0.0;
                     for (int j = 0; j < nr; ++j)
@@ -687,7 +911,7 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
                 }
             }
             if (hasE) {
-                double *dC = a.dC + sd.oC + (long long)i * b2;
+                double *dC = a.dC + sd.oC + (long long)gs * b2;
                 for (int r = 0; r < b; ++r) {
                     double s = 0.0;
                     for (int j = 0; j < nr; ++j)

@@ -74,6 +74,8 @@ struct Args {
     int *failidx;                       // per system: first failing stage (1-based), INT_MAX = none
     int *status;                        // per system: final info of the last factorization
     int *info;                          // caller's info (factor modes), may be null
+    const int *red;                     // systems of a segmented dense class (sequential phase)
+    int n_red;
     int nr;
     int spin_limit;
 };

@@ -86,13 +86,14 @@ def lib():
         L.kkt_plan_class_info.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                           ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32)]
         L.kkt_plan_set_class_events.argtypes = [vp, i32, vp, vp]
+        L.kkt_plan_class_kind.argtypes = [vp, i32, ctypes.POINTER(i32)]
         L.kkt_workspace_error.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
         L.kkt_plan_set_spin_limit.argtypes = [vp, i32]
         L.kkt_status_string.restype = ctypes.c_char_p
         L.kkt_status_string.argtypes = [ctypes.c_int]
         for name in ("kkt_plan_create", "kkt_plan_create_tuned", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
                      "kkt_workspace_init", "kkt_factor", "kkt_solve", "kkt_factor_solve", "kkt_solve_adjoint",
-                     "kkt_plan_class_info", "kkt_plan_set_class_events", "kkt_workspace_error",
+                     "kkt_plan_class_info", "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error",
                      "kkt_plan_set_spin_limit"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -102,7 +103,7 @@ def lib():
 EXPORTED = ("kkt_plan_create", "kkt_plan_create_tuned", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
             "kkt_plan_factor_offset", "kkt_workspace_init", "kkt_factor", "kkt_solve",
             "kkt_factor_solve", "kkt_solve_adjoint", "kkt_status_string", "kkt_plan_class_info",
-            "kkt_plan_set_class_events", "kkt_workspace_error", "kkt_plan_set_spin_limit")
+            "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error", "kkt_plan_set_spin_limit")
 
 
 def _check(rc, what):
@@ -266,6 +267,15 @@ class Plan:
                                              ctypes.byref(lds), ctypes.byref(gr)), "kkt_plan_class_info")
             t = (bp.value, it.value, nt.value, lds.value)
             out.append(t + (gr.value,) if with_grid else t)
+        return out
+
+    def class_kinds(self):
+        """Kind of each launch class: 0 general, 1 dense (whole systems), 2 dense segmented."""
+        out = []
+        for c in range(self.info.num_classes):
+            k = ctypes.c_int32()
+            _check(lib().kkt_plan_class_kind(self._h, c, ctypes.byref(k)), "kkt_plan_class_kind")
+            out.append(k.value)
         return out
 
     def workspace_error(self, ws, stream=None):

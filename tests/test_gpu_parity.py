@@ -179,6 +179,25 @@ def test_indefinite_block_reports_info_and_nan():
     check_solution(plan, x, systems[:1])
 
 
+def test_indefinite_block_segmented_dense_classes():
+    """Failures inside a segment, at a separator and at the corner of segmented
+    16/24/32-wide systems (the dense segment sweeps and the sequential phase)."""
+    dims = [(14, 12, 2), (14, 12, 2), (14, 20, 3), (14, 28, 2), (14, 12, 0)]
+    systems = gen(19, dims)
+    ps = [3, 3, 2, 3, 3]
+    systems[1].D[2] = -np.eye(12)         # a stage of segment 1
+    systems[2].D[9] = -np.eye(20)         # a stage of segment 2
+    systems[3].corner[:] = -np.eye(2)     # corner
+    plan, pools, ws, x, info = run(systems, ps, 1)
+    exp = [okkt.KKTFactor(s.D, s.C, s.B, s.corner, plan.segment_lengths(i)).info for i, s in enumerate(systems)]
+    assert info.tolist() == exp and exp[0] == 0 and exp[4] == 0 and all(e != 0 for e in exp[1:4])
+    xs = split_rhs(plan, x, systems)
+    for i in (1, 2, 3):
+        assert np.isnan(xs[i]).all()
+    check_solution(plan, x, [systems[0]])
+    check_factor(plan, ws, [systems[0]])
+
+
 def test_repeat_runs_bitwise_identical():
     systems = gen(11, [(30, 8, 4), (25, 16, 0), (17, 6, 2)])
     ps = [3, 2, 1]
