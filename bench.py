@@ -168,15 +168,15 @@ def fd_check(torch, kkt, workloads, dsys, dplan, dev, grads, systems=(0, 511, 10
 SINGLE_P = {"small": (1, 2, 4, 8), "race": (1, 2, 4, 8, 16, 32, 64, 128)}
 
 
-def single_systems(torch, kkt, workloads, okkt, dev, reps=50):
+def single_systems(torch, kkt, workloads, okkt, dev, cost_model=None, reps=50):
     """Latency of one factor + solve call on the single-system workloads, per
-    segment count p and with the p the default cost model picks; speedup vs p = 1."""
+    segment count p and with the p the cost model picks; speedup vs p = 1."""
     out = {}
     for name, plist in SINGLE_P.items():
         sy = workloads.single(name)
         nrhs = sy.r.shape[1]
         pools = kkt.pack_to_device(workloads.pack([sy]), dev)
-        auto = kkt.Plan([(sy.N, sy.b, sy.ng, 0)], nrhs=nrhs).segments()[0]
+        auto = kkt.Plan([(sy.N, sy.b, sy.ng, 0)], nrhs=nrhs, cost_model=cost_model).segments()[0]
         res = {}
         for p in sorted(set(plist) | {auto}):
             plan = kkt.Plan([(sy.N, sy.b, sy.ng, p)], nrhs=nrhs)
@@ -220,7 +220,9 @@ def main():
     ap.add_argument("--systems", type=int, default=4096)
     ap.add_argument("--plain-sample", type=int, default=512)
     ap.add_argument("--cpu-sample", type=int, default=2048)
-    ap.add_argument("--p", type=int, default=1, help="segments per system (1 = sequential, 0 = cost model)")
+    ap.add_argument("--p", type=int, default=0,
+                    help="segments per system (1 = sequential; 0 = chosen by the cost model measured on this GPU; "
+                         "-1 = chosen by the default flop-ratio model)")
     ap.add_argument("--skip-diff", action="store_true")
     ap.add_argument("--skip-single", action="store_true", help="skip the single-system latency section")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay measurement")
@@ -256,7 +258,17 @@ def main():
     S = len(systems)
     log("generated %d systems in %.1fs (%.2f GB of inputs)" % (S, time.time() - t0,
         sum(v.nbytes for v in pools.values()) / 1e9))
-    plan = kkt.Plan([(sy.N, sy.b, sy.ng, args.p) for sy in systems], nrhs=1)
+    cost_model, calib_s = None, None
+    if args.p == 0:
+        from paper_2511_00946_amd import autotune
+        t_cal = time.time()
+        cost_model = autotune.cost_model()
+        calib_s = round(time.time() - t_cal, 1)
+        log("cost model (measured, %.1fs): %s" % (calib_s, cost_model))
+    plan = kkt.Plan([(sy.N, sy.b, sy.ng, max(args.p, 0)) for sy in systems], nrhs=1, cost_model=cost_model)
+    if args.p <= 0:
+        segs = plan.segments()
+        log("segments chosen: %d systems split, max p %d" % (sum(1 for q in segs if q > 1), max(segs)))
     dp = kkt.pack_to_device(pools, dev)
     ws = plan.new_workspace(dev)
     info = torch.zeros(S, dtype=torch.int32, device=dev)
@@ -409,14 +421,14 @@ def main():
     del dp, ws, x, info
     torch.cuda.empty_cache()
 
-    single = None if args.skip_single else single_systems(torch, kkt, workloads, okkt, dev)
+    single = None if args.skip_single else single_systems(torch, kkt, workloads, okkt, dev, cost_model)
 
     # differentiation workload: forward factor + solve, adjoint backward
     diff = None
     if not args.skip_diff:
         dspec = workloads.uniform_batch_spec()
         dsys, dpools = build_pools(dspec)
-        dplan = kkt.Plan([(sy.N, sy.b, sy.ng, args.p if args.p else 1) for sy in dsys], nrhs=1)
+        dplan = kkt.Plan([(sy.N, sy.b, sy.ng, max(args.p, 0)) for sy in dsys], nrhs=1, cost_model=cost_model)
         dd = kkt.pack_to_device(dpools, dev)
         dws = dplan.new_workspace(dev)
         dinfo = torch.zeros(len(dsys), dtype=torch.int32, device=dev)
@@ -476,7 +488,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "ragged batch: %d systems, N~U{16..256}, b~U{8,16,32}, ng~U{0,2,4}, 1 rhs, seed 4"
-                               % S, "segments": "p=%d" % args.p if args.p else "cost model"},
+                               % S, "segments": "p=%d" % args.p if args.p > 0 else
+                                     ("cost model measured on this GPU" if args.p == 0 else "default cost model")},
         "plain_systems_per_s": None if plain_sps is None else round(plain_sps, 1),
         "plain_sample": int(len(samp)),
         "batched_vs_plain": None if plain_sps is None else round(value / plain_sps, 2),

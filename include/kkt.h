@@ -121,16 +121,21 @@ int kkt_plan_create(kkt_plan **plan, int32_t num_systems, const kkt_dims *dims, 
  * block-size class (8, 16, 24, 32): the time of one stage of a first segment
  * (t_first), of a segment carrying fill rows (t_fill, segments 2..p), of one
  * reduced-chain stage (t_red), the fixed cost of an item (t_item), and the
- * number of items the device runs at once (workers).  Units are arbitrary but
+ * number of items the device runs at once, for unsegmented systems (workers)
+ * and for the items of segmented ones (workers_seg; 0 = same as workers).  The
+ * work of a system counts against the pool its items run in.  Units are arbitrary but
  * common.  Segment lengths follow Eq. 13's balance with sigma = t_fill / t_first.
- * Starting from p = 1, the plan repeatedly adds a segment to the system with the
- * longest estimated item while that lowers the estimated makespan
- * max(total work / workers, longest item) of its class.  A default model
+ * The classes of a batch share the device, so the step is estimated as
+ * max(sum over classes of total work / workers, longest item).  The plan
+ * searches a bound T on the longest item: every system with p = 0 takes the
+ * fewest segments whose longest item stays within T, and the smallest T that
+ * the resulting summed work also meets is kept (systems of one class and length
+ * get equal p).  Fixed p are honoured and enter the estimate.  A default model
  * follows the flop ratios of Table 1 (7/3, 19/3 and 10/3 b^3 per stage); a
  * measured one (paper_2511_00946_amd/autotune.py) can be passed here. */
 typedef struct {
     double t_first[4], t_fill[4], t_red[4], t_item[4];
-    double workers[4];
+    double workers[4], workers_seg[4];
 } kkt_cost_model;
 
 int kkt_plan_create_tuned(kkt_plan **plan, int32_t num_systems, const kkt_dims *dims, int32_t nrhs,
@@ -183,8 +188,9 @@ int kkt_plan_set_spin_limit(kkt_plan *plan, int32_t limit);
 
 /* Launch class c of the plan (0 <= c < num_classes): padded block size, number
  * of work items, threads per workgroup and LDS bytes of its factor-mode launch,
- * and the largest number of resident workgroups launched so far (0 before the
- * first call).  Systems are grouped by padded block size (8, 16, 24, 32); in the
+ * and the number of workgroups of its item sweeps (the first launch of a factor
+ * call: as many as fit on the device at once, at most one per item; 0 before
+ * the plan's first factor call).  Systems are grouped by padded block size (8, 16, 24, 32); in the
  * 16, 24 and 32 groups the unsegmented systems (p = 1) and the segmented ones
  * form two classes, both run with one 64-lane wave per work item (dense stage
  * sweeps on the FP64 matrix cores); see kkt_plan_class_kind. */

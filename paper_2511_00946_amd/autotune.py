@@ -2,11 +2,13 @@
 
 For every padded block-size class the device is timed on small synthetic
 batches (the library's own kernels, one persistent launch per class):
-  workers   resident workgroups of the class's launch (read back from the plan)
+  workers   workgroups of the class's item sweeps for unsegmented systems
+            (read back from the plan)
+  workers_seg  the same for the items of segmented systems
   t_first   per-stage time of a first segment under full load
             (a batch of `workers` systems, p = 1, timed at horizons 8 and 24)
   t_fill    per-stage time of a segment carrying fill rows under full load
-            (systems with p = 2 and a one-stage first segment)
+            (workers_seg / 2 systems with p = 2 and a one-stage first segment)
   t_red     per-stage time of the reduced chain (a single system at large p,
             minus its segments), floored at t_first
   t_item    fixed cost of an item (intercept of the p = 1 fit)
@@ -60,24 +62,26 @@ def _time_batch(dims, reps=3):
 
 
 def calibrate(verbose=False):
-    model = {k: [0.0] * 4 for k in ("t_first", "t_fill", "t_red", "t_item", "workers")}
+    model = {k: [0.0] * 4 for k in ("t_first", "t_fill", "t_red", "t_item", "workers", "workers_seg")}
     for c, bp in enumerate(CLASSES):
         b = bp
         _, W = _time_batch([(1, b, 2, 1)] * 8192, reps=1)          # more items than slots: the full grid
         W = max(1, W)
+        _, Ws = _time_batch([(3, b, 2, 2, 1)] * 8192, reps=1)      # two items per system
+        Ws = max(2, Ws)
         t1, _ = _time_batch([(8, b, 2, 1)] * W)
         t2, _ = _time_batch([(24, b, 2, 1)] * W)
         t_first = max((t2 - t1) / 16.0, 1e-6)
         t_item = max(t1 - 8 * t_first, 0.0)
-        tf, _ = _time_batch([(18, b, 2, 2, 1)] * W)                 # N1 = 1, Nk = 16 with fill rows
+        tf, _ = _time_batch([(18, b, 2, 2, 1)] * (Ws // 2))         # N1 = 1, Nk = 16 with fill rows
         t_fill = max((tf - t_item) / 16.0, t_first)
         ts, _ = _time_batch([(65, b, 2, 32)])                       # 32 short segments, 31 reduced stages
         t_red = max((ts - t_item - 2 * t_fill) / 31.0, t_first)
         model["t_first"][c], model["t_fill"][c], model["t_red"][c] = t_first, t_fill, t_red
-        model["t_item"][c], model["workers"][c] = t_item, float(W)
+        model["t_item"][c], model["workers"][c], model["workers_seg"][c] = t_item, float(W), float(Ws)
         if verbose:
-            print("class %2d: workers %d t_first %.4f t_fill %.4f t_red %.4f t_item %.4f (ms)"
-                  % (bp, W, t_first, t_fill, t_red, t_item), flush=True)
+            print("class %2d: workers %d / %d t_first %.4f t_fill %.4f t_red %.4f t_item %.4f (ms)"
+                  % (bp, W, Ws, t_first, t_fill, t_red, t_item), flush=True)
     return model
 
 

@@ -21,6 +21,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <unordered_set>
@@ -617,53 +618,95 @@ ItemEst estimate(int N, int p, int cls, const kkt_cost_model &m)
     return {std::max(seg1, segk) + red, seg1 + (p - 1) * segk + red};
 }
 
-// Choose p for the systems of one class with dims[s].p == 0: start from p = 1 and
-// keep splitting the system that bounds the makespan max(total / workers, longest)
-// while that lowers it.
-void choose_segments(std::vector<kkt_dims> &dims, const std::vector<int> &cls_of, int cls, const kkt_cost_model &m)
+// Items of class cls the device runs at once, for systems of p segments.
+double pool(const kkt_cost_model &m, int cls, int p)
 {
-    std::vector<int> tun;
-    double total = 0.0, fixed_longest = 0.0;
+    const double w = (p > 1 && m.workers_seg[cls] > 0.0) ? m.workers_seg[cls] : m.workers[cls];
+    return std::max(1.0, w);
+}
+
+// Choose p for the systems with dims[s].p == 0.  The classes of a batch run
+// concurrently and share the device, so the step is modelled as
+// max(sum over classes of total work / workers, longest item of any class).  For a
+// bound T on the longest item every tuned system takes the fewest segments whose
+// longest item stays within T; total work falls as T grows, so the best T sits
+// where the summed work crosses T.  The candidate bounds are the longest-item
+// values themselves, searched by bisection, and the two candidates around the
+// crossing are compared.  Systems of one class and length always get equal p (a
+// greedy split of one system at a time stalls on such ties).
+void choose_segments(std::vector<kkt_dims> &dims, const std::vector<int> &cls_of, const kkt_cost_model &m)
+{
+    double fixed_work = 0.0, fixed_longest = 0.0;
+    std::map<std::pair<int, int>, int> count;      // tuned systems per (class, N)
     for (size_t s = 0; s < dims.size(); ++s) {
-        if (cls_of[s] != cls) continue;
+        const int c = cls_of[s];
         if (dims[s].p == 0) {
-            dims[s].p = 1;
-            tun.push_back((int)s);
+            count[{c, dims[s].N}] += 1;
         } else {
-            const ItemEst e = estimate(dims[s].N, dims[s].p, cls, m);
-            total += e.total;
+            const ItemEst e = estimate(dims[s].N, dims[s].p, c, m);
+            fixed_work += e.total / pool(m, c, dims[s].p);
             fixed_longest = std::max(fixed_longest, e.longest);
         }
     }
-    if (tun.empty()) return;
-    std::vector<ItemEst> est(tun.size());
-    for (size_t i = 0; i < tun.size(); ++i) {
-        est[i] = estimate(dims[tun[i]].N, 1, cls, m);
-        total += est[i].total;
+    if (count.empty()) return;
+    struct Len {
+        int cls, N, cnt;
+        std::vector<ItemEst> est;                  // est[p - 1], p = 1 .. (N + 1) / 2
+    };
+    std::vector<Len> lens;
+    std::vector<double> cand;
+    for (const auto &kv : count) {
+        const int c = kv.first.first, N = kv.first.second;
+        Len L{c, N, kv.second, {}};
+        const int pmax = std::max(1, std::min((N + 1) / 2, 256));
+        for (int p = 1; p <= pmax; ++p) {
+            L.est.push_back(estimate(N, p, c, m));
+            if (L.est.back().longest < 1e299) cand.push_back(std::max(L.est.back().longest, fixed_longest));
+        }
+        lens.push_back(std::move(L));
     }
-    const double W = std::max(1.0, m.workers[cls]);
-    long long max_iter = 0;                        // every step raises one p, p <= (N + 1) / 2
-    for (int s : tun) max_iter += (dims[s].N + 1) / 2;
-    for (long long iter = 0; iter < max_iter; ++iter) {
-        size_t worst = 0;
-        for (size_t i = 1; i < tun.size(); ++i)
-            if (est[i].longest > est[worst].longest) worst = i;
-        const double longest = std::max(fixed_longest, est[worst].longest);
-        const double makespan = std::max(total / W, longest);
-        if (est[worst].longest < total / W || est[worst].longest < fixed_longest) break;
-        kkt_dims &d = dims[tun[worst]];
-        const int pn = d.p + 1;
-        if (d.N < 2 * pn - 1) break;
-        const ItemEst en = estimate(d.N, pn, cls, m);
-        const double total_n = total - est[worst].total + en.total;
-        double longest_n = std::max(fixed_longest, en.longest);
-        for (size_t i = 0; i < tun.size(); ++i)
-            if (i != worst) longest_n = std::max(longest_n, est[i].longest);
-        if (std::max(total_n / W, longest_n) >= makespan) break;
-        d.p = pn;
-        total = total_n;
-        est[worst] = en;
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    // fewest segments meeting T (the shortest longest item if none does), per length
+    auto pick = [&](double T, std::vector<int> *ps, double *longest) {
+        double work = fixed_work;
+        *longest = fixed_longest;
+        for (size_t i = 0; i < lens.size(); ++i) {
+            const Len &L = lens[i];
+            int best = 0;
+            for (int q = 0; q < (int)L.est.size(); ++q) {
+                if (L.est[q].longest <= T) { best = q; break; }
+                if (L.est[q].longest < L.est[best].longest) best = q;
+            }
+            if (ps) (*ps)[i] = best + 1;
+            work += L.cnt * L.est[best].total / pool(m, L.cls, best + 1);
+            *longest = std::max(*longest, L.est[best].longest);
+        }
+        return work;
+    };
+    // smallest candidate T that the choice for T meets: summed work <= T, longest <= T
+    double lg = 0.0;
+    auto meets = [&](double T) { return std::max(pick(T, nullptr, &lg), lg) <= T; };
+    size_t lo = 0, hi = cand.size() - 1;
+    if (meets(cand[hi])) {
+        while (lo < hi) {
+            const size_t mid = (lo + hi) / 2;
+            if (meets(cand[mid])) hi = mid; else lo = mid + 1;
+        }
+    } else {
+        lo = hi;
     }
+    double best_span = 1e300;
+    std::vector<int> ps(lens.size()), best_ps(lens.size(), 1);
+    for (size_t k = (lo > 0 ? lo - 1 : 0); k <= lo; ++k) {
+        const double work = pick(cand[k], &ps, &lg);
+        const double span = std::max(work, lg);
+        if (span < best_span) { best_span = span; best_ps = ps; }
+    }
+    std::map<std::pair<int, int>, int> p_of;
+    for (size_t i = 0; i < lens.size(); ++i) p_of[{lens[i].cls, lens[i].N}] = best_ps[i];
+    for (size_t s = 0; s < dims.size(); ++s)
+        if (dims[s].p == 0) dims[s].p = p_of[{cls_of[s], dims[s].N}];
 }
 
 kkt_cost_model default_cost_model()
@@ -676,6 +719,7 @@ kkt_cost_model default_cost_model()
         m.t_red[c] = 10.0 / 3.0 * b3;
         m.t_item[c] = 0.0;
         m.workers[c] = 512.0;
+        m.workers_seg[c] = 512.0;
     }
     return m;
 }
@@ -913,7 +957,7 @@ int kkt_plan_create_tuned(kkt_plan **out, int32_t S, const kkt_dims *dims_in, in
             cls0[s] = class_of(dims[s].b);
         }
         const kkt_cost_model m = model ? *model : default_cost_model();
-        for (int c = 0; c < NCLS; ++c) choose_segments(dims, cls0, c, m);
+        choose_segments(dims, cls0, m);
     }
     kkt_plan *P = new (std::nothrow) kkt_plan;
     if (!P) return KKT_EINTERNAL;
@@ -1191,9 +1235,8 @@ int kkt_plan_class_info(const kkt_plan *plan, int32_t c, int32_t *block_pad, int
                         int32_t *threads, int64_t *lds_bytes, int32_t *grid)
 {
     if (grid && plan && c >= 0 && c < (int)plan->cls.size()) {
-        int g = 0;
-        for (int m = 0; m < 6; ++m) g = std::max(g, plan->grid[c][m]);
-        *grid = g;
+        // the item sweeps: the first launch of the factor modes
+        *grid = std::max(plan->grid[c][M_FACTOR * 3], plan->grid[c][M_FACTOR_SOLVE * 3]);
     }
     if (!plan) return KKT_EPOINTER;
     if (c < 0 || c >= (int)plan->cls.size()) return KKT_EDIMS;

@@ -41,16 +41,17 @@ class SystemLayout(ctypes.Structure):
 
 class CostModel(ctypes.Structure):
     """Per padded block-size class (8, 16, 24, 32): stage times of first segments,
-    fill-carrying segments and reduced stages, item overhead, concurrent workers."""
+    fill-carrying segments and reduced stages, item overhead, concurrent items of
+    unsegmented systems (workers) and of segmented ones (workers_seg, 0 = workers)."""
     _fields_ = [("t_first", ctypes.c_double * 4), ("t_fill", ctypes.c_double * 4),
                 ("t_red", ctypes.c_double * 4), ("t_item", ctypes.c_double * 4),
-                ("workers", ctypes.c_double * 4)]
+                ("workers", ctypes.c_double * 4), ("workers_seg", ctypes.c_double * 4)]
 
     @classmethod
     def from_dict(cls, d):
         m = cls()
-        for k in ("t_first", "t_fill", "t_red", "t_item", "workers"):
-            for i, v in enumerate(d[k]):
+        for k in ("t_first", "t_fill", "t_red", "t_item", "workers", "workers_seg"):
+            for i, v in enumerate(d.get(k, [0.0] * 4)):
                 getattr(m, k)[i] = float(v)
         return m
 

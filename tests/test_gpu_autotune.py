@@ -18,7 +18,7 @@ def test_measured_cost_model_and_its_choice(tmp_path, monkeypatch):
     monkeypatch.setenv("KKT_CACHE_DIR", str(tmp_path))
     print("gpu case: autotune calibration", file=sys.stderr, flush=True)
     m = autotune.cost_model(refresh=True, verbose=True)
-    for k in ("t_first", "t_fill", "t_red", "workers"):
+    for k in ("t_first", "t_fill", "t_red", "workers", "workers_seg"):
         assert all(np.isfinite(v) and v > 0 for v in m[k]), (k, m[k])
     assert autotune.cost_model() == m                    # cached
     s = workloads.single("race")
