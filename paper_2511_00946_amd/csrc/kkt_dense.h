@@ -205,7 +205,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * rt + 4 * v + lk;
-                    rn[rt][v] = (nextD && r < b && li < nr) ? rs[r * nr + li] : 0.0;
+                    rn[rt][v] = ld_or_zero(rs, r * nr + li, nextD && r < b && li < nr);
                 }
         }
         double cA[TB][KS];
@@ -215,18 +215,26 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
 #pragma unroll
             for (int kk = 0; kk < KS; ++kk) {
                 const int r = 16 * rt + li, c = 4 * kk + lk;
-                cA[rt][kk] = (hasN && r < b && c < b) ? Ci[r * b + c] : 0.0;
+                cA[rt][kk] = ld_or_zero(Ci, r * b + c, hasN && r < b && c < b);
             }
         phase_fence();
         // ---- (1) L = chol(Dw) on the row lanes, L^{-1} on the column lanes
         double vec[DB];
         {
+            // every lane reads both candidates (in bounds for all lanes) before any
+            // select, so the reads issue together instead of one round trip each
             const double *rowp = RA + (isP ? ri : 0) * PD, *colp = RA + (isP ? ri : 0);
+            double lo[DB], up[DB];
 #pragma unroll
             for (int c = 0; c < DB; ++c) {
-                const double lo = rowp[c], up = colp[c * PD];
-                vec[c] = isP ? ((c <= ri) ? lo : up) : ((isI && c == ri) ? 1.0 : 0.0);
+                lo[c] = rowp[c];
+                up[c] = colp[c * PD];
             }
+            pin_row<DB>(lo);
+            pin_row<DB>(up);
+#pragma unroll
+            for (int c = 0; c < DB; ++c)
+                vec[c] = isP ? ((c <= ri) ? lo[c] : up[c]) : ((isI && c == ri) ? 1.0 : 0.0);
         }
         bool bad = false;
         // Every lane writes its column entry each step, the lanes that hold no
@@ -265,6 +273,9 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             wave_sync();
         }
         if (bad && !failed) failed = gs + 1;
+        // C_i and r_{i+1} have long arrived: retire them here, before this stage's
+        // first stores, so that no later use of them waits for outstanding stores
+        vm_drain();
 
         phase_fence();
         // ---- (2) L rows and L^{-1} columns into LDS; store L
@@ -363,8 +374,8 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * rt + 4 * v + lk, c = 16 * ct + li;
                     const bool in = nextD && r < b && c < b;
-                    dn[t][v] = in ? Dn[r * b + c] : 0.0;
-                    dt[t][v] = in ? Dn[c * b + r] : 0.0;
+                    dn[t][v] = ld_or_zero(Dn, r * b + c, in);
+                    dt[t][v] = ld_or_zero(Dn, c * b + r, in);
                 }
         double bn[TB][4];
         const double *Bn = a.B + sd.oB + (long long)(gs + 1) * ng * b;
@@ -373,7 +384,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int q = 4 * v + lk, c = 16 * ct + li;
-                bn[ct][v] = (nextD && q < ng && c < b) ? Bn[q * b + c] : 0.0;
+                bn[ct][v] = ld_or_zero(Bn, q * b + c, nextD && q < ng && c < b);
             }
 
         phase_fence();
@@ -393,7 +404,6 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                     for (int v = 0; v < 4; ++v) {
                         const int r = 16 * rt + 4 * v + lk;
                         L.Y[r * nr + li] = accY[rt][v];
-                        if (r < b) a.rhs[sd.oRhs + ((long long)gs * b + r) * nr + li] = accY[rt][v];
                     }
             }
             wave_sync();
@@ -582,6 +592,10 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                 }
         }
         wave_sync();
+        // y_i goes out only now: stored earlier, the wait for the next stage's blocks
+        // in the Gram would also wait for these stores
+        if (FWD)
+            for (int e = lane; e < b * nr; e += NTL) a.rhs[sd.oRhs + (long long)gs * b * nr + e] = L.Y[e];
     }
 
     // ---- epilogue: separator partials (k >= 2) and the arrow partials of segment k
@@ -623,7 +637,7 @@ struct BwdStage {
 #pragma unroll
         for (int m = 0; m < MD; ++m) {
             const int x = lane + m * NTL;
-            f[m] = (x < b * b) ? src[x] : 0.0;
+            f[m] = ld_or_zero(src, x, x < b * b);
         }
     }
 
@@ -654,25 +668,25 @@ struct BwdStage {
 #pragma unroll
         for (int m = 0; m < MD; ++m) {
             const int x = lane + m * NTL;
-            d[m] = (x < b * b) ? Ld[x] : 0.0;
-            e[m] = (hasE && x < b * b) ? Lc[x] : 0.0;
+            d[m] = ld_or_zero(Ld, x, x < b * b);
+            e[m] = ld_or_zero(Lc, x, hasE && x < b * b);
         }
 #pragma unroll
         for (int m = 0; m < MG; ++m) {
             const int x = lane + m * NTL;
-            g[m] = (x < ng * b) ? Lb[x] : 0.0;
+            g[m] = ld_or_zero(Lb, x, x < ng * b);
         }
 #pragma unroll
         for (int m = 0; m < MY; ++m) {
             const int x = lane + m * NTL;
-            y[m] = (x < b * nr) ? Y[x] : 0.0;
+            y[m] = ld_or_zero(Y, x, x < b * nr);
         }
         if (PRIMAL) {
             const double *XP = a.xp + sd.oRhs + (long long)i * b * nr;
 #pragma unroll
             for (int m = 0; m < MY; ++m) {
                 const int x = lane + m * NTL;
-                px[m] = (x < b * nr) ? XP[x] : 0.0;
+                px[m] = ld_or_zero(XP, x, x < b * nr);
             }
         }
     }
@@ -744,8 +758,12 @@ __device__ __forceinline__ void dense_forward(const Args &a, const SysDesc &sd, 
         const bool rv = r < b;
         const bool hasN = i + 1 < N;
         wave_sync();
-        pf.stage(sd, nr, stD, stE, stG, L.Y, lane_s);   // Y receives r_i (unused; w_i is in W)
+        pf.stage(sd, nr, stD, stE, stG, L.XC, lane_s);   // XC receives r_i (unused; w_i is in W)
         wave_sync();
+        // y of the previous stage goes out only now, after the wait for this stage's
+        // blocks: stored earlier, that wait would also wait for the stores
+        if (i > 0)
+            for (int e = lane_s; e < b * nr; e += NTL) X[(long long)(i - 1) * b * nr + e] = L.Y[e];
         if (hasN) pf.fetch(a, sd, i + 1, lane_s);
         double drow[DB];
 #pragma unroll
@@ -759,7 +777,6 @@ __device__ __forceinline__ void dense_forward(const Args &a, const SysDesc &sd, 
             const double yv = fwd_subst<DB>(drow, w, dinv);
             wave_sync();
             if (rv) {
-                X[((long long)i * b + r) * nr + j] = yv;
                 L.Y[r * nr + j] = yv;
             } else if (r < DB) {
                 L.Y[r * nr + j] = 0.0;
@@ -800,6 +817,7 @@ __device__ __forceinline__ void dense_forward(const Args &a, const SysDesc &sd, 
         }
     }
     wave_sync();
+    for (int e = lane; e < b * nr; e += NTL) X[(long long)(N - 1) * b * nr + e] = L.Y[e];
     if (ng)
         for (int e = lane; e < ng * nr; e += NTL) a.F[sd.oScr + scr_yg(b, ng, nr) + e] = L.XG[e];
     wave_sync();
@@ -854,6 +872,10 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
         if (ADJ) pf.stage_primal(sd, nr, L.PC, lane_s);
         if (hasF) pf.stage_fill(sd, stF, lane_s);
         wave_sync();
+        // x of the stage solved last goes out only now, after the wait for this
+        // stage's blocks: stored earlier, that wait would also wait for the stores
+        if (i < len - 1)
+            for (int e = lane_s; e < b * nr; e += NTL) X[(long long)(gs + 1) * b * nr + e] = L.XN[e];
         if (i > 0) {
             pf.template fetch<ADJ>(a, sd, gs - 1, lane_s);
             if (hasF) pf.fetch_fill(a, sd, k, i - 1, lane_s);
@@ -887,10 +909,7 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
             const double acc = cv ? L.XC[c * nr + j] - L.Y[c * nr + j] : 0.0;
             const double xv = back_subst<DB>(dcol, acc, dinv);
             wave_sync();
-            if (cv) {
-                X[((long long)gs * b + c) * nr + j] = xv;
-                L.XC[c * nr + j] = xv;
-            }
+            if (cv) L.XC[c * nr + j] = xv;
             wave_sync();
         }
         if (ADJ && cv) {
@@ -927,6 +946,8 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
                 if (ADJ) L.PN[c * nr + j] = L.PC[c * nr + j];
             }
     }
+    wave_sync();
+    for (int e = lane; e < b * nr; e += NTL) X[(long long)s0 * b * nr + e] = L.XN[e];
     wave_sync();
 }
 

@@ -177,6 +177,16 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
+// Wait for every outstanding vector memory operation of the wave.  Loads and
+// stores share one counter here and may complete out of order with respect to
+// each other, so a wait for a load issued while stores are pending waits for
+// all of them; draining at a point where the loads are known to have arrived
+// keeps later uses of their registers free of waits.
+__device__ __forceinline__ void vm_drain()
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt(7), lgkmcnt(15)
+}
+
 // Opaque register use: values computed before this point cannot be sunk below it.
 template <int BP>
 __device__ __forceinline__ void pin_row(double (&v)[BP])
@@ -268,19 +278,40 @@ __device__ __forceinline__ void load_rhs(double *dst, const double *src, const d
 
 // Coalesced store of rows [0, rows) x [0, cols) of an LDS block with a row pitch
 // to a row-major global block (rows * cols <= MAXE).
+// Every thread reads all its elements first (indices past the block are clamped
+// to element 0, so the reads need no branch) and only then stores: the block
+// costs one LDS round trip, not one per element.
 template <int NT, int MAXE>
 __device__ __forceinline__ void store_block(double *dst, const double *lds, int pitch, int rows, int cols)
 {
+    constexpr int M = (MAXE + NT - 1) / NT;
     const int n = rows * cols;
     const float invc = 1.0f / (float)cols;
+    double v[M];
 #pragma unroll
-    for (int m = 0; m < (MAXE + NT - 1) / NT; ++m) {
+    for (int m = 0; m < M; ++m) {
         const int e = threadIdx.x + m * NT;
-        if (e < n) {
-            const int r = row_of(e, invc);
-            dst[e] = lds[r * pitch + (e - r * cols)];
-        }
+        const int ec = e < n ? e : 0;
+        const int r = row_of(ec, invc);
+        v[m] = lds[r * pitch + (ec - r * cols)];
     }
+    pin_row<M>(v);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int e = threadIdx.x + m * NT;
+        if (e < n) dst[e] = v[m];
+    }
+}
+
+// A word of zeros in device memory that nothing writes.
+__device__ double zero_word[2];
+
+// src[i] if ok, else 0, with neither a branch nor a select after the load: the
+// address is chosen instead (the zero word when !ok), so the value can stay in
+// flight until it is used.  src is not dereferenced when !ok.
+__device__ __forceinline__ double ld_or_zero(const double *src, int i, bool ok)
+{
+    return *(ok ? src + i : zero_word);
 }
 
 // ---------------------------------------------------------------- elimination
