@@ -56,16 +56,23 @@ template <int RT, int KD, bool TA>
 __device__ __forceinline__ void mm_rhs(const double *A, int pa, const double *B, int nr, dx4 (&acc)[RT], int li,
                                        int lk)
 {
+    // every operand is read before the first product, so the reads overlap
+    constexpr int KS = KD / 4;
+    double bv[KS], av[KS][RT];
 #pragma unroll
-    for (int kk = 0; kk < KD / 4; ++kk) {
+    for (int kk = 0; kk < KS; ++kk) {
         const int k = 4 * kk + lk;
-        const double bv = (li < nr) ? B[k * nr + (li < nr ? li : 0)] : 0.0;
+        bv[kk] = B[k * nr + (li < nr ? li : 0)];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
             const int r = 16 * rt + li;
-            acc[rt] = mfma4(TA ? A[k * pa + r] : A[r * pa + k], bv, acc[rt]);
+            av[kk][rt] = TA ? A[k * pa + r] : A[r * pa + k];
         }
     }
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt] = mfma4(av[kk][rt], li < nr ? bv[kk] : 0.0, acc[rt]);
 }
 
 // Dense LDS layout: a panel area of (2 DB + 16) rows with pitch DB + 1 (the
@@ -243,13 +250,12 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         double *const dummy = L.col + 2 * DB + lane_s;
         *(isP ? buf0 + ri : dummy) = vec[0];
         wave_sync();
+        double col[DB];
+#pragma unroll
+        for (int l = 0; l < DB; ++l) col[l] = buf0[l];
 #pragma unroll
         for (int c = 0; c < DB; ++c) {
-            const double *cur = (c & 1) ? buf1 : buf0;
             double *nxt = (c & 1) ? buf0 : buf1;
-            double col[DB];
-#pragma unroll
-            for (int l = c; l < DB; ++l) col[l] = cur[l];
             const double dcc = col[c];
             bad |= !(dcc > 0.0) || !isfinite(dcc);
             double d, inv;
@@ -261,17 +267,24 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             const double f = act ? v * inv : 0.0;
             vec[c] = (isP && ri == c) ? d : (act ? v : vec[c]);
             if (c + 1 < DB) {
-                // the next pivot column first, so its broadcast overlaps the rest
+                // the next pivot column first: it is written and read back (a wave's
+                // LDS accesses complete in order) before the remaining updates of this
+                // step, which then overlap the round trip
                 vec[c + 1] = fma(-f, col[c + 1], vec[c + 1]);
                 *((isP && ri >= c + 1) ? nxt + ri : dummy) = vec[c + 1];
-                // keep the remaining updates behind the write, so they overlap its round trip
+                wave_sync();
+                double coln[DB];
+#pragma unroll
+                for (int l = c + 1; l < DB; ++l) coln[l] = nxt[l];
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int l = c + 2; l < DB; ++l) vec[l] = fma(-f, col[l], vec[l]);
+#pragma unroll
+                for (int l = c + 1; l < DB; ++l) col[l] = coln[l];
             }
             pin_row<DB>(vec);
-            wave_sync();
         }
+        wave_sync();
         if (bad && !failed) failed = gs + 1;
         // C_i and r_{i+1} have long arrived: retire them here, before this stage's
         // first stores, so that no later use of them waits for outstanding stores
