@@ -34,25 +34,12 @@ __device__ __forceinline__ dx4 mfma4(double a, double b, dx4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// sum_k row[k] * v[k * stride] over k < DB (two partial sums, fully unrolled so
-// every LDS read is issued ahead of the chain).
-template <int DB>
-__device__ __forceinline__ double dot_strided(const double *row, const double *v, int stride)
-{
-    double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-    for (int k = 0; k < DB; k += 2) {
-        s0 = fma(row[k], v[k * stride], s0);
-        s1 = fma(row[k + 1], v[(k + 1) * stride], s1);
-    }
-    return s0 + s1;
-}
-
 // acc[rt] += A B on the FP64 matrix cores for the 16-row tiles rt < RT of A
 // (KD columns) and B = KD x nr (nr <= 16, row pitch nr, columns >= nr taken as
-// zero): A[r][k] = A[r * pa + k], or A[k * pa + r] with TA.  Element v of lane l
-// of acc[rt] is row 16 rt + 4 v + l / 16, column l % 16 of the product.
-template <int RT, int KD, bool TA>
+// zero): A[r][k] = A[r * pa + k], or A[k * pa + r] with TA.  With LOWER, A is
+// lower triangular and the k-chunks right of a tile's last row are skipped.
+// Element v of lane l of acc[rt] is row 16 rt + 4 v + l / 16, column l % 16.
+template <int RT, int KD, bool TA, bool LOWER = false>
 __device__ __forceinline__ void mm_rhs(const double *A, int pa, const double *B, int nr, dx4 (&acc)[RT], int li,
                                        int lk)
 {
@@ -72,7 +59,10 @@ __device__ __forceinline__ void mm_rhs(const double *A, int pa, const double *B,
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk)
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt] = mfma4(av[kk][rt], li < nr ? bv[kk] : 0.0, acc[rt]);
+        for (int rt = 0; rt < RT; ++rt) {
+            if (LOWER && 4 * kk > 16 * rt + 15) continue;
+            acc[rt] = mfma4(av[kk][rt], li < nr ? bv[kk] : 0.0, acc[rt]);
+        }
 }
 
 // Dense LDS layout: a panel area of (2 DB + 16) rows with pitch DB + 1 (the
@@ -312,24 +302,34 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
 #pragma unroll
             for (int rt = 0; rt < TB; ++rt) accE[rt][ct] = dx4{0.0, 0.0, 0.0, 0.0};
         }
-        // B operand: L^{-T}[k][j] = L^{-1}[j][k]
+        // B operand: L^{-T}[k][j] = L^{-1}[j][k], upper triangular: k-chunks past
+        // a tile's last column are zero and skipped.  All operands are read before
+        // the first product.
+        double bo[KS][TB], ga[KS];
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+            ga[kk] = RG[li * PD + 4 * kk + lk];
+#pragma unroll
+            for (int ct = 0; ct < TB; ++ct) bo[kk][ct] = RB[(16 * ct + li) * PD + 4 * kk + lk];
+        }
         if (hasN) {
 #pragma unroll
             for (int kk = 0; kk < KS; ++kk)
 #pragma unroll
                 for (int ct = 0; ct < TB; ++ct) {
-                    const double bo = RB[(16 * ct + li) * PD + 4 * kk + lk];
+                    if (4 * kk > 16 * ct + 15) continue;
 #pragma unroll
-                    for (int rt = 0; rt < TB; ++rt) accE[rt][ct] = mfma4(cA[rt][kk], bo, accE[rt][ct]);
+                    for (int rt = 0; rt < TB; ++rt) accE[rt][ct] = mfma4(cA[rt][kk], bo[kk][ct], accE[rt][ct]);
                 }
         }
         if (ng) {
 #pragma unroll
-            for (int kk = 0; kk < KS; ++kk) {
-                const double ga = RG[li * PD + 4 * kk + lk];
+            for (int kk = 0; kk < KS; ++kk)
 #pragma unroll
-                for (int ct = 0; ct < TB; ++ct) accG[ct] = mfma4(ga, RB[(16 * ct + li) * PD + 4 * kk + lk], accG[ct]);
-            }
+                for (int ct = 0; ct < TB; ++ct) {
+                    if (4 * kk > 16 * ct + 15) continue;
+                    accG[ct] = mfma4(ga[kk], bo[kk][ct], accG[ct]);
+                }
         }
         wave_sync();
 #pragma unroll
@@ -354,10 +354,10 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             for (int kk = 0; kk < KS; ++kk)
 #pragma unroll
                 for (int ct = 0; ct < TB; ++ct) {
-                    const double bo = RB[(16 * ct + li) * PD + 4 * kk + lk];
+                    if (4 * kk > 16 * ct + 15) continue;
 #pragma unroll
                     for (int rt = 0; rt < TB; ++rt)
-                        accF[rt][ct] = mfma4(RF[(16 * rt + li) * PD + 4 * kk + lk], bo, accF[rt][ct]);
+                        accF[rt][ct] = mfma4(RF[(16 * rt + li) * PD + 4 * kk + lk], bo[kk][ct], accF[rt][ct]);
                 }
             wave_sync();
 #pragma unroll
@@ -409,7 +409,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             dx4 accY[TB];
 #pragma unroll
             for (int rt = 0; rt < TB; ++rt) accY[rt] = dx4{0.0, 0.0, 0.0, 0.0};
-            mm_rhs<TB, DB, false>(RB, PD, L.W, nr, accY, li, lk);
+            mm_rhs<TB, DB, false, true>(RB, PD, L.W, nr, accY, li, lk);
             if (li < nr) {
 #pragma unroll
                 for (int rt = 0; rt < TB; ++rt)
@@ -474,29 +474,31 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         for (int ct = 0; ct < TB; ++ct)
 #pragma unroll
             for (int v = 0; v < 4; ++v) accB[ct][v] = bn[ct][v];
+        // every operand is read before the first product
+        double ek[KS][TB], gk[KS];
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+            gk[kk] = RG[li * PD + 4 * kk + lk];
+#pragma unroll
+            for (int t = 0; t < TB; ++t) ek[kk][t] = RA[(16 * t + li) * PD + 4 * kk + lk];
+        }
         if (hasN) {
 #pragma unroll
-            for (int kk = 0; kk < KS; ++kk) {
-                double ek[TB];
-#pragma unroll
-                for (int t = 0; t < TB; ++t) ek[t] = RA[(16 * t + li) * PD + 4 * kk + lk];
+            for (int kk = 0; kk < KS; ++kk)
 #pragma unroll
                 for (int rt = 0; rt < TB; ++rt)
 #pragma unroll
                     for (int ct = 0; ct < TB; ++ct)
-                        if (ct <= rt || (SEG && endS)) accD[rt][ct] = mfma4(-ek[rt], ek[ct], accD[rt][ct]);
-            }
+                        if (ct <= rt || (SEG && endS)) accD[rt][ct] = mfma4(-ek[kk][rt], ek[kk][ct], accD[rt][ct]);
         }
         if (ng) {
 #pragma unroll
             for (int kk = 0; kk < KS; ++kk) {
-                const double gk = RG[li * PD + 4 * kk + lk];
                 if (hasN) {
 #pragma unroll
-                    for (int ct = 0; ct < TB; ++ct)
-                        accB[ct] = mfma4(-gk, RA[(16 * ct + li) * PD + 4 * kk + lk], accB[ct]);
+                    for (int ct = 0; ct < TB; ++ct) accB[ct] = mfma4(-gk[kk], ek[kk][ct], accB[ct]);
                 }
-                accR = mfma4(-gk, gk, accR);
+                accR = mfma4(-gk[kk], gk[kk], accR);
             }
         }
         if (SEG && hasF) {
@@ -514,19 +516,20 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             for (int ct = 0; ct < TB; ++ct)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) accQ[ct][v] = RQ[(4 * v + lk) * PD + 16 * ct + li];
+            double fk[KS][TB];
+#pragma unroll
+            for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+                for (int t = 0; t < TB; ++t) fk[kk][t] = RF[(16 * t + li) * PD + 4 * kk + lk];
 #pragma unroll
             for (int kk = 0; kk < KS; ++kk) {
-                double fk[TB];
-#pragma unroll
-                for (int t = 0; t < TB; ++t) fk[t] = RF[(16 * t + li) * PD + 4 * kk + lk];
-                const double gk = RG[li * PD + 4 * kk + lk];
 #pragma unroll
                 for (int rt = 0; rt < TB; ++rt)
 #pragma unroll
-                    for (int ct = 0; ct < TB; ++ct) accA[rt][ct] = mfma4(-fk[rt], fk[ct], accA[rt][ct]);
+                    for (int ct = 0; ct < TB; ++ct) accA[rt][ct] = mfma4(-fk[kk][rt], fk[kk][ct], accA[rt][ct]);
                 if (ng) {
 #pragma unroll
-                    for (int ct = 0; ct < TB; ++ct) accQ[ct] = mfma4(-gk, fk[ct], accQ[ct]);
+                    for (int ct = 0; ct < TB; ++ct) accQ[ct] = mfma4(-gk[kk], fk[kk][ct], accQ[ct]);
                 }
             }
             dx4 accN[TB][TB];   // -hat B^T hat E^T (next Fw), or -hat E hat B^T (tilde H_k)
@@ -537,18 +540,12 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             if (hasN) {
 #pragma unroll
                 for (int kk = 0; kk < KS; ++kk) {
-                    double fk[TB], ek[TB];
-#pragma unroll
-                    for (int t = 0; t < TB; ++t) {
-                        fk[t] = RF[(16 * t + li) * PD + 4 * kk + lk];
-                        ek[t] = RA[(16 * t + li) * PD + 4 * kk + lk];
-                    }
 #pragma unroll
                     for (int rt = 0; rt < TB; ++rt)
 #pragma unroll
                         for (int ct = 0; ct < TB; ++ct)
-                            accN[rt][ct] = endS ? mfma4(-ek[rt], fk[ct], accN[rt][ct])
-                                                : mfma4(-fk[rt], ek[ct], accN[rt][ct]);
+                            accN[rt][ct] = endS ? mfma4(-ek[kk][rt], fk[kk][ct], accN[rt][ct])
+                                                : mfma4(-fk[kk][rt], ek[kk][ct], accN[rt][ct]);
                 }
             }
             wave_sync();
