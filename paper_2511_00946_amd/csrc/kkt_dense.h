@@ -136,13 +136,13 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
     const int sep = hasF ? sep_of(sd, k) : 0;
     double *sc = F + sd.oScr + (long long)(k - 1) * sd.scrStride;
 
-    // ---- prologue: Dw = sym(D_s0), Gw = B_s0, w = r_s0, y_g partial = 0; for k >= 2
+    // ---- prologue: Dw = D_s0 (sym is taken when it is read), Gw = B_s0, w = r_s0, y_g partial = 0; for k >= 2
     // hat A_k = sym(D_sep), hat Q_k = B_sep, Fw = C_sep^T, separator rhs = r_sep
     {
         const double *D0 = a.D + sd.oD + (long long)s0 * b2;
         for (int e = lane; e < DB * DB; e += NTL) {
             const int r = e / DB, c = e - r * DB;
-            RA[r * PD + c] = (r < b && c < b) ? 0.5 * (D0[r * b + c] + D0[c * b + r]) : (r == c ? 1.0 : 0.0);
+            RA[r * PD + c] = (r < b && c < b) ? D0[r * b + c] : (r == c ? 1.0 : 0.0);   // symmetrized when read
         }
         const double *B0 = a.B + sd.oB + (long long)s0 * ng * b;
         for (int e = lane; e < NGM * DB; e += NTL) {
@@ -229,9 +229,10 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             }
             pin_row<DB>(lo);
             pin_row<DB>(up);
+            // Dw = sym of the block (the Gram term is symmetric already)
 #pragma unroll
             for (int c = 0; c < DB; ++c)
-                vec[c] = isP ? ((c <= ri) ? lo[c] : up[c]) : ((isI && c == ri) ? 1.0 : 0.0);
+                vec[c] = isP ? 0.5 * (lo[c] + up[c]) : ((isI && c == ri) ? 1.0 : 0.0);
         }
         bool bad = false;
         // Every lane writes its column entry each step, the lanes that hold no
@@ -375,20 +376,18 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
 
         phase_fence();
         // ---- next stage's blocks, in flight during the forward substitution
-        // lower tiles (rt >= ct) of sym(D_{i+1}) in accumulator layout
-        constexpr int NLT = TB * (TB + 1) / 2;
-        double dn[NLT][4], dt[NLT][4];
+        // D_{i+1} as stored (all tiles, in accumulator layout: coalesced rows); the
+        // next factorization symmetrizes it when it reads the block
+        double dn[TB][TB][4];
         const double *Dn = a.D + sd.oD + (long long)(gs + 1) * b2;
 #pragma unroll
-        for (int rt = 0, t = 0; rt < TB; ++rt)
+        for (int rt = 0; rt < TB; ++rt)
 #pragma unroll
-            for (int ct = 0; ct <= rt; ++ct, ++t)
+            for (int ct = 0; ct < TB; ++ct)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * rt + 4 * v + lk, c = 16 * ct + li;
-                    const bool in = nextD && r < b && c < b;
-                    dn[t][v] = ld_or_zero(Dn, r * b + c, in);
-                    dt[t][v] = ld_or_zero(Dn, c * b + r, in);
+                    dn[rt][ct][v] = ld_or_zero(Dn, r * b + c, nextD && r < b && c < b);
                 }
         double bn[TB][4];
         const double *Bn = a.B + sd.oB + (long long)(gs + 1) * ng * b;
@@ -457,19 +456,14 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         // arrow accumulator, fill-row products
         dx4 accD[TB][TB], accB[TB];
 #pragma unroll
-        for (int rt = 0, t = 0; rt < TB; ++rt)
+        for (int rt = 0; rt < TB; ++rt)
 #pragma unroll
-            for (int ct = 0; ct < TB; ++ct) {
-                const int tt = ct <= rt ? t : 0;
+            for (int ct = 0; ct < TB; ++ct)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * rt + 4 * v + lk, c = 16 * ct + li;
-                    accD[rt][ct][v] = (ct <= rt && !endS)
-                                          ? ((r < b && c < b) ? 0.5 * (dn[tt][v] + dt[tt][v]) : (r == c ? 1.0 : 0.0))
-                                          : 0.0;
+                    accD[rt][ct][v] = endS ? 0.0 : ((r < b && c < b) ? dn[rt][ct][v] : (r == c ? 1.0 : 0.0));
                 }
-                if (ct <= rt) ++t;
-            }
 #pragma unroll
         for (int ct = 0; ct < TB; ++ct)
 #pragma unroll
@@ -489,7 +483,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                 for (int rt = 0; rt < TB; ++rt)
 #pragma unroll
                     for (int ct = 0; ct < TB; ++ct)
-                        if (ct <= rt || (SEG && endS)) accD[rt][ct] = mfma4(-ek[kk][rt], ek[kk][ct], accD[rt][ct]);
+                        accD[rt][ct] = mfma4(-ek[kk][rt], ek[kk][ct], accD[rt][ct]);
         }
         if (ng) {
 #pragma unroll
@@ -575,7 +569,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
 #pragma unroll
             for (int rt = 0; rt < TB; ++rt)
 #pragma unroll
-                for (int ct = 0; ct <= rt; ++ct)
+                for (int ct = 0; ct < TB; ++ct)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) RA[(16 * rt + 4 * v + lk) * PD + 16 * ct + li] = accD[rt][ct][v];
 #pragma unroll

@@ -160,6 +160,26 @@ def test_ragged_batch_mixed_classes():
     check_solution(plan, x, systems)
 
 
+def test_nonsymmetric_blocks_enter_through_their_symmetric_part():
+    """D_i and the corner enter as sym(.) (the parametrisation of Eq. 3 used here):
+    adding an antisymmetric part to every stored block changes nothing beyond rounding."""
+    rng = np.random.default_rng(31)
+    dims = [(9, 32, 4), (12, 16, 2), (7, 24, 3), (10, 8, 4), (13, 32, 0), (11, 16, 5), (6, 5, 2)]
+    ps = [1, 1, 1, 1, 3, 2, 2]
+    systems = gen(32, dims, nrhs=2)
+    for sysm in systems:
+        K = rng.standard_normal(sysm.D.shape)
+        sysm.D[...] = sysm.D + 0.3 * (K - np.swapaxes(K, 1, 2))
+        if sysm.ng:
+            Kc = rng.standard_normal(sysm.corner.shape)
+            sysm.corner[...] = sysm.corner + 0.3 * (Kc - Kc.T)
+    assert max(float(np.max(np.abs(s.D - np.swapaxes(s.D, 1, 2)))) for s in systems) > 0.1
+    plan, pools, ws, x, info = run(systems, ps, 2)
+    assert (info == 0).all()
+    check_factor(plan, ws, systems)
+    check_solution(plan, x, systems)
+
+
 def test_indefinite_block_reports_info_and_nan():
     dims = [(12, 6, 2), (12, 6, 2), (12, 6, 2), (12, 6, 2)]
     systems = gen(9, dims)
