@@ -266,8 +266,9 @@ def main():
         calib_s = round(time.time() - t_cal, 1)
         log("cost model (measured, %.1fs): %s" % (calib_s, cost_model))
     plan = kkt.Plan([(sy.N, sy.b, sy.ng, max(args.p, 0)) for sy in systems], nrhs=1, cost_model=cost_model)
+    segs = plan.segments()
+    uniform_p = segs[0] if len(set(segs)) == 1 else -1   # the counters apply to one p for all
     if args.p <= 0:
-        segs = plan.segments()
         log("segments chosen: %d systems split, max p %d" % (sum(1 for q in segs if q > 1), max(segs)))
     dp = kkt.pack_to_device(pools, dev)
     ws = plan.new_workspace(dev)
@@ -372,7 +373,7 @@ def main():
     achieved = dom_bytes / (cls_ms[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic(("d%d" if dom_dense else "%d") % dom_bp, args.p, S),
+                "traffic": measured_traffic(("d%d" if dom_dense else "%d") % dom_bp, uniform_p, S),
                 "kernel": {KIND_DENSE: "kkt_dense<%d, factor_solve> + kkt_dense_bwd<%d>" % (dom_db, dom_db),
                            KIND_DSEG: "kkt_dense_seg<%d> + kkt_reduced<%d> + kkt_dense_seg_bwd<%d>"
                                       % (dom_db, dom_bp, dom_db)}.get(
@@ -489,7 +490,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "ragged batch: %d systems, N~U{16..256}, b~U{8,16,32}, ng~U{0,2,4}, 1 rhs, seed 4"
                                % S, "segments": "p=%d" % args.p if args.p > 0 else
-                                     ("cost model measured on this GPU" if args.p == 0 else "default cost model")},
+                                     ("%s cost model: %s" % ("measured" if args.p == 0 else "default",
+                                      "p = %d for every system" % uniform_p if uniform_p > 0 else
+                                      "%d of %d systems split" % (sum(1 for q in segs if q > 1), S)))},
         "plain_systems_per_s": None if plain_sps is None else round(plain_sps, 1),
         "plain_sample": int(len(samp)),
         "batched_vs_plain": None if plain_sps is None else round(value / plain_sps, 2),
