@@ -9,9 +9,13 @@ batches (the library's own kernels, one persistent launch per class):
             (a batch of `workers` systems, p = 1, timed at horizons 8 and 24)
   t_fill    per-stage time of a segment carrying fill rows under full load
             (workers_seg / 2 systems with p = 2 and a one-stage first segment)
-  t_red     per-stage time of the reduced chain (a single system at large p,
-            minus its segments), floored at t_first
   t_item    fixed cost of an item (intercept of the p = 1 fit)
+  t_fill    sigma * t_first, and
+  t_red     rho * t_first, where sigma (a stage of a fill-carrying segment over
+            a stage of a first segment) and rho (a stage of the reduced chain over
+            a first-segment stage) come from the latency of single systems:
+            N = 97 with the first or the second segment one stage long, and
+            N = 127 cut into 64 one-stage segments
 The result is cached as JSON per GPU architecture.  The chooser itself
 (makespan = max(total work / workers, longest item)) runs in the C library.
 """
@@ -73,15 +77,23 @@ def calibrate(verbose=False):
         t2, _ = _time_batch([(24, b, 2, 1)] * W)
         t_first = max((t2 - t1) / 16.0, 1e-6)
         t_item = max(t1 - 8 * t_first, 0.0)
-        tf, _ = _time_batch([(18, b, 2, 2, 1)] * (Ws // 2))         # N1 = 1, Nk = 16 with fill rows
-        t_fill = max((tf - t_item) / 16.0, t_first)
-        ts, _ = _time_batch([(65, b, 2, 32)])                       # 32 short segments, 31 reduced stages
-        t_red = max((ts - t_item - 2 * t_fill) / 31.0, t_first)
+        # stage-cost ratios from single-system latencies
+        l33, _ = _time_batch([(33, b, 2, 1)], reps=5)
+        l97, _ = _time_batch([(97, b, 2, 1)], reps=5)
+        a = max((l97 - l33) / 64.0, 1e-6)                           # latency of a first-segment stage
+        t0 = max(l33 - 33 * a, 0.0)
+        lf, _ = _time_batch([(97, b, 2, 2, 1)], reps=5)             # N1 = 1, Nk = 95 (fill rows)
+        lh, _ = _time_batch([(97, b, 2, 2, 95)], reps=5)            # N1 = 95, Nk = 1
+        sigma = min(max(1.0 + (lf - lh) / (94.0 * a), 1.0), 8.0)
+        lr, _ = _time_batch([(127, b, 2, 64, 1)], reps=5)           # 64 one-stage segments
+        rho = max((lr - t0 - max(1.0, sigma) * a) / (63.0 * a), 0.1)
+        t_fill, t_red = sigma * t_first, rho * t_first
         model["t_first"][c], model["t_fill"][c], model["t_red"][c] = t_first, t_fill, t_red
         model["t_item"][c], model["workers"][c], model["workers_seg"][c] = t_item, float(W), float(Ws)
         if verbose:
-            print("class %2d: workers %d / %d t_first %.4f t_fill %.4f t_red %.4f t_item %.4f (ms)"
-                  % (bp, W, Ws, t_first, t_fill, t_red, t_item), flush=True)
+            print("class %2d: workers %d / %d t_first %.4f t_fill %.4f t_red %.4f t_item %.4f (ms); "
+                  "latency per stage %.4f, sigma %.2f, rho %.2f"
+                  % (bp, W, Ws, t_first, t_fill, t_red, t_item, a, sigma, rho), flush=True)
     return model
 
 
