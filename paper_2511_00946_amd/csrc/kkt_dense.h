@@ -65,6 +65,35 @@ __device__ __forceinline__ void mm_rhs(const double *A, int pa, const double *B,
         }
 }
 
+// sum over k < KD of A(row, k) B[k] for a single rhs on the vector units, one row
+// per lane, A(row, k) = A[row pa + k], or A[k pa + row] with TA.  With one rhs a
+// 16-column MFMA tile would spend 15 of its columns on nothing; here the row and
+// the vector are read CH entries at a time (every lane reads the vector at the
+// same address) and summed in four chains.
+template <int KD, bool TA, int CH = 16>
+__device__ __forceinline__ double row_dot1(const double *A, int pa, int row, const double *B)
+{
+    static_assert(KD % CH == 0 && CH % 4 == 0, "rows are read in chunks of CH");
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+    for (int k0 = 0; k0 < KD; k0 += CH) {
+        double av[CH], bv[CH];
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+            av[t] = TA ? A[(k0 + t) * pa + row] : A[row * pa + k0 + t];
+            bv[t] = B[k0 + t];
+        }
+#pragma unroll
+        for (int t = 0; t < CH; t += 4) {
+            s0 = fma(av[t], bv[t], s0);
+            s1 = fma(av[t + 1], bv[t + 1], s1);
+            s2 = fma(av[t + 2], bv[t + 2], s2);
+            s3 = fma(av[t + 3], bv[t + 3], s3);
+        }
+    }
+    return (s0 + s1) + (s2 + s3);
+}
+
 // Dense LDS layout: a panel area of (2 DB + 16) rows with pitch DB + 1 (the
 // backward sweep and the corner reuse it as their staging area), then the same
 // small vectors as the general layout.  Regions the p = 1 path never touches
@@ -205,6 +234,8 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                     rn[rt][v] = ld_or_zero(rs, r * nr + li, nextD && r < b && li < nr);
                 }
         }
+        // the same for a single rhs, row lane_s
+        const double rn1 = FWD ? ld_or_zero(a.rhs + sd.oRhs + (long long)(gs + 1) * b, lane_s, nextD && lane_s < b) : 0.0;
         double cA[TB][KS];
         const double *Ci = a.C + sd.oC + (long long)gs * b2;
 #pragma unroll
@@ -403,7 +434,29 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         // ---- (4) forward substitution: y = L^{-1} w, w' = r_{i+1} - hat E y, y_g -= hat G y
         // (at a segment end the scratch gets -hat F_k y instead of w'; with fill rows
         // the separator rhs -= hat B^T y)
-        if (FWD) {
+        if (FWD && nr == 1) {
+            // one rhs: y = L^{-1} w on the row lanes, then hat E y (or hat F_k y) and,
+            // with fill rows, hat B^T y on the row lanes and hat G y on the next 16 lanes
+            const int r = lane_s;
+            const bool rowL = r < DB, gl = r >= DB && r < DB + NGM;
+            const int q = r - DB;
+            const double yv = row_dot1<DB, false>(RB, PD, rowL ? r : 0, L.W);
+            if (rowL) L.Y[r] = yv;
+            wave_sync();
+            const double ev = row_dot1<DB, false>(rowL ? RA : RG, PD, rowL ? r : (gl ? q : 0), L.Y);
+            const double sv = (SEG && hasF) ? row_dot1<DB, false>(RF, PD, rowL ? r : 0, L.Y) : 0.0;
+            wave_sync();
+            if (rowL) {
+                if (endS) {
+                    if (r < b) sc[scr_dy(b, ng, 1) + r] = -ev;
+                } else {
+                    L.W[r] = (r < b) ? rn1 - ev : 0.0;
+                }
+                if (SEG && hasF && r < b) L.XS[r] -= sv;
+            } else if (gl && q < ng) {
+                L.XG[q] -= ev;
+            }
+        } else if (FWD) {
             // y = L^{-1} w, then hat E y and hat G y, all rhs at once on the matrix cores
             dx4 accY[TB];
 #pragma unroll
@@ -449,7 +502,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                     if (q < ng) L.XG[q * nr + li] -= accG1[0][v];
                 }
             }
-        }
+                }
 
         phase_fence();
         // ---- (5) Gram: next Dw and Gw (or, at a segment end, the scratch products),
@@ -787,30 +840,44 @@ __device__ __forceinline__ void dense_forward(const Args &a, const SysDesc &sd, 
             }
             wave_sync();
         }
-        // hat E y and hat G y for all rhs on the matrix cores
-        const int li = lane_s & 15, lk = lane_s >> 4;
-        constexpr int TB = DB / 16;
-        dx4 accW[TB], accG1[1];
-#pragma unroll
-        for (int rt = 0; rt < TB; ++rt) accW[rt] = dx4{0.0, 0.0, 0.0, 0.0};
-        accG1[0] = dx4{0.0, 0.0, 0.0, 0.0};
-        if (hasN) mm_rhs<TB, DB, false>(stE, PD, L.Y, nr, accW, li, lk);
-        if (ng) mm_rhs<1, DB, false>(stG, PD, L.Y, nr, accG1, li, lk);
-        wave_sync();
-        if (li < nr) {
-            if (hasN) {
-#pragma unroll
-                for (int rt = 0; rt < TB; ++rt)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) L.XN[(16 * rt + 4 * v + lk) * nr + li] = accW[rt][v];
+        if (nr == 1) {
+            // one rhs: hat E y on the row lanes, hat G y on the next 16 lanes
+            const bool rowL = r < DB, gl = r >= DB && r < DB + NGM;
+            const int q = r - DB;
+            const double ev = row_dot1<DB, false>(rowL ? stE : stG, PD, rowL ? r : (gl ? q : 0), L.Y);
+            wave_sync();
+            if (rowL) {
+                if (hasN) L.XN[r] = ev;
+            } else if (gl && q < ng) {
+                L.XG[q] -= ev;
             }
+            wave_sync();
+        } else {
+            // hat E y and hat G y for all rhs on the matrix cores
+            const int li = lane_s & 15, lk = lane_s >> 4;
+            constexpr int TB = DB / 16;
+            dx4 accW[TB], accG1[1];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int q = 4 * v + lk;
-                if (q < ng) L.XG[q * nr + li] -= accG1[0][v];
+            for (int rt = 0; rt < TB; ++rt) accW[rt] = dx4{0.0, 0.0, 0.0, 0.0};
+            accG1[0] = dx4{0.0, 0.0, 0.0, 0.0};
+            if (hasN) mm_rhs<TB, DB, false>(stE, PD, L.Y, nr, accW, li, lk);
+            if (ng) mm_rhs<1, DB, false>(stG, PD, L.Y, nr, accG1, li, lk);
+            wave_sync();
+            if (li < nr) {
+                if (hasN) {
+#pragma unroll
+                    for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) L.XN[(16 * rt + 4 * v + lk) * nr + li] = accW[rt][v];
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int q = 4 * v + lk;
+                    if (q < ng) L.XG[q * nr + li] -= accG1[0][v];
+                }
             }
+            wave_sync();
         }
-        wave_sync();
         // w_{i+1} = r_{i+1} - hat E y (r_{i+1} is in flight in pf.y)
         if (hasN) {
 #pragma unroll
@@ -891,7 +958,17 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
             dcol[l] = (cv && l < b) ? v : (l == c ? 1.0 : 0.0);
         }
         const double dinv = cv ? 1.0 / stD[c * PD + c] : 1.0;
-        {
+        if (nr == 1) {
+            // one rhs: column c of each block on lane c, on the vector units
+            const int cc = c < DB ? c : 0;
+            double t = 0.0;
+            // (short chunks: this sweep holds the next stage's blocks in registers)
+            constexpr int CH = ADJ ? 4 : 8;
+            if (hasE) t += row_dot1<DB, true, CH>(stE, PD, cc, L.XN);
+            if (ng) t += row_dot1<NGM, true, CH>(stG, PD, cc, L.XG);
+            if (SEG && hasF) t += row_dot1<DB, true, CH>(stF, PD, cc, L.XS);
+            if (c < DB) L.Y[c] = t;
+        } else {
             // hat E^T x_{i+1} + hat G^T x_g (+ hat B x_sep) for all rhs on the matrix cores, into Y
             const int li = lane_s & 15, lk = lane_s >> 4;
             constexpr int TB = DB / 16;
