@@ -34,6 +34,37 @@ __device__ __forceinline__ dx4 mfma4(double a, double b, dx4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Lane mapping of a tile with DB columns handled by one 64-lane wave: lane l holds
+// column l % DB of the rows l / DB + (64 / DB) m, so every LDS offset is a
+// compile-time immediate and each row of a row-major global block is one
+// contiguous access.
+template <int DB>
+struct TileMap {
+    static constexpr int RS = 64 / DB;   // rows per pass
+    int c, r0;
+    __device__ __forceinline__ explicit TileMap(int lane) : c(lane & (DB - 1)), r0(lane / DB) {}
+    __device__ __forceinline__ int row(int m) const { return r0 + RS * m; }
+};
+
+// Rows [0, rows) x columns [0, cols) of an LDS tile of ROWS rows (pitch DB + 1) to
+// a row-major global block: every read first, then the predicated stores.
+template <int DB, int ROWS>
+__device__ __forceinline__ void store_tile(double *dst, const double *lds, int rows, int cols, int lane)
+{
+    constexpr int PD = DB + 1, M = ROWS / TileMap<DB>::RS;
+    const TileMap<DB> t(lane);
+    double v[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = lds[t.row(m) * PD + t.c];
+    pin_row<M>(v);
+    const bool cin = t.c < cols;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int r = t.row(m);
+        if (cin && r < rows) dst[r * cols + t.c] = v[m];
+    }
+}
+
 // acc[rt] += A B on the FP64 matrix cores for the 16-row tiles rt < RT of A
 // (KD columns) and B = KD x nr (nr <= 16, row pitch nr, columns >= nr taken as
 // zero): A[r][k] = A[r * pa + k], or A[k * pa + r] with TA.  With LOWER, A is
@@ -322,7 +353,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             for (int r = 0; r < DB; ++r) RB[r * PD + ri] = (r >= ri) ? vec[r] : 0.0;
         }
         wave_sync();
-        store_block<NTL, DB * DB>(F + sd.oLd + (long long)gs * b2, RA, PD, b, b);
+        store_tile<DB, DB>(F + sd.oLd + (long long)gs * b2, RA, b, b, lane_s);
         wave_sync();
 
         phase_fence();
@@ -374,8 +405,8 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                 RG[(4 * v + lk) * PD + c] = accG[ct][v];
             }
         wave_sync();
-        if (hasN) store_block<NTL, DB * DB>(F + sd.oLc + (long long)gs * b2, RA, PD, b, b);
-        if (ng) store_block<NTL, NGM * DB>(F + sd.oLb + (long long)gs * ng * b, RG, PD, ng, b);
+        if (hasN) store_tile<DB, DB>(F + sd.oLc + (long long)gs * b2, RA, b, b, lane_s);
+        if (ng) store_tile<DB, NGM>(F + sd.oLb + (long long)gs * ng * b, RG, ng, b, lane_s);
         if (SEG && hasF) {
             dx4 accF[TB][TB];
 #pragma unroll
@@ -402,7 +433,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             // the first fill block sits in the coupling slot of the separator
             double *dst = (i == 0) ? F + sd.oLc + (long long)sep * b2
                                    : F + sd.oFill + ((long long)(k - 2) * (sd.Nk - 1) + (i - 1)) * b2;
-            store_block<NTL, DB * DB>(dst, RF, PD, b, b);
+            store_tile<DB, DB>(dst, RF, b, b, lane_s);
         }
 
         phase_fence();
@@ -676,8 +707,9 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
     return failed;
 }
 
-// Factor blocks and y of stage i, fetched into registers (element e = lane + 64 m
-// of each row-major block).
+// Factor blocks and y of stage i, fetched into registers: the blocks in the tile
+// mapping (entries outside a block fetched as zeros), the rhs rows as element
+// e = lane + 64 m.
 template <int DB>
 struct BwdStage {
     static constexpr int NTL = 64, MD = DB * DB / NTL, MG = NGM * DB / NTL,
@@ -691,26 +723,20 @@ struct BwdStage {
         const long long b2 = (long long)b * b;
         const double *src = (il == 0) ? a.F + sd.oLc + (long long)sep_of(sd, k) * b2
                                       : a.F + sd.oFill + ((long long)(k - 2) * (sd.Nk - 1) + (il - 1)) * b2;
+        const TileMap<DB> t(lane);
 #pragma unroll
         for (int m = 0; m < MD; ++m) {
-            const int x = lane + m * NTL;
-            f[m] = ld_or_zero(src, x, x < b * b);
+            const int r = t.row(m);
+            f[m] = ld_or_zero(src, r * b + t.c, r < b && t.c < b);
         }
     }
 
     __device__ __forceinline__ void stage_fill(const SysDesc &sd, double *stF, int lane) const
     {
         constexpr int PD = DB + 1;
-        const int b = sd.b;
-        const float invb = 1.0f / (float)b;
+        const TileMap<DB> t(lane);
 #pragma unroll
-        for (int m = 0; m < MD; ++m) {
-            const int x = lane + m * NTL;
-            if (x < b * b) {
-                const int r = row_of(x, invb), c = x - r * b;
-                stF[r * PD + c] = f[m];
-            }
-        }
+        for (int m = 0; m < MD; ++m) stF[t.row(m) * PD + t.c] = f[m];   // zeros outside the block
     }
 
     // with PRIMAL, also the primal solution of stage i (adjoint gradients)
@@ -722,16 +748,18 @@ struct BwdStage {
         const bool hasE = i + 1 < sd.N;
         const double *Ld = a.F + sd.oLd + (long long)i * b2, *Lc = a.F + sd.oLc + (long long)i * b2;
         const double *Lb = a.F + sd.oLb + (long long)i * ng * b, *Y = a.rhs + sd.oRhs + (long long)i * b * nr;
+        const TileMap<DB> t(lane);
 #pragma unroll
         for (int m = 0; m < MD; ++m) {
-            const int x = lane + m * NTL;
-            d[m] = ld_or_zero(Ld, x, x < b * b);
-            e[m] = ld_or_zero(Lc, x, hasE && x < b * b);
+            const int r = t.row(m);
+            const bool in = r < b && t.c < b;
+            d[m] = ld_or_zero(Ld, r * b + t.c, in);
+            e[m] = ld_or_zero(Lc, r * b + t.c, hasE && in);
         }
 #pragma unroll
         for (int m = 0; m < MG; ++m) {
-            const int x = lane + m * NTL;
-            g[m] = ld_or_zero(Lb, x, x < ng * b);
+            const int q = t.row(m);
+            g[m] = ld_or_zero(Lb, q * b + t.c, q < ng && t.c < b);
         }
 #pragma unroll
         for (int m = 0; m < MY; ++m) {
@@ -753,25 +781,16 @@ struct BwdStage {
                                           int lane) const
     {
         constexpr int PD = DB + 1;
-        const int b = sd.b, ng = sd.ng;
-        const float invb = 1.0f / (float)b;
+        const int b = sd.b;
+        const TileMap<DB> t(lane);
+        // whole tiles: the entries outside the blocks were fetched as zeros
 #pragma unroll
         for (int m = 0; m < MD; ++m) {
-            const int x = lane + m * NTL;
-            if (x < b * b) {
-                const int r = row_of(x, invb), c = x - r * b;
-                stD[r * PD + c] = d[m];
-                stE[r * PD + c] = e[m];
-            }
+            stD[t.row(m) * PD + t.c] = d[m];
+            stE[t.row(m) * PD + t.c] = e[m];
         }
 #pragma unroll
-        for (int m = 0; m < MG; ++m) {
-            const int x = lane + m * NTL;
-            if (x < ng * b) {
-                const int r = row_of(x, invb), c = x - r * b;
-                stG[r * PD + c] = g[m];
-            }
-        }
+        for (int m = 0; m < MG; ++m) stG[t.row(m) * PD + t.c] = g[m];
 #pragma unroll
         for (int m = 0; m < MY; ++m) {
             const int x = lane + m * NTL;
