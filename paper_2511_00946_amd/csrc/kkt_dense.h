@@ -394,6 +394,30 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                     accG[ct] = mfma4(ga[kk], bo[kk][ct], accG[ct]);
                 }
         }
+        // hat E and hat G go to the factor straight from the accumulators (each
+        // element v of a tile is 4 rows of 16 consecutive entries)
+        if (hasN) {
+            double *dE = F + sd.oLc + (long long)gs * b2;
+#pragma unroll
+            for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < TB; ++ct)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * rt + 4 * v + lk, c = 16 * ct + li;
+                        if (r < b && c < b) dE[r * b + c] = accE[rt][ct][v];
+                    }
+        }
+        if (ng) {
+            double *dG = F + sd.oLb + (long long)gs * ng * b;
+#pragma unroll
+            for (int ct = 0; ct < TB; ++ct)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int q = 4 * v + lk, c = 16 * ct + li;
+                    if (q < ng && c < b) dG[q * b + c] = accG[ct][v];
+                }
+        }
         wave_sync();
 #pragma unroll
         for (int ct = 0; ct < TB; ++ct)
@@ -405,8 +429,6 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                 RG[(4 * v + lk) * PD + c] = accG[ct][v];
             }
         wave_sync();
-        if (hasN) store_tile<DB, DB>(F + sd.oLc + (long long)gs * b2, RA, b, b, lane_s);
-        if (ng) store_tile<DB, NGM>(F + sd.oLb + (long long)gs * ng * b, RG, ng, b, lane_s);
         if (SEG && hasF) {
             dx4 accF[TB][TB];
 #pragma unroll
