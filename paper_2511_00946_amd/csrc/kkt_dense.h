@@ -125,6 +125,23 @@ __device__ __forceinline__ double row_dot1(const double *A, int pa, int row, con
     return (s0 + s1) + (s2 + s3);
 }
 
+// x[c] of T^T x = rhs for a lower triangular T, lane c holding accs = rhs[c] / T[c][c]
+// and dcs[l] = T[l][c] / T[c][c]: with the scaling done beforehand the serial chain
+// is one broadcast and one FMA per column.
+template <int DB>
+__device__ __forceinline__ double back_subst_scaled(const double (&dcs)[DB], double accs)
+{
+    const int lane = threadIdx.x;
+    double xv = 0.0;
+#pragma unroll
+    for (int c2 = DB - 1; c2 >= 0; --c2) {
+        const double x2 = readlane_d(accs, c2);
+        if (lane == c2) xv = x2;
+        accs = fma(-dcs[c2], x2, accs);
+    }
+    return xv;
+}
+
 // Dense LDS layout: a panel area of (2 DB + 16) rows with pitch DB + 1 (the
 // backward sweep and the corner reuse it as their staging area), then the same
 // small vectors as the general layout.  Regions the p = 1 path never touches
@@ -999,6 +1016,9 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
             dcol[l] = (cv && l < b) ? v : (l == c ? 1.0 : 0.0);
         }
         const double dinv = cv ? 1.0 / stD[c * PD + c] : 1.0;
+        double dcs[DB];
+#pragma unroll
+        for (int l = 0; l < DB; ++l) dcs[l] = dcol[l] * dinv;
         if (nr == 1) {
             // one rhs: column c of each block on lane c, on the vector units
             const int cc = c < DB ? c : 0;
@@ -1029,7 +1049,7 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
         wave_sync();
         for (int j = 0; j < nr; ++j) {
             const double acc = cv ? L.XC[c * nr + j] - L.Y[c * nr + j] : 0.0;
-            const double xv = back_subst<DB>(dcol, acc, dinv);
+            const double xv = back_subst_scaled<DB>(dcs, acc * dinv);
             wave_sync();
             if (cv) L.XC[c * nr + j] = xv;
             wave_sync();
