@@ -60,6 +60,35 @@ class HipEvents:
         return float(ms.value)
 
 
+def _oracle_worker(job):
+    """One worker of the all-cores oracle baseline (its own process): the oracle's
+    factor + solve over the systems idx of the ragged batch of S systems, timed."""
+    S, idx = job
+    from oracle import kkt as okkt
+    from paper_2511_00946_amd import workloads
+    spec = workloads.ragged_batch_spec(S=S)
+    systems = [spec.system(i) for i in idx]
+    t = time.perf_counter()
+    for sy in systems:
+        okkt.solve(sy.D, sy.C, sy.B, sy.corner, sy.r)
+    return time.perf_counter() - t
+
+
+def oracle_all_cores(S, csamp, max_workers=16):
+    """The same oracle sample spread over the host's cores, one process per core
+    (the systems are independent; no parallelism inside a system).  Returns
+    (systems/s, workers) with the rate taken over the slowest worker."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    n = max(1, min(len(os.sched_getaffinity(0)), max_workers, len(csamp)))
+    jobs = [(S, [int(i) for i in csamp[w::n]]) for w in range(n)]
+    # fresh interpreters (spawn), never forks of this process; a worker that dies
+    # raises here instead of leaving the pool waiting
+    with ProcessPoolExecutor(n, mp_context=mp.get_context("spawn")) as pool:
+        times = list(pool.map(_oracle_worker, jobs, timeout=600))
+    return len(csamp) / max(times), n
+
+
 def build_pools(spec, idx=None):
     """Pack systems (all, or the index list idx) of a BatchSpec into numpy pools."""
     from paper_2511_00946_amd import workloads
@@ -220,6 +249,8 @@ def main():
     ap.add_argument("--systems", type=int, default=4096)
     ap.add_argument("--plain-sample", type=int, default=512)
     ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--skip-oracle-all-cores", action="store_true",
+                    help="time the oracle on one core only")
     ap.add_argument("--p", type=int, default=0,
                     help="segments per system (1 = sequential; 0 = chosen by the cost model measured on this GPU; "
                          "-1 = chosen by the default flop-ratio model)")
@@ -278,6 +309,7 @@ def main():
     kinds = plan.class_kinds()
     log("plan: %d items, classes %s, workspace %.2f GB" % (plan.info.num_items, classes,
         plan.info.workspace_bytes / 1e9))
+    step_flops = float(plan.info.factor_flops + plan.info.solve_flops)   # standard counts, one step
 
     def step():
         x.copy_(dp["r"])
@@ -296,12 +328,16 @@ def main():
     lib = ctypes.CDLL("libamdhip64.so")
     lib.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.hipEventRecord(ctypes.c_void_p(start), ctypes.c_void_p(st.cuda_stream))
+    step_ev = [ev.create() for _ in range(K + 1)]
     for k in range(K):
+        lib.hipEventRecord(ctypes.c_void_p(step_ev[k]), ctypes.c_void_p(st.cuda_stream))
         for c in range(len(classes)):
             plan.set_class_events(c, cls_ev[k][c][0], cls_ev[k][c][1])
         step()
+    lib.hipEventRecord(ctypes.c_void_p(step_ev[K]), ctypes.c_void_p(st.cuda_stream))
     lib.hipEventRecord(ctypes.c_void_p(stop), ctypes.c_void_p(st.cuda_stream))
     torch.cuda.synchronize()
+    step_ms = [ev.elapsed_ms(step_ev[k], step_ev[k + 1]) for k in range(K)]
     for c in range(len(classes)):
         plan.set_class_events(c, None, None)
     total_ms = ev.elapsed_ms(start, stop)
@@ -418,6 +454,12 @@ def main():
     cpu_s = time.perf_counter() - t1
     cpu_sps = len(csamp) / cpu_s if len(csamp) else None
     log("oracle: %d systems in %.1fs -> %s systems/s" % (len(csamp), cpu_s, cpu_sps))
+    cpu_all = None
+    if len(csamp) and not args.skip_oracle_all_cores:
+        sps_all, nw = oracle_all_cores(S, csamp)
+        cpu_all = {"value": round(sps_all, 2), "unit": "systems/s", "cores": nw, "kind": "oracle",
+                   "sample": "the same %d systems, one process per core over systems" % len(csamp)}
+        log("oracle on %d cores: %.1f systems/s" % (nw, sps_all))
 
     del dp, ws, x, info
     torch.cuda.empty_cache()
@@ -483,6 +525,7 @@ def main():
         "steps": K,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step_std": round(float(np.std(step_ms)), 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -507,6 +550,10 @@ def main():
         "cpu_baseline": {"value": None if cpu_sps is None else round(cpu_sps, 2), "unit": "systems/s", "cores": 1,
                          "kind": "oracle",
                          "sample": "%d random systems of the batch, factor + solve each" % len(csamp)},
+        "cpu_baseline_all_cores": cpu_all,
+        "fp64": {"achieved_tflops": round(step_flops / (ms_per_step * 1e-3) / 1e12, 4), "peak_tflops": 78.6,
+                 "frac": round(step_flops / (ms_per_step * 1e-3) / 1e12 / 78.6, 5),
+                 "flops_per_step": step_flops},
     }
     print(json.dumps(out), flush=True)
 
