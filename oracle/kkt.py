@@ -16,7 +16,7 @@ lists the segment stages first (segment 1, then 2, ...), then the separators
 (``blockchol``); p = 1 is the sequential method the paper compares against
 (Sec. 3.3, O_seq).
 
-Readings where the paper is silent (listed in the design doc as well):
+Readings where the paper is silent:
   * failure: ``info`` is the 1-based natural stage index of the first diagonal
     block, in elimination order, whose pivot is not positive and finite; N + 1
     names the corner.  The paper does not discuss indefinite input.

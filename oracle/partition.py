@@ -9,7 +9,7 @@ other segments all get the same length N_k, rounded from the ideal value
 to whichever of floor / ceil gives the smaller max{7/3 N_1, 19/3 N_k}, with
 N_1 = N - (p - 1) - (p - 1) N_k (Eq. 13: N_1 + (p-1) N_k + p - 1 = N).
 
-Readings (the paper is garbled or silent here; also listed in the design doc):
+Readings (the paper is garbled or silent here):
   * the denominator is (p - 1 + sigma).  The printed (p + sigma) does not give the
     numbers of Table 2; (p - 1 + sigma) follows from N_1 = sigma N_k and
     N_1 + (p-1) N_k = N - p + 1, and reproduces Table 2.
