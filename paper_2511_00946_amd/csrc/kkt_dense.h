@@ -34,6 +34,15 @@ __device__ __forceinline__ dx4 mfma4(double a, double b, dx4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Four independent 4x4x4 FP64 products per instruction (lane layout probed on
+// gfx950: with lane l = x + 4 blk + 16 y, A[blk][x][y], B[blk][y][x] and
+// D[blk][y][x] are held by lane l).  Used for the arrow rows when there are at
+// most four of them, where a 16-row tile would be mostly padding.
+__device__ __forceinline__ double mfma44(double a, double b, double c)
+{
+    return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
 // Lane mapping of a tile with DB columns handled by one 64-lane wave: lane l holds
 // column l % DB of the rows l / DB + (64 / DB) m, so every LDS offset is a
 // compile-time immediate and each row of a row-major global block is one
@@ -253,6 +262,10 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
     wave_sync();
 
     dx4 accR = {0.0, 0.0, 0.0, 0.0};
+    double accR4 = 0.0;                 // the same on 4x4 tiles (ng <= 4), partial per block
+    // at most four arrow rows: hat G, hat G hat E^T and hat G hat G^T on 4x4 tiles
+    const bool g4 = sd.ng > 0 && sd.ng <= 4;
+    constexpr int T4 = DB / 16;         // 4x4x4 instructions per k-chunk (4 column blocks each)
     int failed = 0;
     for (int i = 0; i < len; ++i) {
         const int gs = s0 + i;
@@ -402,7 +415,27 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                     for (int rt = 0; rt < TB; ++rt) accE[rt][ct] = mfma4(cA[rt][kk], bo[kk][ct], accE[rt][ct]);
                 }
         }
-        if (ng) {
+        const int x4 = lane_s & 3, k4 = (lane_s >> 2) & 3, y4 = lane_s >> 4;
+        double accG4[T4];
+#pragma unroll
+        for (int t = 0; t < T4; ++t) accG4[t] = 0.0;
+        if (g4) {
+            // hat G[y4][4 (4 t + k4) + x4] per lane: A = Gw[x4][4 kc + y4], B = L^{-1} rows
+            double av[KS], bv[KS][T4];
+#pragma unroll
+            for (int kc = 0; kc < KS; ++kc) {
+                av[kc] = RG[x4 * PD + 4 * kc + y4];
+#pragma unroll
+                for (int t = 0; t < T4; ++t) bv[kc][t] = RB[(4 * (4 * t + k4) + x4) * PD + 4 * kc + y4];
+            }
+#pragma unroll
+            for (int kc = 0; kc < KS; ++kc)
+#pragma unroll
+                for (int t = 0; t < T4; ++t) {
+                    if (kc > 4 * t + 3) continue;   // L^{-T} is zero there for all four blocks
+                    accG4[t] = mfma44(av[kc], bv[kc][t], accG4[t]);
+                }
+        } else if (ng) {
 #pragma unroll
             for (int kk = 0; kk < KS; ++kk)
 #pragma unroll
@@ -425,7 +458,14 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                         if (r < b && c < b) dE[r * b + c] = accE[rt][ct][v];
                     }
         }
-        if (ng) {
+        if (g4) {
+            double *dG = F + sd.oLb + (long long)gs * ng * b;
+#pragma unroll
+            for (int t = 0; t < T4; ++t) {
+                const int c = 4 * (4 * t + k4) + x4;
+                if (y4 < ng && c < b) dG[y4 * b + c] = accG4[t];
+            }
+        } else if (ng) {
             double *dG = F + sd.oLb + (long long)gs * ng * b;
 #pragma unroll
             for (int ct = 0; ct < TB; ++ct)
@@ -443,8 +483,17 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                 const int c = 16 * ct + li;
 #pragma unroll
                 for (int rt = 0; rt < TB; ++rt) RA[(16 * rt + 4 * v + lk) * PD + c] = accE[rt][ct][v];
-                RG[(4 * v + lk) * PD + c] = accG[ct][v];
             }
+        if (g4) {
+            // rows 0..3 of the arrow tile (the rows below stay zero)
+#pragma unroll
+            for (int t = 0; t < T4; ++t) RG[y4 * PD + 4 * (4 * t + k4) + x4] = accG4[t];
+        } else {
+#pragma unroll
+            for (int ct = 0; ct < TB; ++ct)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) RG[(4 * v + lk) * PD + 16 * ct + li] = accG[ct][v];
+        }
         wave_sync();
         if (SEG && hasF) {
             dx4 accF[TB][TB];
@@ -499,6 +548,12 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                 const int q = 4 * v + lk, c = 16 * ct + li;
                 bn[ct][v] = ld_or_zero(Bn, q * b + c, nextD && q < ng && c < b);
             }
+        double bn4[T4];
+#pragma unroll
+        for (int t = 0; t < T4; ++t) {
+            const int c = 4 * (4 * t + k4) + x4;
+            bn4[t] = ld_or_zero(Bn, y4 * b + c, g4 && nextD && y4 < ng && c < b);
+        }
 
         phase_fence();
         // ---- (4) forward substitution: y = L^{-1} w, w' = r_{i+1} - hat E y, y_g -= hat G y
@@ -608,7 +663,32 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                     for (int ct = 0; ct < TB; ++ct)
                         accD[rt][ct] = mfma4(-ek[kk][rt], ek[kk][ct], accD[rt][ct]);
         }
-        if (ng) {
+        double accB4[T4];
+#pragma unroll
+        for (int t = 0; t < T4; ++t) accB4[t] = bn4[t];
+        if (g4) {
+            // A = hat G[x4][4 kc + y4]; next Gw -= hat G hat E^T (B = hat E rows), and
+            // hat G hat G^T with k-chunk 4 s + k4 in block k4 (summed over the blocks
+            // at the end of the sweep)
+            double gv[KS], evv[KS][T4];
+#pragma unroll
+            for (int kc = 0; kc < KS; ++kc) {
+                gv[kc] = RG[x4 * PD + 4 * kc + y4];
+#pragma unroll
+                for (int t = 0; t < T4; ++t) evv[kc][t] = RA[(4 * (4 * t + k4) + x4) * PD + 4 * kc + y4];
+            }
+            if (hasN) {
+#pragma unroll
+                for (int kc = 0; kc < KS; ++kc)
+#pragma unroll
+                    for (int t = 0; t < T4; ++t) accB4[t] = mfma44(-gv[kc], evv[kc][t], accB4[t]);
+            }
+#pragma unroll
+            for (int sc4 = 0; sc4 < T4; ++sc4) {
+                const double gr = RG[x4 * PD + 4 * (4 * sc4 + k4) + y4];
+                accR4 = mfma44(-gr, gr, accR4);
+            }
+        } else if (ng) {
 #pragma unroll
             for (int kk = 0; kk < KS; ++kk) {
                 if (hasN) {
@@ -695,10 +775,15 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                 for (int ct = 0; ct < TB; ++ct)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) RA[(16 * rt + 4 * v + lk) * PD + 16 * ct + li] = accD[rt][ct][v];
+            if (g4) {
 #pragma unroll
-            for (int ct = 0; ct < TB; ++ct)
+                for (int t = 0; t < T4; ++t) RG[y4 * PD + 4 * (4 * t + k4) + x4] = accB4[t];
+            } else {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) RG[(4 * v + lk) * PD + 16 * ct + li] = accB[ct][v];
+                for (int ct = 0; ct < TB; ++ct)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) RG[(4 * v + lk) * PD + 16 * ct + li] = accB[ct][v];
+            }
         } else if (SEG && endS) {
             // hat F_k hat F_k^T and hat G hat F_k^T (accumulated as negatives)
 #pragma unroll
@@ -710,13 +795,21 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                         const int r = 16 * rt + 4 * v + lk, c = 16 * ct + li;
                         if (r < b && c < b) sc[scr_dA(b, ng, nr) + r * b + c] = -accD[rt][ct][v];
                     }
+            if (g4) {
 #pragma unroll
-            for (int ct = 0; ct < TB; ++ct)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int q = 4 * v + lk, c = 16 * ct + li;
-                    if (q < ng && c < b) sc[scr_dQ(b, ng, nr) + q * b + c] = -accB[ct][v];
+                for (int t = 0; t < T4; ++t) {
+                    const int c = 4 * (4 * t + k4) + x4;
+                    if (y4 < ng && c < b) sc[scr_dQ(b, ng, nr) + y4 * b + c] = -accB4[t];
                 }
+            } else {
+#pragma unroll
+                for (int ct = 0; ct < TB; ++ct)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int q = 4 * v + lk, c = 16 * ct + li;
+                        if (q < ng && c < b) sc[scr_dQ(b, ng, nr) + q * b + c] = -accB[ct][v];
+                    }
+            }
         }
         wave_sync();
         // y_i goes out only now: stored earlier, the wait for the next stage's blocks
@@ -732,7 +825,18 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         if (FWD)
             for (int e = lane; e < b * nr; e += NTL) a.rhs[sd.oRhs + (long long)sep * b * nr + e] = L.XS[e];
     }
-    if (ng) {
+    if (g4) {
+        // the four blocks' partial sums of hat G hat G^T, through the (now free)
+        // pivot-column buffer
+        L.col[lane] = accR4;
+        wave_sync();
+        const int x = lane & 3, y = lane >> 4;
+        if (((lane >> 2) & 3) == 0 && y < ng && x < ng)
+            sc[scr_Rk(b, ng, nr) + y * ng + x] = L.col[lane] + L.col[lane + 4] + L.col[lane + 8] + L.col[lane + 12];
+        wave_sync();
+        if (FWD)
+            for (int e = lane; e < ng * nr; e += NTL) sc[scr_yg(b, ng, nr) + e] = L.XG[e];
+    } else if (ng) {
         const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
