@@ -74,8 +74,9 @@ typedef struct kkt_plan kkt_plan;   /* opaque, host-only, immutable after creati
  *   ng  global block size, 0..KKT_MAX_NG
  *   p   segments: 1 = sequential method; p >= 2 = segmented method with p
  *       segments (needs N >= 2p - 1); 0 = let the plan's cost model choose.
- *   N1  first-segment length; 0 = the balance rule of Eq. (13) (sigma = 19/7).
- *       Otherwise the other p-1 segments get (N - N1 - (p-1)) / (p-1) stages,
+ *   N1  first-segment length; 0 = the balance rule of Eq. (13): sigma = 19/7
+ *       for a given p; for p = 0 the cost model's sigma = t_fill / t_first, the
+ *       balance its estimates assume.  Otherwise the other p-1 segments get (N - N1 - (p-1)) / (p-1) stages,
  *       which must be a positive integer.                                        */
 typedef struct {
     int32_t N, b, ng, p, N1;

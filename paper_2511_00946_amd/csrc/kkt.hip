@@ -705,8 +705,16 @@ void choose_segments(std::vector<kkt_dims> &dims, const std::vector<int> &cls_of
     }
     std::map<std::pair<int, int>, int> p_of;
     for (size_t i = 0; i < lens.size(); ++i) p_of[{lens[i].cls, lens[i].N}] = best_ps[i];
-    for (size_t s = 0; s < dims.size(); ++s)
-        if (dims[s].p == 0) dims[s].p = p_of[{cls_of[s], dims[s].N}];
+    // a tuned system is split with the balance the estimates assumed (Eq. 13 with
+    // sigma = t_fill / t_first of the model) unless its first segment is given
+    for (size_t s = 0; s < dims.size(); ++s) {
+        if (dims[s].p != 0) continue;
+        const int c = cls_of[s], p = p_of[{c, dims[s].N}];
+        dims[s].p = p;
+        int N1 = 0, Nk = 0;
+        if (p > 1 && dims[s].N1 == 0 && partition_sigma(dims[s].N, p, m.t_first[c], m.t_fill[c], &N1, &Nk))
+            dims[s].N1 = N1;
+    }
 }
 
 kkt_cost_model default_cost_model()
@@ -767,10 +775,15 @@ struct kkt_plan {
     // optional per-class timing events (kkt_plan_set_class_events)
     hipEvent_t ev_start[MAXC] = {nullptr};
     hipEvent_t ev_stop[MAXC] = {nullptr};
-    // With several classes, each class runs on a stream of its own, forked from and
-    // joined back into the caller's stream through events (created on first use on
-    // the current device; the mutex keeps concurrent callers' fork/join sequences
-    // from interleaving).
+    // With several classes, the first NSIDE classes run on streams of their own,
+    // forked from and joined back into the caller's stream through events (created
+    // on first use on the current device; the mutex keeps concurrent callers'
+    // fork/join sequences from interleaving), and any further class runs on the
+    // caller's stream itself.  HIP maps a process's streams onto 4 hardware queues
+    // by default; a fourth side stream would share a queue with another side stream
+    // and run only after that stream's work, while the caller's stream has a queue
+    // of its own.
+    static constexpr int NSIDE = 3;
     mutable std::mutex side_mu;
     mutable int side_dev = -1;
     mutable hipStream_t side[MAXC] = {nullptr};
@@ -793,7 +806,7 @@ struct kkt_plan {
         if (side_dev == dev) return true;
         release_side();
         if (hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming) != hipSuccess) return false;
-        for (size_t c = 0; c < cls.size() && c < (size_t)MAXC; ++c) {
+        for (size_t c = 0; c < cls.size() && c < (size_t)NSIDE; ++c) {
             if (hipStreamCreateWithFlags(&side[c], hipStreamNonBlocking) != hipSuccess) return false;
             if (hipEventCreateWithFlags(&join_ev[c], hipEventDisableTiming) != hipSuccess) return false;
         }
@@ -844,11 +857,14 @@ int launch_mode(const kkt_plan *plan, int mode, const Args &base, hipStream_t st
         if (hipGetDevice(&dev) != hipSuccess || !plan->ensure_side(dev)) return KKT_ELAUNCH;
         if (hipEventRecord(plan->fork_ev, stream) != hipSuccess) return KKT_ELAUNCH;
     }
+    // active classes 0 .. NSIDE-1 on the side streams, the rest on the caller's stream
+    int nside = 0;
     for (size_t ci = 0; ci < plan->cls.size(); ++ci) {
         const kkt_plan::Cls &c = plan->cls[ci];
         if (c.item_cnt == 0) continue;
-        hipStream_t st = fork ? plan->side[ci] : stream;
-        if (fork && hipStreamWaitEvent(st, plan->fork_ev, 0) != hipSuccess) return KKT_ELAUNCH;
+        const bool on_side = fork && nside < kkt_plan::NSIDE;
+        hipStream_t st = on_side ? plan->side[nside] : stream;
+        if (on_side && hipStreamWaitEvent(st, plan->fork_ev, 0) != hipSuccess) return KKT_ELAUNCH;
         Args a = base;
         a.items = base.items + c.item_off;
         a.n_items = c.item_cnt;
@@ -904,10 +920,12 @@ int launch_mode(const kkt_plan *plan, int mode, const Args &base, hipStream_t st
             if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
         }
         if (plan->ev_stop[ci] && hipEventRecord(plan->ev_stop[ci], st) != hipSuccess) return KKT_ELAUNCH;
-        if (fork && (hipEventRecord(plan->join_ev[ci], st) != hipSuccess ||
-                     hipStreamWaitEvent(stream, plan->join_ev[ci], 0) != hipSuccess))
-            return KKT_ELAUNCH;
+        if (on_side && hipEventRecord(plan->join_ev[nside++], st) != hipSuccess) return KKT_ELAUNCH;
     }
+    // the caller's stream waits for the side streams only after its own classes are
+    // queued, so that those run beside the side streams
+    for (int j = 0; j < nside; ++j)
+        if (hipStreamWaitEvent(stream, plan->join_ev[j], 0) != hipSuccess) return KKT_ELAUNCH;
     return KKT_OK;
 }
 

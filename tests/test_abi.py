@@ -134,6 +134,27 @@ def test_cost_model_single_system_near_optimal(N, b, ng):
     assert t[0] > 0
 
 
+def test_tuned_split_uses_the_model_balance():
+    """A system split by the cost model gets the segment lengths its estimate
+    assumed: Eq. 13 balanced with sigma = t_fill / t_first of the model (here 1.4,
+    not the flop ratio 19/7); a system with p given keeps sigma = 19/7."""
+    kkt = _kkt()
+    b3 = float(32) ** 3
+    m = dict(_model(), t_first=[b3] * 4, t_fill=[1.4 * b3] * 4)
+    N = 256
+    plan = kkt.Plan([(N, 32, 4, 0)], cost_model=m)
+    (p,) = plan.segments()
+    assert p > 1
+    lay = plan.layouts[0]
+    assert lay.N1 + (p - 1) * (lay.Nk + 1) == N
+    # brute force over every admissible first-segment length
+    best = min(max(n1, 1.4 * ((N - n1 - (p - 1)) // (p - 1)))
+               for n1 in range(1, N) if (N - n1 - (p - 1)) % (p - 1) == 0 and N - n1 - (p - 1) >= p - 1)
+    assert max(lay.N1, 1.4 * lay.Nk) == pytest.approx(best)
+    fixed = kkt.Plan([(N, 32, 4, p)], cost_model=m).layouts[0]
+    assert 7 * fixed.N1 >= 19 * fixed.Nk - 19 and fixed.N1 > lay.N1
+
+
 def test_cost_model_saturated_batch_keeps_one_segment():
     """With far more systems than workers, splitting only adds work: every p stays 1."""
     kkt = _kkt()
