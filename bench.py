@@ -205,10 +205,14 @@ def single_systems(torch, kkt, workloads, okkt, dev, cost_model=None, reps=50):
         sy = workloads.single(name)
         nrhs = sy.r.shape[1]
         pools = kkt.pack_to_device(workloads.pack([sy]), dev)
-        auto = kkt.Plan([(sy.N, sy.b, sy.ng, 0)], nrhs=nrhs, cost_model=cost_model).segments()[0]
+        tuned = kkt.Plan([(sy.N, sy.b, sy.ng, 0)], nrhs=nrhs, cost_model=cost_model)
+        auto = tuned.segments()[0]
         res = {}
-        for p in sorted(set(plist) | {auto}):
-            plan = kkt.Plan([(sy.N, sy.b, sy.ng, p)], nrhs=nrhs)
+        # every p of the list with the Eq. 13 partition (sigma = 19/7), then the plan
+        # the cost model makes (its p, split with its measured sigma)
+        cases = [(p, kkt.Plan([(sy.N, sy.b, sy.ng, p)], nrhs=nrhs)) for p in sorted(set(plist) | {auto})]
+        cases.append(("cost_model", tuned))
+        for p, plan in cases:
             ws = plan.new_workspace(dev)
             info = torch.zeros(1, dtype=torch.int32, device=dev)
             x = torch.empty_like(pools["r"])
@@ -235,7 +239,8 @@ def single_systems(torch, kkt, workloads, okkt, dev, cost_model=None, reps=50):
         out[name] = {"shape": "N=%d b=%d ng=%d nrhs=%d" % (sy.N, sy.b, sy.ng, nrhs),
                      "us_per_factor_solve": {str(p): round(v, 2) for p, v in res.items()},
                      "speedup_vs_p1": {str(p): round(base / v, 3) for p, v in res.items()},
-                     "cost_model_p": auto}
+                     "cost_model_p": auto,
+                     "cost_model_segments": [tuned.layouts[0].N1, tuned.layouts[0].Nk]}
         log("single %s: %s" % (name, {p: round(v, 1) for p, v in res.items()}))
     out["chain"] = "not run: block size 42 is above the supported maximum of 32"
     return out
