@@ -112,6 +112,11 @@ SINGLE_CASES = [
     pytest.param(5, 42, 0, 2, 1, marks=pytest.mark.skip(reason=LARGE_B_OFF)),
     pytest.param(7, 48, 1, 3, 1, marks=pytest.mark.skip(reason=LARGE_B_OFF)),
     (40, 6, 8, 4, 4),
+    # the maxima: block size 32, 16 arrow rows, 8 rhs (whole and segmented, dense path)
+    (6, 32, 16, 1, 8),
+    (9, 32, 16, 3, 8),
+    (7, 24, 16, 2, 5),
+    (9, 8, 16, 3, 8),
 ]
 
 
