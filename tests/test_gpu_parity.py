@@ -233,13 +233,22 @@ def test_repeat_runs_bitwise_identical():
     assert torch.equal(x1, x2)
 
 
-@pytest.mark.parametrize("p", [1, 3])
-def test_adjoint_matches_oracle(p):
-    kkt = _kkt()
+ADJ_CASES = {
     # the last three are whole (p = 1) systems of the dense classes
-    systems = gen(21, [(12, 6, 3), (9, 8, 0), (7, 16, 2), (6, 24, 4), (5, 32, 0)], nrhs=2, with_w=True)
-    ps = [p, min(p, 2), 1, 1, 1]
-    plan, pools, ws, x, info = run(systems, ps, 2)
+    "mixed": ([(12, 6, 3), (9, 8, 0), (7, 16, 2), (6, 24, 4), (5, 32, 0)], 2),
+    # the maxima: block size 32, 16 arrow rows, 8 rhs
+    "maxima": ([(9, 8, 16), (6, 32, 16), (7, 16, 16)], 8),
+}
+
+
+@pytest.mark.parametrize("case", ["mixed", "maxima"])
+@pytest.mark.parametrize("p", [1, 3])
+def test_adjoint_matches_oracle(p, case):
+    kkt = _kkt()
+    dims, nr = ADJ_CASES[case]
+    systems = gen(21, dims, nrhs=nr, with_w=True)
+    ps = [p, min(p, 2)] + [1] * (len(dims) - 2)
+    plan, pools, ws, x, info = run(systems, ps, nr)
     assert (info == 0).all()
     gx = torch.from_numpy(workloads.pack(systems)["w"]).cuda()
     lam = gx.clone()
@@ -253,7 +262,7 @@ def test_adjoint_matches_oracle(p):
     xs = split_rhs(plan, x, systems)
     for s, sysm in enumerate(systems):
         lay = plan.layouts[s]
-        N, b, ng, nr = sysm.N, sysm.b, sysm.ng, 2
+        N, b, ng = sysm.N, sysm.b, sysm.ng
         ref = okkt.adjoint(sysm.D, sysm.C, sysm.B, sysm.corner, xs[s], sysm.w, plan.segment_lengths(s))
         got = (lam_h[lay.off_rhs:lay.off_rhs + sysm.n * nr].reshape(sysm.n, nr),
                dD_h[lay.off_D:lay.off_D + N * b * b].reshape(N, b, b),
