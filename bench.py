@@ -28,9 +28,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 30
-SRC_FILES = ("paper_2511_00946_amd/csrc/kkt.hip", "paper_2511_00946_amd/csrc/kkt_sweeps.h",
-             "paper_2511_00946_amd/csrc/kkt_dense.h",
-             "paper_2511_00946_amd/csrc/kkt_device.h")
+SRC_FILES = ("paper_2511_00946_amd/csrc/kkt.hip", "paper_2511_00946_amd/csrc/kkt_wave.h",
+             "paper_2511_00946_amd/csrc/kkt_wave_inst.hip", "paper_2511_00946_amd/csrc/kkt_internal.h",
+             "paper_2511_00946_amd/csrc/kkt_dense.h", "paper_2511_00946_amd/csrc/kkt_device.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ragged4096.json")
 
 
@@ -136,14 +136,15 @@ def measured_traffic(bp, p, S):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-KIND_GENERAL, KIND_DENSE, KIND_DSEG = 0, 1, 2
+KIND_ROWLANE, KIND_DENSE, KIND_DSEG = 0, 1, 2
+DENSE_GROUPS = (16, 24, 32)
 
 
 def in_class(bp, kind, b, p):
     """Whether a system of block size b split into p segments belongs to a launch class."""
     if class_of(b) != bp:
         return False
-    if bp < 16:
+    if bp not in DENSE_GROUPS:
         return True
     return (p == 1) == (kind == KIND_DENSE)
 
@@ -153,7 +154,7 @@ def class_label(bp, kind):
 
 
 def class_of(b):
-    for i, bp in enumerate((8, 16, 24, 32)):
+    for bp in (8, 16, 24, 32, 48):
         if b <= bp:
             return bp
     raise ValueError(b)
@@ -416,9 +417,9 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": measured_traffic(("d%d" if dom_dense else "%d") % dom_bp, uniform_p, S),
                 "kernel": {KIND_DENSE: "kkt_dense<%d, factor_solve> + kkt_dense_bwd<%d>" % (dom_db, dom_db),
-                           KIND_DSEG: "kkt_dense_seg<%d> + kkt_reduced<%d> + kkt_dense_seg_bwd<%d>"
+                           KIND_DSEG: "kkt_dense_seg<%d> + kkt_wave_p2<%d> + kkt_dense_seg_bwd<%d>"
                                       % (dom_db, dom_bp, dom_db)}.get(
-                               dom_kind, "kkt_persistent<%d, factor_solve>" % dom_bp),
+                               dom_kind, "kkt_wave_p1/p2/p3<%d, factor_solve>" % dom_bp),
                 "kernel_ms": round(float(cls_ms[dom]), 4), "alg_bytes": dom_bytes}
 
     # plain single-system path: one call (one launch) per system, on a sample

@@ -1,28 +1,30 @@
 /*
  * kkt.h -- C ABI of the MI355X (gfx950) segmented block Cholesky KKT solver.
  *
- * Solves Psi x = r (arXiv 2511.00946, Eq. 2) for block-tridiagonal-arrow SPD
- * matrices Psi (Eq. 3) with uniform stage size b (Sec. 3.1) and a global block
- * of size ng >= 0, for one system or a ragged batch of systems.  The horizon of
- * each system is split into p segments; segments are factored independently
- * (Algorithm 1, parallel phase, Eqs. 4-5), the separator and arrow blocks form a
- * reduced system (Eq. 7) that is factored next (Algorithm 1, sequential phase),
- * and the substitutions sweep the same way (Algorithms 2 and 3, Eqs. 9-12).
- * p = 1 is the sequential block Cholesky.
+ * Solves Psi x = r (arXiv 2511.00946, Sec. 2, Eq. 2) for block-tridiagonal-arrow
+ * SPD matrices Psi (Eq. 3) with uniform stage size b (Sec. 3.1) and a global
+ * block of size ng >= 0, for one system or a ragged batch of systems.  The
+ * horizon of each system is split into p segments; segments are factored
+ * independently (Algorithm 1, parallel phase, Eqs. 4-5), the separator and arrow
+ * blocks form a reduced system (Eq. 7) that is factored next (Algorithm 1,
+ * sequential phase), and the substitutions sweep the same way (Algorithms 2 and
+ * 3, Eqs. 9-12).  p = 1 is the sequential block Cholesky.
  *
  * Precision: FP64 throughout.
  *
  * Memory: every data pointer is a DEVICE pointer owned by the caller.  The
- * library never allocates device memory.  Factor and solve calls only enqueue
- * work (no host synchronisation), so they can be captured in a HIP graph;
- * kkt_workspace_init and kkt_workspace_error synchronise the stream.  When a plan
- * has more than one launch class, the classes of a call run concurrently on
- * streams the plan creates on first use (one per class and device), forked from
- * and joined back into the caller's stream with events: the call stays ordered
- * on the caller's stream.  Scratch lives in the caller's workspace (kkt_plan_info.workspace_bytes,
- * 256-byte aligned); kkt_workspace_init must be enqueued once on a workspace
- * before its first use with a plan.  Calls that share a workspace must not
- * overlap in time.
+ * library never allocates device memory.  kkt_workspace_init prepares a workspace
+ * (and, on its first use on a device, the plan's launch state there: side
+ * streams, events, launch shapes) and synchronises the stream; factor and solve
+ * calls then only enqueue work -- no allocation, no device query, no host
+ * synchronisation -- so they can be captured in a HIP graph, the first call on a
+ * workspace included.  When a plan has more than one launch class, the classes
+ * of a call run concurrently on streams the plan owns, forked from and joined
+ * back into the caller's stream with events: the call stays ordered on the
+ * caller's stream.  Scratch lives in the caller's workspace
+ * (kkt_plan_info.workspace_bytes, 256-byte aligned).  Calls that share a
+ * workspace must not overlap in time; calls of one plan on different workspaces
+ * may be made from several host threads (the plan serialises their enqueueing).
  *
  * Data layout (FP64, row-major blocks).  Systems are packed one after another in
  * five pools; kkt_plan_system gives each system's offsets (in doubles):
@@ -33,7 +35,9 @@
  *   rhs    [N b + ng, nrhs]  stage rows first, g rows last; overwritten by x.
  * With ng = 0 the B and corner pools are empty and may be NULL.
  *
- * Return codes: 0 OK; negative values are launch-time errors (see KKT_E*).
+ * Return codes: 0 OK; negative values are launch-time errors (see KKT_E*); on an
+ * error nothing of the call runs, except that a launch failure after the first
+ * kernel leaves the kernels already queued ordered on the caller's stream.
  * Numerical breakdown is reported per system in the device array info[S]:
  *   0      factorization succeeded;
  *   j > 0  the diagonal block of natural stage j (1-based) met a pivot that is
@@ -54,19 +58,21 @@ extern "C" {
 #endif
 
 #define KKT_OK              0
-#define KKT_EDIMS          -1   /* N < 1, b outside 1..32, ng outside 0..16, nrhs outside 1..8,
+#define KKT_EDIMS          -1   /* N < 1, b outside 1..48, ng outside 0..16, nrhs outside 1..8,
                                    p > (N+1)/2, or an impossible first-segment length      */
 #define KKT_EPOINTER       -2   /* NULL or misaligned pointer                               */
-#define KKT_EWORKSPACE     -3   /* workspace too small or not initialised for this plan     */
-#define KKT_ELAUNCH        -4   /* HIP launch error                                         */
+#define KKT_EWORKSPACE     -3   /* workspace not initialised for this plan on the current
+                                   device (kkt_workspace_init)                              */
+#define KKT_ELAUNCH        -4   /* HIP launch or runtime error                              */
 #define KKT_ENOTFACTORED   -5   /* solve before any factorization into this workspace       */
 #define KKT_EINTERNAL      -6
 
-#define KKT_MAX_B     32
+#define KKT_MAX_B     48
 #define KKT_MAX_NG    16
 #define KKT_MAX_NRHS   8
+#define KKT_NUM_CLASSES 5       /* padded block sizes 8, 16, 24, 32, 48 */
 
-typedef struct kkt_plan kkt_plan;   /* opaque, host-only, immutable after creation */
+typedef struct kkt_plan kkt_plan;   /* opaque, host-only */
 
 /* One system's shape.
  *   N   number of stages (diagonal blocks), >= 1
@@ -76,8 +82,8 @@ typedef struct kkt_plan kkt_plan;   /* opaque, host-only, immutable after creati
  *       segments (needs N >= 2p - 1); 0 = let the plan's cost model choose.
  *   N1  first-segment length; 0 = the balance rule of Eq. (13): sigma = 19/7
  *       for a given p; for p = 0 the cost model's sigma = t_fill / t_first, the
- *       balance its estimates assume.  Otherwise the other p-1 segments get (N - N1 - (p-1)) / (p-1) stages,
- *       which must be a positive integer.                                        */
+ *       balance its estimates assume.  Otherwise the other p-1 segments get
+ *       (N - N1 - (p-1)) / (p-1) stages, which must be a positive integer.        */
 typedef struct {
     int32_t N, b, ng, p, N1;
 } kkt_dims;
@@ -86,17 +92,18 @@ typedef struct {
     int32_t num_systems;
     int32_t nrhs;
     int32_t num_items;        /* (system, segment) work items                      */
-    int32_t num_classes;      /* launch classes = persistent launches per call (at most 7) */
+    int32_t num_classes;      /* launch classes (at most 8)                         */
     int64_t D_len, C_len, B_len, corner_len, rhs_len;   /* pool lengths, doubles   */
     int64_t workspace_bytes;
-    double  factor_flops;     /* standard flop count of one factorization          */
-    double  solve_flops;      /* one solve (all rhs)                               */
+    double  factor_flops;     /* one factorization: standard counts (potrf n^3/3, trsm m n^2,
+                                 syrk n^2 k, gemm 2 m n k) of the operations of Algorithm 1 */
+    double  solve_flops;      /* one solve, all rhs (trsv n^2, gemv 2 m n; Algorithms 2, 3) */
     int64_t factor_words;     /* |hat L| in doubles, including fill-in             */
     int64_t input_words;      /* |Psi| in doubles (D, C, B, corner pools)           */
 } kkt_plan_info;
 
 /* Where one system lives.  Pool offsets in doubles from the pool base; factor
- * offsets in doubles from the workspace's factor region (see kkt_plan_info).
+ * offsets in doubles from the workspace's factor region (kkt_plan_factor_offset).
  * The factor is stored block for block in the pattern of the input:
  *   Ld[s]  (b x b, lower)  hat D of segment stages, hat A_k at separators
  *   Lc[s]  (b x b)         the factor block coupling stages s and s+1, oriented as
@@ -113,46 +120,55 @@ typedef struct {
     int64_t off_Ld, off_Lc, off_Lb, off_Lg, off_fill, off_H;
 } kkt_system_layout;
 
-/* Plan a batch of num_systems systems (dims: host array), nrhs right-hand sides
- * each.  Fails with KKT_EDIMS on an unsupported shape.  Systems with p = 0 get
- * their segment count from the default cost model (see kkt_cost_model). */
+/* Plan a batch of num_systems systems (dims: host array, read during the call),
+ * nrhs right-hand sides each.  *plan receives a host object the caller releases
+ * with kkt_plan_destroy.  Fails with KKT_EDIMS on an unsupported shape.  Systems
+ * with p = 0 get their segment count from the default cost model (below). */
 int kkt_plan_create(kkt_plan **plan, int32_t num_systems, const kkt_dims *dims, int32_t nrhs);
 
-/* Cost model used to choose p for systems given with p = 0.  Per padded
- * block-size class (8, 16, 24, 32): the time of one stage of a first segment
- * (t_first), of a segment carrying fill rows (t_fill, segments 2..p), of one
- * reduced-chain stage (t_red), the fixed cost of an item (t_item), and the
- * number of items the device runs at once, for unsegmented systems (workers)
- * and for the items of segmented ones (workers_seg; 0 = same as workers).  The
- * work of a system counts against the pool its items run in.  Units are arbitrary but
- * common.  Segment lengths follow Eq. 13's balance with sigma = t_fill / t_first.
- * The classes of a batch share the device, so the step is estimated as
- * max(sum over classes of total work / workers, longest item).  The plan
- * searches a bound T on the longest item: every system with p = 0 takes the
- * fewest segments whose longest item stays within T, and the smallest T that
- * the resulting summed work also meets is kept (systems of one class and length
- * get equal p).  Fixed p are honoured and enter the estimate.  A default model
- * follows the flop ratios of Table 1 (7/3, 19/3 and 10/3 b^3 per stage); a
- * measured one (paper_2511_00946_amd/autotune.py) can be passed here. */
+/* Cost model used to choose p for systems given with p = 0 (Sec. 3.3: the
+ * balance of Eq. 13 and the makespan of Table 1's phases, with measured stage
+ * costs).  Per padded block-size class (8, 16, 24, 32, 48): the time of one stage
+ * of a first segment (t_first), of a segment carrying fill rows (t_fill,
+ * segments 2..p), of one reduced-chain stage (t_red), the fixed cost of an item
+ * (t_item), and the number of items the device runs at once, for unsegmented
+ * systems (workers) and for the items of segmented ones (workers_seg; 0 = same
+ * as workers).  The work of a system counts against the pool its items run in.
+ * Units are arbitrary but common.  Segment lengths follow Eq. 13's balance with
+ * sigma = t_fill / t_first.  The classes of a batch share the device, so the
+ * step is estimated as max(sum over classes of total work / workers, longest
+ * item).  The plan searches a bound T on the longest item: every system with
+ * p = 0 takes the fewest segments whose longest item stays within T, and the
+ * smallest T that the resulting summed work also meets is kept (systems of one
+ * class and length get equal p).  Fixed p are honoured and enter the estimate.
+ * The default model follows the flop ratios of Table 1 (7/3, 19/3 and 10/3 b^3
+ * per stage); a measured one (paper_2511_00946_amd/autotune.py) can be passed. */
 typedef struct {
-    double t_first[4], t_fill[4], t_red[4], t_item[4];
-    double workers[4], workers_seg[4];
+    double t_first[KKT_NUM_CLASSES], t_fill[KKT_NUM_CLASSES], t_red[KKT_NUM_CLASSES], t_item[KKT_NUM_CLASSES];
+    double workers[KKT_NUM_CLASSES], workers_seg[KKT_NUM_CLASSES];
 } kkt_cost_model;
 
 int kkt_plan_create_tuned(kkt_plan **plan, int32_t num_systems, const kkt_dims *dims, int32_t nrhs,
                           const kkt_cost_model *model);
+/* Releases the plan and its side streams and events.  No call of the plan may be
+ * in flight on the host; work already enqueued is unaffected. */
 int kkt_plan_destroy(kkt_plan *plan);
 int kkt_plan_get_info(const kkt_plan *plan, kkt_plan_info *info);
 int kkt_plan_system(const kkt_plan *plan, int32_t s, kkt_system_layout *out);
 /* Byte offset of the factor region inside the workspace. */
 int64_t kkt_plan_factor_offset(const kkt_plan *plan);
 
-/* Copy the plan's tables into the workspace and synchronise the stream.  Once
- * per workspace, before its first use; the plan then forgets any factor it held
- * in this workspace. */
+/* Prepare a workspace (device, 256-byte aligned, kkt_plan_info.workspace_bytes
+ * bytes) for this plan on the current device: copies the plan's tables into it,
+ * on the first workspace of a device also creates the plan's side streams and
+ * events there and fixes every launch shape, and synchronises the stream.  Once
+ * per workspace before its first use; the plan then forgets any factor it held
+ * in this workspace.  Not capturable (it synchronises). */
 int kkt_workspace_init(const kkt_plan *plan, void *workspace, hipStream_t stream);
 
-/* Factorization (Algorithm 1).  info: device int32[S]. */
+/* Factorization (Algorithm 1).  D, C, B, corner: input pools (device, read
+ * only).  info: device int32[S], written per system.  KKT_EWORKSPACE if the
+ * workspace was not initialised for this plan on the current device. */
 int kkt_factor(const kkt_plan *plan, const double *D, const double *C, const double *B,
                const double *corner, void *workspace, int32_t *info, hipStream_t stream);
 
@@ -168,49 +184,47 @@ int kkt_factor_solve(const kkt_plan *plan, const double *D, const double *C, con
                      const double *corner, void *workspace, double *rhs, int32_t *info,
                      hipStream_t stream);
 
-/* Adjoint of x = Psi^{-1} r for a loss L(x): given x and gx = dL/dx (rhs pool
- * layout), overwrite gx with lambda = Psi^{-1} gx = dL/dr and write the
- * gradients restricted to the block pattern (pools laid out like D, C, B, corner):
+/* Adjoint of x = Psi^{-1} r for a loss L(x) (Psi is symmetric, Eq. 3): given x and
+ * gx = dL/dx (rhs pool layout, all nrhs columns), overwrite gx with
+ * lambda = Psi^{-1} gx = dL/dr and write the gradients restricted to the block
+ * pattern (pools laid out like D, C, B, corner):
  *   dD_i = -sym(lambda_i x_i^T),  dC_i = -(lambda_{i+1} x_i^T + x_{i+1} lambda_i^T),
  *   dB_i = -(lambda_g x_i^T + x_g lambda_i^T),  dcorner = -sym(lambda_g x_g^T),
  * summed over the rhs columns.  Uses the factor in the workspace. */
 int kkt_solve_adjoint(const kkt_plan *plan, void *workspace, const double *x, double *gx,
                       double *dD, double *dC, double *dB, double *dcorner, hipStream_t stream);
 
-/* Scheduler health of the last call on this workspace: *flag = 0 if every
- * backward-sweep item of a segmented system was handed over in time, nonzero if
- * a worker gave up waiting (its spin limit, kkt_plan_set_spin_limit, ran out);
- * the solutions of that call are then not valid.  Synchronises the stream. */
+/* Device-side check of the last call on this workspace: *flag = 0, or
+ * KKT_WS_FOREIGN if the workspace held another plan's tables (it was
+ * re-initialised by another plan): every kernel of that call then returned
+ * without touching its outputs.  Synchronises the stream. */
+#define KKT_WS_FOREIGN 2
 int kkt_workspace_error(const kkt_plan *plan, const void *workspace, hipStream_t stream, int32_t *flag);
 
-/* Upper bound on the polls a worker makes while waiting for a backward-sweep
- * item (each poll sleeps briefly); default 4 Mi.  For tests of the error path. */
-int kkt_plan_set_spin_limit(kkt_plan *plan, int32_t limit);
-
 /* Launch class c of the plan (0 <= c < num_classes): padded block size, number
- * of work items, threads per workgroup and LDS bytes of its factor-mode launch,
- * and the number of workgroups of its item sweeps (the first launch of a factor
- * call: as many as fit on the device at once, at most one per item; 0 before
- * the plan's first factor call).  Systems are grouped by padded block size (8, 16, 24, 32); in the
+ * of work items, threads per workgroup and LDS bytes of its first launch in the
+ * factor-solve mode, and its number of workgroups (as many as fit on the device
+ * at once, at most one per item; 0 before kkt_workspace_init on the current
+ * device).  Systems are grouped by padded block size (8, 16, 24, 32, 48); in the
  * 16, 24 and 32 groups the unsegmented systems (p = 1) and the segmented ones
- * form two classes, both run with one 64-lane wave per work item (dense stage
- * sweeps on the FP64 matrix cores); see kkt_plan_class_kind. */
+ * form two classes (see kkt_plan_class_kind). */
 int kkt_plan_class_info(const kkt_plan *plan, int32_t c, int32_t *block_pad, int32_t *num_items,
                         int32_t *threads, int64_t *lds_bytes, int32_t *grid);
 
-/* Kind of launch class c: the general persistent kernel (one workgroup of
- * 3 BP + 16 rounded-up lanes per item), whole systems on the dense single-wave
- * sweeps, or segmented systems of the 16/24/32 groups on the dense segment sweeps
- * (their sequential phase runs on the general kernel; in the solve-only and
- * adjoint modes the whole class runs on the general kernel). */
-#define KKT_CLASS_GENERAL          0
+/* Kind of launch class c: the row-lane sweeps (one workgroup of one to three
+ * 64-lane waves per item, every thread holding one row of a stage's panel:
+ * the 8 and 48 groups), whole systems on the dense single-wave sweeps (FP64
+ * matrix cores), or segmented systems of the 16/24/32 groups on the dense segment
+ * sweeps (their sequential phase, and in the solve-only and adjoint modes the
+ * whole class, run on the row-lane sweeps). */
+#define KKT_CLASS_ROWLANE          0
 #define KKT_CLASS_DENSE            1
 #define KKT_CLASS_DENSE_SEGMENTED  2
 int kkt_plan_class_kind(const kkt_plan *plan, int32_t c, int32_t *kind);
 
-/* Record start / stop on the caller's stream around the persistent launch of
- * class c in every later call (NULL, NULL turns it off).  For measurement: the
- * events are the caller's and must outlive the calls that record them. */
+/* Record start / stop on the class's stream around the launches of class c in
+ * every later call (NULL, NULL turns it off).  For measurement: the events are
+ * the caller's and must outlive the calls that record them. */
 int kkt_plan_set_class_events(kkt_plan *plan, int32_t c, hipEvent_t start, hipEvent_t stop);
 
 const char *kkt_status_string(int status);

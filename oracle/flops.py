@@ -1,5 +1,7 @@
 """Operation lists of Algorithms 1-3 and their flop counts (Table 1) -- test infrastructure only.
 
+Not a product module: only tests/ and the benchmark's CPU leg use it.
+
 Each function walks the loop structure of one algorithm and emits the dense block
 operations it performs, as (phase, op, m, n, k) tuples, for uniform stage size b
 and global size ng.  ``cost`` prices them under the paper's counting convention
@@ -134,6 +136,15 @@ def cost(op, m, n, k):
     if op == "gead":
         return Fraction(m * n * k)
     raise ValueError(op)
+
+
+def std_cost(op, m, n, k):
+    """Flops of one operation under standard counts (the plan's flop totals use
+    these): potrf n^3/3, trsm m n^2, syrk n^2 k, gemm 2 m n k, trsv n^2, gemv 2 m n,
+    gead m n k.  Only trsv differs from the paper's convention (n^2 / 2 there)."""
+    if op == "trsv":
+        return Fraction(n * n)
+    return cost(op, m, n, k)
 
 
 def phase_totals(ops):

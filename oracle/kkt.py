@@ -133,10 +133,6 @@ class KKTFactor:
         x[N * b:] = xp[N * b:]
         return x
 
-    def forward(self, r):
-        """hat y with hat L hat y = P r (in elimination order), via solve of L only."""
-        raise NotImplementedError("the oracle exposes the full solve only")
-
     def solve(self, r):
         """x with Psi x = r (natural order, any number of columns)."""
         if self.info:

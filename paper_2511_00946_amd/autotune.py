@@ -27,7 +27,10 @@ import numpy as np
 
 from . import kkt, workloads
 
-CLASSES = (8, 16, 24, 32)
+CLASSES = kkt.CLASS_BLOCKS
+# classes calibrated on the device; the 48 group (no batch workload uses it) is
+# scaled from the 32 group
+MEASURED = (8, 16, 24, 32)
 
 
 def _cache_path(arch):
@@ -65,9 +68,13 @@ def _time_batch(dims, reps=3):
     return a.elapsed_time(b2) / reps, grid
 
 
-def calibrate(verbose=False):
-    model = {k: [0.0] * 4 for k in ("t_first", "t_fill", "t_red", "t_item", "workers", "workers_seg")}
+def calibrate(verbose=False, classes=MEASURED):
+    """Measure the classes in `classes`; any other class gets the stage costs of the
+    widest measured class scaled by the cube of the block size (the flop ratio)."""
+    model = {k: [0.0] * len(CLASSES) for k in ("t_first", "t_fill", "t_red", "t_item", "workers", "workers_seg")}
     for c, bp in enumerate(CLASSES):
+        if bp not in classes:
+            continue
         b = bp
         _, W = _time_batch([(1, b, 2, 1)] * 8192, reps=1)          # more items than slots: the full grid
         W = max(1, W)
@@ -94,6 +101,15 @@ def calibrate(verbose=False):
             print("class %2d: workers %d / %d t_first %.4f t_fill %.4f t_red %.4f t_item %.4f (ms); "
                   "latency per stage %.4f, sigma %.2f, rho %.2f"
                   % (bp, W, Ws, t_first, t_fill, t_red, t_item, a, sigma, rho), flush=True)
+    ref = max(c for c, bp in enumerate(CLASSES) if bp in classes)
+    for c, bp in enumerate(CLASSES):
+        if bp in classes:
+            continue
+        scale = (bp / CLASSES[ref]) ** 3
+        for k in ("t_first", "t_fill", "t_red", "t_item"):
+            model[k][c] = model[k][ref] * scale
+        model["workers"][c] = model["workers"][ref]
+        model["workers_seg"][c] = model["workers_seg"][ref]
     return model
 
 

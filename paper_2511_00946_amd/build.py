@@ -1,32 +1,62 @@
-"""Build the HIP library libkkt.so for gfx950 (in-tree, next to this file)."""
+"""Build the HIP library libkkt.so for gfx950 (in-tree, next to this file).
+
+The host plan and dense kernels (kkt.hip) and the row-lane kernels of each
+block class (kkt_wave_inst.hip, once per class) compile in parallel to objects
+that are linked into one shared library."""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "kkt.hip")
+CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libkkt.so")
+BUILD = os.path.join(HERE, "_build")
+WAVE_CLASSES = (8, 16, 24, 32, 48)
 
 HIPCC_FLAGS = [
-    "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
+    "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
     # no packed FP32 instructions anywhere
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
 
-def build(verbose=False):
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + HIPCC_FLAGS + ["-I" + os.path.join(ROOT, "include"), "-o", tmp, SRC]
+def _units():
+    units = [("kkt", os.path.join(CSRC, "kkt.hip"), [])]
+    for bp in WAVE_CLASSES:
+        units.append(("kkt_wave%d" % bp, os.path.join(CSRC, "kkt_wave_inst.hip"), ["-DKKT_WAVE_BP=%d" % bp]))
+    return units
+
+
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in res.stdout.splitlines() if "packed-fp32-ops" not in l)
-    if res.returncode != 0:
+    return res.returncode, out
+
+
+def build(verbose=False, extra_flags=()):
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(BUILD, exist_ok=True)
+    inc = ["-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+    jobs = []
+    for name, src, defs in _units():
+        obj = os.path.join(BUILD, name + ".o")
+        jobs.append((obj, [hipcc] + HIPCC_FLAGS + list(extra_flags) + inc + defs + ["-c", "-o", obj, src]))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "8"))))
+    with ThreadPoolExecutor(workers) as pool:
+        results = list(pool.map(lambda j: _run(j[1], verbose), jobs))
+    for (obj, _), (rc, out) in zip(jobs, results):
+        if rc != 0:
+            raise RuntimeError("hipcc failed for %s:\n%s" % (obj, out))
+    tmp = OUT + ".tmp%d" % os.getpid()
+    rc, out = _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in jobs], verbose)
+    if rc != 0:
         if os.path.exists(tmp):
             os.remove(tmp)
-        raise RuntimeError("hipcc failed:\n" + out)
+        raise RuntimeError("link failed:\n" + out)
     os.replace(tmp, OUT)
     return OUT
 

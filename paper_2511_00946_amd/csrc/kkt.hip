@@ -1,330 +1,85 @@
 // MI355X (gfx950) segmented block Cholesky for block-tridiagonal-arrow KKT
-// systems (arXiv 2511.00946): persistent kernels, host plan and the C ABI of
-// include/kkt.h.
+// systems (arXiv 2511.00946): dense single-wave kernels, host plan and the C ABI
+// of include/kkt.h.
 //
 // Scheduling.  A plan splits every system into p segments (Eq. 13 or given) and
 // lists one work item per (system, segment), longest first (LPT).  Systems are
-// grouped by padded block size ("class"); each class gets one persistent launch
-// whose workgroups pull items from an atomic queue:
-//   phase 1  factor (+ forward) sweep of the segment               (Alg. 1/2 parallel)
-//   arrival  the last segment of a system to finish runs phase 2:
-//   phase 2  reduced chain + corner: factor, forward, backward      (Alg. 1/2/3 sequential)
-//            then publishes the system's other segments for phase 3
-//   phase 3  backward sweep of the segment (+ adjoint gradients)    (Alg. 3 parallel)
-// Phase-3 items are taken only once the phase-1 queue is empty, so every item a
-// worker waits for is already held by a running workgroup (no deadlock); the
-// wait is bounded by a spin limit that raises an error flag instead of hanging.
-// p = 1 systems run all three phases in one item with no synchronisation.
+// grouped by padded block size into launch classes; each class runs up to three
+// persistent launches whose workgroups pull work from atomic queues:
+//   phase 1  every item: a whole system (p = 1) runs Algorithms 1-3 end to end;
+//            a segment runs its factor (+ forward) sweep or its forward sweep
+//            (Algorithms 1/2, parallel phase)
+//   phase 2  each segmented system: the reduced separator chain and the corner
+//            (Algorithms 1-3, sequential phases)
+//   phase 3  each segment of a segmented system: its backward sweep (+ adjoint
+//            gradients) (Algorithm 3, parallel phase)
+// The launch boundaries order the phases, so no workgroup ever waits on another.
+// Whole systems of the 16/24/32 classes run on the dense single-wave sweeps
+// (kkt_dense.h), their segments' phases 1 and 3 on the dense segment sweeps;
+// everything else runs on the row-lane sweeps (kkt_wave.h).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
+#include <unordered_map>
 #include <unordered_set>
 #include <vector>
 
 #include "kkt.h"
 #include "kkt_device.h"
-#include "kkt_sweeps.h"
+#include "kkt_internal.h"
+#include "kkt_wave.h"
 #include "kkt_dense.h"
 
 using namespace kkt_dev;
 
+namespace kkt_dev {
+
+kfun_t wave_kernel(int bp, int mode, int phase)
+{
+    switch (bp) {
+    case 8: return wave_kernel_8(mode, phase);
+    case 16: return wave_kernel_16(mode, phase);
+    case 24: return wave_kernel_24(mode, phase);
+    case 32: return wave_kernel_32(mode, phase);
+    default: return wave_kernel_48(mode, phase);
+    }
+}
+
+int wave_threads(int bp)
+{
+    switch (bp) {
+    case 8: return wave_threads_8();
+    case 16: return wave_threads_16();
+    case 24: return wave_threads_24();
+    case 32: return wave_threads_32();
+    default: return wave_threads_48();
+    }
+}
+
+size_t wave_lds_bytes(int bp)
+{
+    switch (bp) {
+    case 8: return wave_lds_bytes_8();
+    case 16: return wave_lds_bytes_16();
+    case 24: return wave_lds_bytes_24();
+    case 32: return wave_lds_bytes_32();
+    default: return wave_lds_bytes_48();
+    }
+}
+
+}  // namespace kkt_dev
+
 namespace {
 
-// ------------------------------------------------------------------ corner
-template <int BP>
-__device__ __forceinline__ const double *seg_scr(const Args &a, const SysDesc &sd, int k)
-{
-    return a.F + sd.oScr + (long long)(k - 1) * sd.scrStride;
-}
-
-// tilde R = sym(corner) + sum_k tilde R_k (+ reduced-chain part), then
-// hat R = chol(tilde R) (Algorithm 1, last two lines; Eq. 8d).  With FWD also
-// hat y_g = hat R^{-1} tilde y_g and x_g = hat R^{-T} hat y_g (Algorithms 2, 3).
-template <int BP, bool FWD, int NTT = K<BP>::NT>
-__device__ __forceinline__ bool corner_factor(const Args &a, const SysDesc &sd, const Lds &L, bool red)
-{
-    constexpr int NT = NTT, G0 = K<BP>::G0, PC = NGM + 1;
-    static_assert(K<BP>::NROWS * (BP + 1) >= NGM * PC || BP >= NGM, "corner staging must fit");
-    const int ng = sd.ng, nr = a.nr, tid = threadIdx.x, b = sd.b, N = sd.N;
-    if (ng == 0) return false;
-    double *St = L.P;
-    const double *cor = a.corner + sd.oCorner;
-    for (int e = tid; e < NGM * nr; e += NT) L.W[e] = 0.0;
-    __syncthreads();
-    for (int e = tid; e < ng * ng; e += NT) {
-        const int q = e / ng, c = e - q * ng;
-        double v = 0.5 * (cor[e] + cor[c * ng + q]);
-        for (int k = 1; k <= sd.p; ++k) v += seg_scr<BP>(a, sd, k)[scr_Rk(b, ng, nr) + e];
-        if (red) v += L.R[q * NGM + c];
-        St[q * PC + c] = v;
-    }
-    if (FWD) {
-        const double *rg = a.rhs + sd.oRhs + (long long)N * b * nr;
-        for (int e = tid; e < ng * nr; e += NT) {
-            const int q = e / nr, j = e - q * nr;
-            double v = rg[e];
-            for (int k = 1; k <= sd.p; ++k) v += seg_scr<BP>(a, sd, k)[scr_yg(b, ng, nr) + e];
-            if (red) v += L.RP[(G0 + q) * nr + j];
-            L.W[q * nr + j] = v;
-        }
-    }
-    __syncthreads();
-    double xr[NGM];
-#pragma unroll
-    for (int c = 0; c < NGM; ++c) {
-        xr[c] = (tid < NGM) ? ((tid < ng && c < ng) ? St[tid * PC + c] : (tid == c ? 1.0 : 0.0)) : 0.0;
-    }
-    const bool bad = eliminate<NGM>(xr, L, nr, FWD);
-    double *Lg = a.F + sd.oLg;
-    if (tid < ng) {
-#pragma unroll
-        for (int c = 0; c < NGM; ++c)
-            if (c < ng) Lg[tid * ng + c] = (c <= tid) ? xr[c] : 0.0;
-    }
-    if (tid < NGM) {
-#pragma unroll
-        for (int c = 0; c < NGM; ++c) St[tid * PC + c] = (c <= tid) ? xr[c] : 0.0;
-    }
-    __syncthreads();
-    if (FWD && tid < 64) {
-        double dcol[NGM];
-#pragma unroll
-        for (int l = 0; l < NGM; ++l) dcol[l] = (tid < NGM) ? St[l * PC + tid] : (l == tid ? 1.0 : 0.0);
-        const double dinv = (tid < NGM) ? 1.0 / St[tid * PC + tid] : 1.0;
-        double *xg = a.rhs + sd.oRhs + (long long)N * b * nr;
-        for (int j = 0; j < nr; ++j) {
-            const double acc = (tid < NGM) ? L.Y[tid * nr + j] : 0.0;
-            const double x = back_subst<NGM>(dcol, acc, dinv);
-            if (tid < ng) xg[tid * nr + j] = x;
-        }
-    }
-    __syncthreads();
-    return bad;
-}
-
-// Corner solve with the factor in place: tilde y_g, hat y_g, x_g.
-template <int BP, int NTT = K<BP>::NT>
-__device__ __forceinline__ void corner_solve(const Args &a, const SysDesc &sd, const Lds &L, bool red)
-{
-    constexpr int NT = NTT, G0 = K<BP>::G0;
-    const int ng = sd.ng, nr = a.nr, tid = threadIdx.x, b = sd.b, N = sd.N;
-    if (ng == 0) return;
-    double *rg = a.rhs + sd.oRhs + (long long)N * b * nr;
-    for (int e = tid; e < ng * nr; e += NT) {
-        const int q = e / nr, j = e - q * nr;
-        double v = rg[e];
-        for (int k = 1; k <= sd.p; ++k) v += seg_scr<BP>(a, sd, k)[scr_yg(b, ng, nr) + e];
-        if (red) v += L.RP[(G0 + q) * nr + j];
-        L.W[q * nr + j] = v;
-    }
-    __syncthreads();
-    if (tid < 64) {
-        const double *Lg = a.F + sd.oLg;
-        double drow[NGM], dcol[NGM];
-        const bool v = tid < ng;
-#pragma unroll
-        for (int c = 0; c < NGM; ++c) {
-            drow[c] = (v && c < ng) ? (c <= tid ? Lg[tid * ng + c] : 0.0) : (tid == c ? 1.0 : 0.0);
-            dcol[c] = (v && c < ng) ? (c >= tid ? Lg[c * ng + tid] : 0.0) : (tid == c ? 1.0 : 0.0);
-        }
-        const double dinv = v ? 1.0 / Lg[tid * ng + tid] : 1.0;
-        for (int j = 0; j < nr; ++j) {
-            const double w = v ? L.W[tid * nr + j] : 0.0;
-            const double y = fwd_subst<NGM>(drow, w, dinv);
-            const double x = back_subst<NGM>(dcol, y, dinv);
-            if (v) rg[tid * nr + j] = x;
-        }
-    }
-    __syncthreads();
-}
-
-// dcorner = -sym(lambda_g x_g^T) summed over the rhs columns.
-template <int BP>
-__device__ __forceinline__ void corner_grad(const Args &a, const SysDesc &sd, const Lds &L)
-{
-    const int ng = sd.ng, nr = a.nr, tid = threadIdx.x, b = sd.b, N = sd.N;
-    if (ng == 0) return;
-    const long long og = sd.oRhs + (long long)N * b * nr;
-    if (tid < 64) {
-        for (int e = tid; e < ng * nr; e += 64) { L.XG[e] = a.rhs[og + e]; L.PG[e] = a.xp[og + e]; }
-        wave_sync();
-        if (tid < ng) {
-            double *dR = a.dcorner + sd.oCorner;
-            for (int q = 0; q < ng; ++q) {
-                double s = 0.0;
-                for (int j = 0; j < nr; ++j)
-                    s += L.XG[q * nr + j] * L.PG[tid * nr + j] + L.PG[q * nr + j] * L.XG[tid * nr + j];
-                dR[q * ng + tid] = -0.5 * s;
-            }
-        }
-    }
-    __syncthreads();
-}
-
-__device__ __forceinline__ int load_status(const int *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// A failed system's solution is NaN (natural stage range [s0, s1), plus g if withg).
-template <int NT>
-__device__ __forceinline__ void fill_nan(const Args &a, const SysDesc &sd, int s0, int s1, bool withg)
-{
-    const int nr = a.nr, b = sd.b;
-    const double qnan = __longlong_as_double(0x7ff8000000000000LL);
-    double *X = a.rhs + sd.oRhs;
-    for (long long e = (long long)s0 * b * nr + threadIdx.x; e < (long long)s1 * b * nr; e += NT) X[e] = qnan;
-    if (withg)
-        for (int e = threadIdx.x; e < sd.ng * nr; e += NT) X[(long long)sd.N * b * nr + e] = qnan;
-}
-
-// ------------------------------------------------------------------ phases
-template <int BP, int MODE>
-__device__ __forceinline__ void phase1(const Args &a, const SysDesc &sd, int s, int k, const Lds &L)
-{
-    int f = 0;
-    if (MODE == M_FACTOR) f = sweep_factor<BP, false, false>(a, sd, k, L);
-    else if (MODE == M_FACTOR_SOLVE) f = sweep_factor<BP, true, false>(a, sd, k, L);
-    else sweep_forward<BP, false>(a, sd, k, L);
-    if (f && threadIdx.x == 0) atomicMin(&a.failidx[s], f);
-}
-
-template <int BP, int MODE>
-__device__ __forceinline__ void phase2(const Args &a, const SysDesc &sd, int s, const Lds &L)
-{
-    constexpr int NT = K<BP>::NT;
-    const bool red = sd.p > 1;
-    const int tid = threadIdx.x;
-    if (MODE == M_FACTOR || MODE == M_FACTOR_SOLVE) {
-        constexpr bool FWD = MODE == M_FACTOR_SOLVE;
-        int rf = 0;
-        if (red) rf = sweep_factor<BP, FWD, true>(a, sd, 0, L);
-        const bool cf = corner_factor<BP, FWD>(a, sd, L, red);
-        if (tid == 0) {
-            const int segf = load_status(&a.failidx[s]);
-            const int info = segf != INT_MAX ? segf : (rf ? rf : (cf ? sd.N + 1 : 0));
-            a.status[s] = info;
-            if (a.info) a.info[s] = info;
-            L.misc[2] = info;
-        }
-        __syncthreads();
-        if (FWD && red) sweep_backward<BP, false, true>(a, sd, 0, L);
-    } else {
-        if (tid == 0) L.misc[2] = load_status(&a.status[s]);
-        if (red) sweep_forward<BP, true>(a, sd, 0, L);
-        corner_solve<BP>(a, sd, L, red);
-        if (MODE == M_ADJOINT) corner_grad<BP>(a, sd, L);
-        if (red) sweep_backward<BP, MODE == M_ADJOINT, true>(a, sd, 0, L);
-    }
-    __syncthreads();
-    if (MODE != M_FACTOR && L.misc[2] != 0) {
-        // NaN the separators and g (segments do their own stages in phase 3)
-        for (int k = 2; k <= sd.p; ++k) {
-            const int sp = sep_of(sd, k);
-            fill_nan<NT>(a, sd, sp, sp + 1, false);
-        }
-        fill_nan<NT>(a, sd, 0, 0, true);
-    }
-    __syncthreads();
-}
-
-template <int BP, int MODE>
-__device__ __forceinline__ void phase3(const Args &a, const SysDesc &sd, int s, int k, const Lds &L)
-{
-    constexpr int NT = K<BP>::NT;
-    sweep_backward<BP, MODE == M_ADJOINT, false>(a, sd, k, L);
-    __syncthreads();
-    if (threadIdx.x == 0) L.misc[3] = load_status(&a.status[s]);
-    __syncthreads();
-    if (L.misc[3] != 0) {
-        const int f = seg_first(sd, k);
-        fill_nan<NT>(a, sd, f, f + seg_len(sd, k), false);
-    }
-    __syncthreads();
-}
-
-// ------------------------------------------------------------------ kernels
-template <int BP, int MODE>
-__global__ void __launch_bounds__(K<BP>::NT) kkt_persistent(Args a)
-{
-    extern __shared__ double lds_raw[];
-    const Lds L = make_lds(lds_raw, BP, a.nr);
-    int *sh = L.misc;
-    const int tid = threadIdx.x;
-
-    for (;;) {
-        if (tid == 0) sh[0] = atomicAdd(&a.ctr[0], 1);
-        __syncthreads();
-        const int it = sh[0];
-        __syncthreads();
-        if (it >= a.n_items) break;
-        const int2 w = a.items[it];
-        const SysDesc sd = a.sys[w.x];
-        phase1<BP, MODE>(a, sd, w.x, w.y, L);
-        if (sd.p == 1) {
-            phase2<BP, MODE>(a, sd, w.x, L);
-            if (MODE != M_FACTOR) phase3<BP, MODE>(a, sd, w.x, 1, L);
-            continue;
-        }
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) sh[1] = (atomicAdd(&a.arrive[w.x], 1) == sd.p - 1) ? 1 : 0;
-        __syncthreads();
-        const bool lastArr = sh[1] != 0;
-        __syncthreads();
-        if (!lastArr) continue;
-        __threadfence();
-        phase2<BP, MODE>(a, sd, w.x, L);
-        if (MODE == M_FACTOR) continue;
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) {
-            const int base = atomicAdd(&a.ctr[1], sd.p - 1);
-            int m = 0;
-            for (int kk = 1; kk <= sd.p; ++kk)
-                if (kk != w.y) a.s3_slot[base + m++] = make_int2(w.x, kk);
-            __threadfence();
-            for (m = 0; m < sd.p - 1; ++m)
-                __hip_atomic_store(&a.s3_ready[base + m], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        phase3<BP, MODE>(a, sd, w.x, w.y, L);
-    }
-    if (MODE == M_FACTOR || a.n_s3 == 0) return;
-    for (;;) {
-        if (tid == 0) {
-            int j = atomicAdd(&a.ctr[2], 1);
-            if (j < a.n_s3) {
-                int spins = 0;
-                while (__hip_atomic_load(&a.s3_ready[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-                    __builtin_amdgcn_s_sleep(8);
-                    if (++spins > a.spin_limit) {
-                        atomicOr(&a.ctr[3], 1);
-                        j = INT_MAX;
-                        break;
-                    }
-                }
-            }
-            sh[0] = j;
-        }
-        __syncthreads();
-        const int j = sh[0];
-        __syncthreads();
-        if (j >= a.n_s3) break;
-        __threadfence();
-        int2 w;
-        w.x = __hip_atomic_load(&a.s3_slot[j].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        w.y = __hip_atomic_load(&a.s3_slot[j].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const SysDesc sd = a.sys[w.x];
-        phase3<BP, MODE>(a, sd, w.x, w.y, L);
-    }
-}
-
+// ------------------------------------------------------------------ dense kernels
 // Whole (p = 1) systems of the 16-, 24- and 32-wide classes: one wave per
 // system, dense stage sweeps (factor on the matrix cores, forward and backward
 // substitution with the next stage's blocks in flight), then the corner
@@ -334,32 +89,26 @@ __global__ void __launch_bounds__(64, DB == 16 ? 2 : 1) kkt_dense(Args a)
 {
     extern __shared__ double lds_raw[];
     const Lds L = make_lds_dense(lds_raw, DB, a.nr);
-    int *sh = L.misc;
-    const int tid = threadIdx.x;
+    double *CR = L.P, *CW = L.P + NGM * (NGM + 1);
     constexpr bool FACT = MODE == M_FACTOR || MODE == M_FACTOR_SOLVE;
     for (;;) {
-        if (tid == 0) sh[0] = atomicAdd(&a.ctr[0], 1);
-        __syncthreads();
-        const int it = sh[0];
-        __syncthreads();
+        const int it = next_work(a.ctr + 0, a.abort, L.misc);
         if (it >= a.n_items) break;
         const int2 w = a.items[it];
         const SysDesc sd = a.sys[w.x];
         if (FACT) {
             constexpr bool FWD = MODE == M_FACTOR_SOLVE;
             const int f = dense_factor<DB, FWD>(a, sd, L);
-            const bool cf = corner_factor<DB, FWD, 64>(a, sd, L, false);
-            if (tid == 0) {
+            const bool cf = corner_factor_w<64, FWD>(a, sd, CR, CW, nullptr, nullptr);
+            if (threadIdx.x == 0) {
                 const int info = f ? f : (cf ? sd.N + 1 : 0);
                 a.status[w.x] = info;
                 if (a.info) a.info[w.x] = info;
-                sh[2] = info;
             }
         } else {
             dense_forward<DB>(a, sd, L);
-            corner_solve<DB, 64>(a, sd, L, false);
-            if (MODE == M_ADJOINT) corner_grad<DB>(a, sd, L);
-            if (tid == 0) sh[2] = load_status(&a.status[w.x]);
+            corner_solve_w<64>(a, sd, CR, CW, nullptr);
+            if (MODE == M_ADJOINT) corner_grad_w<64>(a, sd);
         }
         __syncthreads();
     }
@@ -368,118 +117,86 @@ __global__ void __launch_bounds__(64, DB == 16 ? 2 : 1) kkt_dense(Args a)
 // Backward substitution (and with ADJ the adjoint gradients) of the whole systems
 // of a dense class, after kkt_dense has run the factor or forward sweep and the
 // corner of every one of them; a launch of its own, so that each of the two
-// sweeps gets the registers it needs.  Items come from the second queue counter.
+// sweeps gets the registers it needs.  Items come from the second queue.
 template <int DB, bool ADJ>
 __global__ void __launch_bounds__(64, 2) kkt_dense_bwd(Args a)
 {
     extern __shared__ double lds_raw[];
     const Lds L = make_lds_dense(lds_raw, DB, a.nr);
-    int *sh = L.misc;
-    const int tid = threadIdx.x;
     for (;;) {
-        if (tid == 0) sh[0] = atomicAdd(&a.ctr[1], 1);
-        __syncthreads();
-        const int it = sh[0];
-        __syncthreads();
+        const int it = next_work(a.ctr + 1, a.abort, L.misc);
         if (it >= a.n_items) break;
         const int2 w = a.items[it];
         const SysDesc sd = a.sys[w.x];
         dense_backward<DB, ADJ>(a, sd, L);
-        if (tid == 0) sh[2] = load_status(&a.status[w.x]);
+        if (threadIdx.x == 0) L.misc[2] = load_status(&a.status[w.x]);
         __syncthreads();
-        if (sh[2] != 0) fill_nan<64>(a, sd, 0, sd.N, true);
+        if (L.misc[2] != 0) nan_fill<64>(a, sd, 0, sd.N, true);
         __syncthreads();
     }
 }
 
-// Segmented systems of the 16-, 24- and 32-wide classes, factor modes: (1) every
-// segment's factor (+ forward) sweep, one wave per segment (Algorithm 1/2
-// parallel phase); (2) kkt_reduced: each system's reduced chain and corner
-// (sequential phase); (3) every segment's backward sweep (Algorithm 3 parallel
-// phase).  Three launches on one stream: each launch boundary is the
-// synchronisation between the phases.
+// Segmented systems of the 16-, 24- and 32-wide classes, factor modes, phase 1:
+// every segment's factor (+ forward) sweep, one wave per segment.
 template <int DB, bool FWD>
 __global__ void __launch_bounds__(64, DB == 16 ? 2 : 1) kkt_dense_seg(Args a)
 {
     extern __shared__ double lds_raw[];
     const Lds L = make_lds_dense(lds_raw, DB, a.nr, true);
-    int *sh = L.misc;
-    const int tid = threadIdx.x;
     for (;;) {
-        if (tid == 0) sh[0] = atomicAdd(&a.ctr[0], 1);
-        __syncthreads();
-        const int it = sh[0];
-        __syncthreads();
+        const int it = next_work(a.ctr + 0, a.abort, L.misc);
         if (it >= a.n_items) break;
         const int2 w = a.items[it];
         const SysDesc sd = a.sys[w.x];
         const int f = dense_factor<DB, FWD, true>(a, sd, L, w.y);
-        if (tid == 0 && f) atomicMin(&a.failidx[w.x], f);
+        if (threadIdx.x == 0 && f) atomicMin(&a.failidx[w.x], f);
         __syncthreads();
     }
 }
 
-template <int BP, int MODE>
-__global__ void __launch_bounds__(K<BP>::NT) kkt_reduced(Args a)
-{
-    extern __shared__ double lds_raw[];
-    const Lds L = make_lds(lds_raw, BP, a.nr);
-    int *sh = L.misc;
-    const int tid = threadIdx.x;
-    for (;;) {
-        if (tid == 0) sh[0] = atomicAdd(&a.ctr[1], 1);
-        __syncthreads();
-        const int it = sh[0];
-        __syncthreads();
-        if (it >= a.n_red) break;
-        const int s = a.red[it];
-        const SysDesc sd = a.sys[s];
-        phase2<BP, MODE>(a, sd, s, L);
-    }
-}
-
+// ... phase 3: every segment's backward sweep, the separators already solved.
 template <int DB>
 __global__ void __launch_bounds__(64, DB == 16 ? 2 : 1) kkt_dense_seg_bwd(Args a)
 {
     extern __shared__ double lds_raw[];
     const Lds L = make_lds_dense(lds_raw, DB, a.nr, true);
-    int *sh = L.misc;
-    const int tid = threadIdx.x;
     for (;;) {
-        if (tid == 0) sh[0] = atomicAdd(&a.ctr[2], 1);
-        __syncthreads();
-        const int it = sh[0];
-        __syncthreads();
-        if (it >= a.n_items) break;
-        const int2 w = a.items[it];
+        const int it = next_work(a.ctr + 2, a.abort, L.misc);
+        if (it >= a.n_s3) break;
+        const int2 w = a.s3[it];
         const SysDesc sd = a.sys[w.x];
         dense_backward<DB, false, true>(a, sd, L, w.y);
-        if (tid == 0) sh[2] = load_status(&a.status[w.x]);
+        if (threadIdx.x == 0) L.misc[2] = load_status(&a.status[w.x]);
         __syncthreads();
-        if (sh[2] != 0) {
+        if (L.misc[2] != 0) {
             const int f0 = seg_first(sd, w.y);
-            fill_nan<64>(a, sd, f0, f0 + seg_len(sd, w.y), false);
+            nan_fill<64>(a, sd, f0, f0 + seg_len(sd, w.y), false);
         }
         __syncthreads();
     }
 }
 
-__global__ void kkt_reset(int *ctr, int nctr, int *arrive, int *failidx, int S, int *ready, int nready,
+// Start of every call: check that the workspace holds this plan's tables (a
+// mismatch makes every later kernel of the call return at once and is reported
+// by kkt_workspace_error), then clear the queue heads and the per-system failure
+// indices of the call.  A kernel, not a memset, so the call can be captured.
+__global__ void kkt_reset(const long long *tag, long long expect, int *abort, int *ctr, int nctr, int *failidx, int S,
                           int *info)
 {
+    const bool ok = tag[0] == expect;
     const int t = blockIdx.x * blockDim.x + threadIdx.x, st = gridDim.x * blockDim.x;
+    if (t == 0) *abort = ok ? 0 : 1;
+    if (!ok) return;
     for (int i = t; i < nctr; i += st) ctr[i] = 0;
     for (int i = t; i < S; i += st) {
-        arrive[i] = 0;
         if (failidx) failidx[i] = INT_MAX;
         if (info) info[i] = 0;
     }
-    for (int i = t; i < nready; i += st) ready[i] = 0;
 }
 
 // ------------------------------------------------------------------ host plan
-constexpr int NCLS = 4;
-constexpr int CLS_BP[NCLS] = {8, 16, 24, 32};
+constexpr int NCLS = 5;
+constexpr int CLS_BP[NCLS] = {8, 16, 24, 32, 48};
 
 int class_of(int b)
 {
@@ -488,21 +205,11 @@ int class_of(int b)
     return -1;
 }
 
-typedef void (*kfun_t)(Args);
-
-template <int BP>
-kfun_t kernel_for(int mode)
-{
-    switch (mode) {
-    case M_FACTOR: return kkt_persistent<BP, M_FACTOR>;
-    case M_FACTOR_SOLVE: return kkt_persistent<BP, M_FACTOR_SOLVE>;
-    case M_SOLVE: return kkt_persistent<BP, M_SOLVE>;
-    default: return kkt_persistent<BP, M_ADJOINT>;
-    }
-}
+int dense_width(int bp) { return bp <= 16 ? 16 : 32; }
+bool dense_capable(int bp) { return bp >= 16 && bp <= 32; }
 
 template <int DB>
-kfun_t dense_kernel_for(int mode)
+kfun_t dense_for(int mode)
 {
     switch (mode) {
     case M_FACTOR: return kkt_dense<DB, M_FACTOR>;
@@ -512,50 +219,14 @@ kfun_t dense_kernel_for(int mode)
     }
 }
 
-kfun_t dense_kernel_for(int bp, int mode)
-{
-    return bp <= 16 ? dense_kernel_for<16>(mode) : dense_kernel_for<32>(mode);
-}
-
-kfun_t dseg_kernel_for(int bp, int mode, int l)
-{
-    const bool w16 = bp <= 16;
-    if (l == 0) {
-        if (mode == M_FACTOR) return w16 ? kkt_dense_seg<16, false> : kkt_dense_seg<32, false>;
-        return w16 ? kkt_dense_seg<16, true> : kkt_dense_seg<32, true>;
-    }
-    if (l == 2) return w16 ? kkt_dense_seg_bwd<16> : kkt_dense_seg_bwd<32>;
-    const bool fs = mode == M_FACTOR_SOLVE;
-    switch (bp) {
-    case 16: return fs ? kkt_reduced<16, M_FACTOR_SOLVE> : kkt_reduced<16, M_FACTOR>;
-    case 24: return fs ? kkt_reduced<24, M_FACTOR_SOLVE> : kkt_reduced<24, M_FACTOR>;
-    default: return fs ? kkt_reduced<32, M_FACTOR_SOLVE> : kkt_reduced<32, M_FACTOR>;
-    }
-}
-
-kfun_t dense_bwd_kernel_for(int bp, int mode)
-{
-    if (mode == M_ADJOINT) return bp <= 16 ? kkt_dense_bwd<16, true> : kkt_dense_bwd<32, true>;
-    return bp <= 16 ? kkt_dense_bwd<16, false> : kkt_dense_bwd<32, false>;
-}
-
-int dense_width(int bp) { return bp <= 16 ? 16 : 32; }
-
-kfun_t kernel_for_class(int cls, int mode)
-{
-    switch (CLS_BP[cls]) {
-    case 8: return kernel_for<8>(mode);
-    case 16: return kernel_for<16>(mode);
-    case 24: return kernel_for<24>(mode);
-    default: return kernel_for<32>(mode);
-    }
-}
-
-int nt_of_class(int cls)
-{
-    const int bp = CLS_BP[cls];
-    return ((3 * bp + NGM + 63) / 64) * 64;
-}
+// The launches of one class in one mode: kernel, threads, LDS bytes, and which
+// work list sizes its grid (0 items, 1 reduced systems, 2 phase-3 segments).
+struct Launch {
+    kfun_t fn;
+    int nt;
+    size_t lds;
+    int list;
+};
 
 // Eq. (13) with the (p - 1 + sigma) denominator, sigma = 19/7, ties to floor,
 // N_1 >= 1 and N_k >= 1 enforced.  Exact rational comparisons (integers x21).
@@ -720,7 +391,7 @@ void choose_segments(std::vector<kkt_dims> &dims, const std::vector<int> &cls_of
 kkt_cost_model default_cost_model()
 {
     kkt_cost_model m;
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NCLS; ++c) {
         const double b3 = (double)CLS_BP[c] * CLS_BP[c] * CLS_BP[c];
         m.t_first[c] = 7.0 / 3.0 * b3;
         m.t_fill[c] = 19.0 / 3.0 * b3;
@@ -732,94 +403,134 @@ kkt_cost_model default_cost_model()
     return m;
 }
 
+// Standard flop counts (potrf n^3/3, trsm m n^2, syrk n^2 k, gemm 2 m n k, matrix
+// additions m n per term) of the operations of Algorithm 1 for one system with
+// segment lengths N1, Nk (p segments): the parallel phase of every segment, then
+// the sequential phase on the separators and the corner.
+double factor_flops_std(int N1, int Nk, int p, double b, double g)
+{
+    const double potrf = b * b * b / 3.0, trsm = b * b * b, syrk = b * b * b, gemm = 2.0 * b * b * b;
+    const double trsm_g = g * b * b, syrk_g = g * g * b, gemm_g = 2.0 * g * b * b;
+    double f = 0.0;
+    for (int k = 1; k <= p; ++k) {
+        const int nk = k == 1 ? N1 : Nk;
+        const double n = nk, inner = nk - 1;
+        f += n * potrf + inner * (trsm + syrk);
+        if (g > 0) f += n * (trsm_g + syrk_g) + inner * gemm_g;
+        if (k > 1) {
+            f += n * (trsm + syrk) + inner * gemm;
+            if (g > 0) f += n * gemm_g;
+        }
+        if (k < p) f += trsm;
+        if (k > 1 && k < p) f += gemm;
+    }
+    for (int k = 2; k <= p; ++k) {
+        f += syrk + potrf;
+        if (k < p) f += trsm + syrk;
+        if (g > 0) {
+            f += gemm_g + trsm_g + syrk_g;
+            if (k < p) f += gemm_g;
+        }
+    }
+    if (g > 0) f += g * g * p + g * g * g / 3.0;
+    return f;
+}
+
+// The same for one solve with one right-hand side (trsv n^2, gemv 2 m n), Algorithms 2 and 3.
+double solve_flops_std(int N1, int Nk, int p, double b, double g)
+{
+    const double trsv = b * b, gemv = 2.0 * b * b, gemv_g = 2.0 * g * b;
+    double f = 0.0;
+    for (int k = 1; k <= p; ++k) {
+        const double n = k == 1 ? N1 : Nk;
+        // forward: trsv per stage, hat E y between stages, fill rows, arrow rows
+        f += n * trsv + (n - 1) * gemv + (k > 1 ? n * gemv : 0.0) + (g > 0 ? n * gemv_g : 0.0);
+        // backward: the same products transposed, and hat F_k^T x_{k+1}
+        f += n * trsv + (n - 1) * gemv + (k > 1 ? n * gemv : 0.0) + (g > 0 ? n * gemv_g : 0.0) + (k < p ? gemv : 0.0);
+    }
+    for (int k = 2; k <= p; ++k) {
+        f += gemv + 2 * trsv + (k < p ? 2 * gemv : 0.0) + (g > 0 ? 2 * gemv_g : 0.0);
+    }
+    if (g > 0) f += g * p + 2.0 * g * g;
+    return f;
+}
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+std::atomic<long long> g_tag_counter{0};
+
+long long new_plan_tag()
+{
+    static const long long seed =
+        (long long)std::chrono::steady_clock::now().time_since_epoch().count() * 0x9E3779B97F4A7C15LL;
+    const long long t = seed + (g_tag_counter.fetch_add(1) + 1) * 0x632BE59BD9B4E019LL;
+    return t == 0 ? 1 : t;
+}
 
 }  // namespace
 
 struct kkt_plan {
+    enum { K_WAVE = 0, K_DENSE = 1, K_DSEG = 2 };
     int S = 0, nrhs = 1;
     std::vector<SysDesc> sys;
     std::vector<kkt_system_layout> lay;
     struct Cls {
-        int cls = 0, bp = 0, nt = 0;
-        int item_off = 0, item_cnt = 0, s3_off = 0, s3_cnt = 0;
-        size_t lds = 0;
-        bool dense = false;       // whole (p = 1) systems: dense single-wave sweeps
-        bool dseg = false;        // segmented systems of the 16/24/32 classes: dense segment sweeps
-        size_t lds_dense = 0;     // LDS of the dense launches
-        int red_off = 0, red_cnt = 0;   // dseg: systems (sequential phase)
+        int cls = 0, bp = 0, kind = K_WAVE;
+        int item_off = 0, item_cnt = 0, red_off = 0, red_cnt = 0, s3_off = 0, s3_cnt = 0;
     };
     std::vector<Cls> cls;
-    std::vector<int2> items;
+    std::vector<int2> items, s3;
     std::vector<int> red;
-    size_t o_ctr = 0, o_sys = 0, o_items = 0, o_slot = 0, o_ready = 0, o_arrive = 0, o_fail = 0,
-           o_status = 0, o_tag = 0, o_F = 0, o_red = 0, bytes = 0;
+    size_t o_tag = 0, o_ctr = 0, o_sys = 0, o_items = 0, o_red = 0, o_s3 = 0, o_fail = 0, o_status = 0, o_F = 0,
+           bytes = 0;
     long long nF = 0;
+    long long tag = 0;
     kkt_plan_info info{};
-    int spin_limit = 1 << 22;
-    // Workspaces this plan has factored into (a host-side guard against solving
-    // with no factor; kkt_workspace_init forgets a workspace again).
-    mutable std::mutex factored_mu;
+    static constexpr int MAXC = 8, NSIDE = 3;
+    // The launch state of one device, made by kkt_workspace_init so that factor
+    // and solve calls make no device queries and create nothing (they can be
+    // captured in a graph, first call included).  With several classes, the first
+    // NSIDE active classes of a call run on streams of their own, forked from and
+    // joined back into the caller's stream through events, and any further class
+    // runs on the caller's stream itself.  HIP maps a process's streams onto 4
+    // hardware queues by default; a fourth side stream would share a queue with
+    // another side stream and run only after that stream's work, while the
+    // caller's stream has a queue of its own.
+    struct Dev {
+        int dev = -1;
+        hipStream_t side[NSIDE] = {};
+        hipEvent_t fork = nullptr, join[NSIDE] = {};
+        int grid[MAXC][4][3] = {};
+    };
+    // Host-side registry, guarded by mu (every call and kkt_workspace_init hold
+    // the lock while they enqueue): the per-device launch state, the workspaces
+    // initialised for this plan and their device, the workspaces holding a factor.
+    mutable std::mutex mu;
+    mutable std::vector<Dev> devs;
+    mutable std::unordered_map<const void *, int> ws_dev;
     mutable std::unordered_set<const void *> factored;
-    void mark_factored(const void *ws) const { std::lock_guard<std::mutex> g(factored_mu); factored.insert(ws); }
-    void forget(const void *ws) const { std::lock_guard<std::mutex> g(factored_mu); factored.erase(ws); }
-    bool is_factored(const void *ws) const
+    hipEvent_t ev_start[MAXC] = {}, ev_stop[MAXC] = {};
+
+    const Dev *dev_state(int d) const
     {
-        std::lock_guard<std::mutex> g(factored_mu);
-        return factored.count(ws) != 0;
+        for (const Dev &x : devs)
+            if (x.dev == d) return &x;
+        return nullptr;
     }
-    // launch configuration per (class, mode), filled on first use so that later
-    // calls (and graph capture) make no device queries
-    static constexpr int MAXC = 8;
-    mutable int grid[MAXC][12] = {{0}};   // per (mode, launch of the class)
-    // optional per-class timing events (kkt_plan_set_class_events)
-    hipEvent_t ev_start[MAXC] = {nullptr};
-    hipEvent_t ev_stop[MAXC] = {nullptr};
-    // With several classes, the first NSIDE classes run on streams of their own,
-    // forked from and joined back into the caller's stream through events (created
-    // on first use on the current device; the mutex keeps concurrent callers'
-    // fork/join sequences from interleaving), and any further class runs on the
-    // caller's stream itself.  HIP maps a process's streams onto 4 hardware queues
-    // by default; a fourth side stream would share a queue with another side stream
-    // and run only after that stream's work, while the caller's stream has a queue
-    // of its own.
-    static constexpr int NSIDE = 3;
-    mutable std::mutex side_mu;
-    mutable int side_dev = -1;
-    mutable hipStream_t side[MAXC] = {nullptr};
-    mutable hipEvent_t fork_ev = nullptr;
-    mutable hipEvent_t join_ev[MAXC] = {nullptr};
-    void release_side() const
+    ~kkt_plan()
     {
         // teardown: a failure to destroy leaves nothing to recover, so it is ignored
-        for (int c = 0; c < MAXC; ++c) {
-            if (side[c]) (void)hipStreamDestroy(side[c]);
-            if (join_ev[c]) (void)hipEventDestroy(join_ev[c]);
-            side[c] = nullptr;
-            join_ev[c] = nullptr;
+        for (Dev &d : devs) {
+            for (int j = 0; j < NSIDE; ++j) {
+                if (d.side[j]) (void)hipStreamDestroy(d.side[j]);
+                if (d.join[j]) (void)hipEventDestroy(d.join[j]);
+            }
+            if (d.fork) (void)hipEventDestroy(d.fork);
         }
-        if (fork_ev) (void)hipEventDestroy(fork_ev);
-        fork_ev = nullptr;
-        side_dev = -1;
     }
-    bool ensure_side(int dev) const
-    {
-        if (side_dev == dev) return true;
-        release_side();
-        if (hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming) != hipSuccess) return false;
-        for (size_t c = 0; c < cls.size() && c < (size_t)NSIDE; ++c) {
-            if (hipStreamCreateWithFlags(&side[c], hipStreamNonBlocking) != hipSuccess) return false;
-            if (hipEventCreateWithFlags(&join_ev[c], hipEventDisableTiming) != hipSuccess) return false;
-        }
-        side_dev = dev;
-        return true;
-    }
-    ~kkt_plan() { release_side(); }
 };
 
 namespace {
-
-const long long PLAN_TAG = 0x6b6b742d67393530LL;   // written by kkt_workspace_init
 
 bool valid_dims(const kkt_dims &d)
 {
@@ -829,8 +540,8 @@ bool valid_dims(const kkt_dims &d)
     return true;
 }
 
-// Cost of one (system, segment) item in stage-steps, weighted by block size:
-// used for the LPT order only.
+// Cost of one (system, segment) item in stage-steps weighted by block size: the
+// LPT order only.
 double item_cost(const SysDesc &s, int k)
 {
     const double b = s.b < 8 ? 8.0 : (double)s.b;
@@ -839,94 +550,94 @@ double item_cost(const SysDesc &s, int k)
     return len * per * b * b * b + (s.p > 1 && k == s.p ? s.p * 3.0 * b * b * b : 0.0);
 }
 
-int launch_mode(const kkt_plan *plan, int mode, const Args &base, hipStream_t stream, int *info)
+// The launches of one class in one mode (at most three).
+int launches_of(const kkt_plan::Cls &c, int mode, int nr, Launch *out)
 {
-    const int nctr = 4 * (int)plan->cls.size();
-    char *ws = (char *)0;
-    (void)ws;
-    hipLaunchKernelGGL(kkt_reset, dim3(std::max(1, std::min(1024, (plan->S + 255) / 256))), dim3(256), 0, stream,
-                       base.ctr, nctr, base.arrive, (mode <= M_FACTOR_SOLVE) ? base.failidx : nullptr, plan->S,
-                       base.s3_ready - 0, (int)plan->info.num_items, (mode <= M_FACTOR_SOLVE) ? info : nullptr);
-    if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
-    int ncls = 0;
-    for (const kkt_plan::Cls &c : plan->cls) ncls += c.item_cnt > 0;
-    const bool fork = ncls > 1;
-    std::unique_lock<std::mutex> side_lock(plan->side_mu, std::defer_lock);
-    if (fork) {
-        side_lock.lock();
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess || !plan->ensure_side(dev)) return KKT_ELAUNCH;
-        if (hipEventRecord(plan->fork_ev, stream) != hipSuccess) return KKT_ELAUNCH;
-    }
-    // active classes 0 .. NSIDE-1 on the side streams, the rest on the caller's stream
-    int nside = 0;
-    for (size_t ci = 0; ci < plan->cls.size(); ++ci) {
-        const kkt_plan::Cls &c = plan->cls[ci];
-        if (c.item_cnt == 0) continue;
-        const bool on_side = fork && nside < kkt_plan::NSIDE;
-        hipStream_t st = on_side ? plan->side[nside] : stream;
-        if (on_side && hipStreamWaitEvent(st, plan->fork_ev, 0) != hipSuccess) return KKT_ELAUNCH;
-        Args a = base;
-        a.items = base.items + c.item_off;
-        a.n_items = c.item_cnt;
-        a.s3_slot = base.s3_slot + c.s3_off;
-        a.s3_ready = base.s3_ready + c.s3_off;
-        a.n_s3 = c.s3_cnt;
-        a.ctr = base.ctr + 4 * ci;
-        // launches of this class: a dense class runs its (factor or forward) sweep and
-        // then its backward sweep; a segmented dense class in the factor modes runs the
-        // segment sweeps, the sequential phase (general kernel) and the segment
-        // backward sweeps; everything else is one general persistent launch
-        const bool dseg = c.dseg && mode <= M_FACTOR_SOLVE;
-        const int nlaunch = c.dense ? (mode != M_FACTOR ? 2 : 1) : dseg ? (mode == M_FACTOR ? 2 : 3) : 1;
-        if (dseg) {
-            a.red = base.red + c.red_off;
-            a.n_red = c.red_cnt;
+    const bool fact = mode == M_FACTOR || mode == M_FACTOR_SOLVE, fwd = mode == M_FACTOR_SOLVE;
+    int n = 0;
+    if (c.kind == kkt_plan::K_DENSE) {
+        const int db = dense_width(c.bp);
+        const size_t lds = (size_t)lds_offsets_dense(db, nr).total * sizeof(double);
+        out[n++] = {db == 16 ? dense_for<16>(mode) : dense_for<32>(mode), 64, lds, 0};
+        if (mode != M_FACTOR) {
+            kfun_t f = mode == M_ADJOINT ? (db == 16 ? kkt_dense_bwd<16, true> : kkt_dense_bwd<32, true>)
+                                         : (db == 16 ? kkt_dense_bwd<16, false> : kkt_dense_bwd<32, false>);
+            out[n++] = {f, 64, lds, 0};
         }
-        if (plan->ev_start[ci] && hipEventRecord(plan->ev_start[ci], st) != hipSuccess) return KKT_ELAUNCH;
-        for (int l = 0; l < nlaunch; ++l) {
-            kfun_t fn;
-            int nt = 64, work = c.item_cnt;
-            size_t lds = c.lds_dense;
-            if (c.dense) {
-                fn = l == 0 ? dense_kernel_for(c.bp, mode) : dense_bwd_kernel_for(c.bp, mode);
-            } else if (dseg) {
-                fn = dseg_kernel_for(c.bp, mode, l);
-                if (l == 1) {
-                    nt = c.nt;
-                    lds = c.lds;
-                    work = c.red_cnt;
+        return n;
+    }
+    const int wnt = wave_threads(c.bp);
+    const size_t wl = wave_lds_bytes(c.bp);
+    if (c.kind == kkt_plan::K_DSEG && fact) {
+        const int db = dense_width(c.bp);
+        const size_t lds = (size_t)lds_offsets_dense(db, nr, true).total * sizeof(double);
+        kfun_t f1 = db == 16 ? (fwd ? kkt_dense_seg<16, true> : kkt_dense_seg<16, false>)
+                             : (fwd ? kkt_dense_seg<32, true> : kkt_dense_seg<32, false>);
+        out[n++] = {f1, 64, lds, 0};
+        out[n++] = {wave_kernel(c.bp, mode, 1), wnt, wl, 1};
+        if (fwd) out[n++] = {db == 16 ? kkt_dense_seg_bwd<16> : kkt_dense_seg_bwd<32>, 64, lds, 2};
+        return n;
+    }
+    out[n++] = {wave_kernel(c.bp, mode, 0), wnt, wl, 0};
+    if (c.red_cnt > 0) {
+        out[n++] = {wave_kernel(c.bp, mode, 1), wnt, wl, 1};
+        if (mode != M_FACTOR) out[n++] = {wave_kernel(c.bp, mode, 2), wnt, wl, 2};
+    }
+    return n;
+}
+
+int work_of(const kkt_plan::Cls &c, int list) { return list == 0 ? c.item_cnt : list == 1 ? c.red_cnt : c.s3_cnt; }
+
+// The launch state of the current device: side streams and events, dynamic LDS
+// limits and the grid of every launch (as many workgroups as fit on the device
+// at once, at most one per work entry).  Called with the plan's lock held.
+int ensure_device(const kkt_plan *plan, int dev)
+{
+    if (plan->dev_state(dev)) return KKT_OK;
+    kkt_plan::Dev d;
+    d.dev = dev;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        return KKT_ELAUNCH;
+    int nact = 0;
+    for (const kkt_plan::Cls &c : plan->cls) nact += c.item_cnt > 0;
+    bool ok = true;
+    if (nact > 1) {
+        ok = hipEventCreateWithFlags(&d.fork, hipEventDisableTiming) == hipSuccess;
+        for (int j = 0; ok && j < kkt_plan::NSIDE && j < nact; ++j) {
+            ok = hipStreamCreateWithFlags(&d.side[j], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&d.join[j], hipEventDisableTiming) == hipSuccess;
+        }
+    }
+    for (size_t ci = 0; ok && ci < plan->cls.size(); ++ci) {
+        for (int mode = 0; ok && mode < 4; ++mode) {
+            Launch L[3];
+            const int n = launches_of(plan->cls[ci], mode, plan->nrhs, L);
+            for (int l = 0; ok && l < n; ++l) {
+                if (L[l].lds > 65536 && hipFuncSetAttribute((const void *)L[l].fn,
+                                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                            (int)L[l].lds) != hipSuccess) {
+                    ok = false;
+                    break;
                 }
-            } else {
-                fn = kernel_for_class(c.cls, mode);
-                nt = c.nt;
-                lds = c.lds;
-            }
-            int &grid = plan->grid[ci][mode * 3 + l];
-            if (grid == 0) {
-                int dev = 0, ncu = 0, occ = 0;
-                if (hipGetDevice(&dev) != hipSuccess) return KKT_ELAUNCH;
-                if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-                    return KKT_ELAUNCH;
-                if (lds > 65536 &&
-                    hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-                        hipSuccess)
-                    return KKT_ELAUNCH;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)fn, nt, lds) != hipSuccess ||
+                int occ = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)L[l].fn, L[l].nt, L[l].lds) !=
+                        hipSuccess ||
                     occ < 1)
                     occ = 1;
-                grid = std::max(1, std::min(work, occ * ncu));
+                d.grid[ci][mode][l] = std::max(1, std::min(work_of(plan->cls[ci], L[l].list), occ * ncu));
             }
-            hipLaunchKernelGGL(fn, dim3(grid), dim3(nt), lds, st, a);
-            if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
         }
-        if (plan->ev_stop[ci] && hipEventRecord(plan->ev_stop[ci], st) != hipSuccess) return KKT_ELAUNCH;
-        if (on_side && hipEventRecord(plan->join_ev[nside++], st) != hipSuccess) return KKT_ELAUNCH;
     }
-    // the caller's stream waits for the side streams only after its own classes are
-    // queued, so that those run beside the side streams
-    for (int j = 0; j < nside; ++j)
-        if (hipStreamWaitEvent(stream, plan->join_ev[j], 0) != hipSuccess) return KKT_ELAUNCH;
+    if (!ok) {
+        for (int j = 0; j < kkt_plan::NSIDE; ++j) {
+            if (d.side[j]) (void)hipStreamDestroy(d.side[j]);
+            if (d.join[j]) (void)hipEventDestroy(d.join[j]);
+        }
+        if (d.fork) (void)hipEventDestroy(d.fork);
+        return KKT_ELAUNCH;
+    }
+    plan->devs.push_back(d);
     return KKT_OK;
 }
 
@@ -939,15 +650,76 @@ Args base_args(const kkt_plan *plan, void *workspace)
     a.sys = (const SysDesc *)(ws + plan->o_sys);
     a.items = (const int2 *)(ws + plan->o_items);
     a.red = (const int *)(ws + plan->o_red);
-    a.s3_slot = (int2 *)(ws + plan->o_slot);
-    a.s3_ready = (int *)(ws + plan->o_ready);
+    a.s3 = (const int2 *)(ws + plan->o_s3);
     a.ctr = (int *)(ws + plan->o_ctr);
-    a.arrive = (int *)(ws + plan->o_arrive);
+    a.abort = (const int *)(ws + plan->o_tag + 16);
     a.failidx = (int *)(ws + plan->o_fail);
     a.status = (int *)(ws + plan->o_status);
     a.nr = plan->nrhs;
-    a.spin_limit = plan->spin_limit;
     return a;
+}
+
+// Enqueue one call: the reset kernel, then every class's launches (classes on
+// forked streams when there are several).  On an error after the fork, the side
+// streams used so far are still joined back into the caller's stream.
+int launch_mode(const kkt_plan *plan, int mode, const Args &base, const void *ws, hipStream_t stream, int *info,
+                bool need_factor)
+{
+    std::lock_guard<std::mutex> guard(plan->mu);
+    const auto wit = plan->ws_dev.find(ws);
+    if (wit == plan->ws_dev.end()) return KKT_EWORKSPACE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return KKT_ELAUNCH;
+    if (wit->second != dev) return KKT_EWORKSPACE;
+    if (need_factor && plan->factored.count(ws) == 0) return KKT_ENOTFACTORED;
+    const kkt_plan::Dev *d = plan->dev_state(dev);
+    if (!d) return KKT_EWORKSPACE;
+    const bool fact = mode == M_FACTOR || mode == M_FACTOR_SOLVE;
+    const char *w = (const char *)ws;
+    hipLaunchKernelGGL(kkt_reset, dim3(std::max(1, std::min(1024, (plan->S + 255) / 256))), dim3(256), 0, stream,
+                       (const long long *)(w + plan->o_tag), plan->tag, (int *)(w + plan->o_tag + 16), base.ctr,
+                       4 * (int)plan->cls.size(), fact ? base.failidx : nullptr, plan->S, fact ? info : nullptr);
+    if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
+    int nact = 0;
+    for (const kkt_plan::Cls &c : plan->cls) nact += c.item_cnt > 0;
+    const bool fork = nact > 1;
+    if (fork && hipEventRecord(d->fork, stream) != hipSuccess) return KKT_ELAUNCH;
+    int rc = KKT_OK, nside = 0;
+    for (size_t ci = 0; ci < plan->cls.size() && rc == KKT_OK; ++ci) {
+        const kkt_plan::Cls &c = plan->cls[ci];
+        if (c.item_cnt == 0) continue;
+        const bool on_side = fork && nside < kkt_plan::NSIDE;
+        hipStream_t st = on_side ? d->side[nside] : stream;
+        if (on_side && hipStreamWaitEvent(st, d->fork, 0) != hipSuccess) {
+            rc = KKT_ELAUNCH;
+            break;
+        }
+        Args a = base;
+        a.items = base.items + c.item_off;
+        a.n_items = c.item_cnt;
+        a.red = base.red + c.red_off;
+        a.n_red = c.red_cnt;
+        a.s3 = base.s3 + c.s3_off;
+        a.n_s3 = c.s3_cnt;
+        a.ctr = base.ctr + 4 * ci;
+        if (plan->ev_start[ci] && hipEventRecord(plan->ev_start[ci], st) != hipSuccess) rc = KKT_ELAUNCH;
+        Launch L[3];
+        const int n = launches_of(c, mode, plan->nrhs, L);
+        for (int l = 0; l < n && rc == KKT_OK; ++l) {
+            hipLaunchKernelGGL(L[l].fn, dim3(d->grid[ci][mode][l]), dim3(L[l].nt), L[l].lds, st, a);
+            if (hipGetLastError() != hipSuccess) rc = KKT_ELAUNCH;
+        }
+        if (rc == KKT_OK && plan->ev_stop[ci] && hipEventRecord(plan->ev_stop[ci], st) != hipSuccess) rc = KKT_ELAUNCH;
+        if (on_side) {
+            if (hipEventRecord(d->join[nside], st) != hipSuccess) rc = KKT_ELAUNCH;
+            ++nside;
+        }
+    }
+    // the caller's stream waits for the side streams only after its own classes are
+    // queued, so that those run beside the side streams
+    for (int j = 0; j < nside; ++j)
+        if (hipStreamWaitEvent(stream, d->join[j], 0) != hipSuccess) rc = KKT_ELAUNCH;
+    return rc;
 }
 
 bool aligned8(const void *p) { return ((uintptr_t)p & 7) == 0; }
@@ -982,6 +754,7 @@ int kkt_plan_create_tuned(kkt_plan **out, int32_t S, const kkt_dims *dims_in, in
     if (!P) return KKT_EINTERNAL;
     P->S = S;
     P->nrhs = nrhs;
+    P->tag = new_plan_tag();
     P->sys.resize(S);
     P->lay.resize(S);
     long long oD = 0, oC = 0, oB = 0, oCor = 0, oR = 0, oF = 0;
@@ -1028,40 +801,27 @@ int kkt_plan_create_tuned(kkt_plan **out, int32_t S, const kkt_dims *dims_in, in
         L.off_D = sd.oD; L.off_C = sd.oC; L.off_B = sd.oB; L.off_corner = sd.oCorner; L.off_rhs = sd.oRhs;
         L.off_Ld = sd.oLd; L.off_Lc = sd.oLc; L.off_Lb = sd.oLb; L.off_Lg = sd.oLg; L.off_fill = sd.oFill;
         L.off_H = sd.oH;
-        // standard flop counts of the sequential method (potrf n^3/3, trsm m n^2,
-        // syrk/gemm 2 m n k) plus the fill-in work of the segmented order
-        const double bb = (double)b, gg = (double)ng;
-        double fseq = N * bb * bb * bb / 3 + (N - 1) * (bb * bb * bb + 2 * bb * bb * bb) +
-                      N * (gg * bb * bb + 2 * gg * gg * bb) + (N - 1) * 2 * gg * bb * bb + gg * gg * gg / 3;
-        if (p >= 2) {
-            // per stage of segments k >= 2: trsm of b fill rows, their Gram with themselves,
-            // with the next-stage rows and with the arrow rows
-            const double extra_stage = bb * bb * bb + 2 * bb * bb * bb + 2 * bb * bb * bb + 2 * gg * bb * bb;
-            fseq += (double)(p - 1) * Nk * extra_stage + (double)(p - 1) * 2 * bb * bb * bb;
-        }
-        fflops += fseq;
-        sflops += nrhs * (2.0 * N * bb * bb + 4.0 * (N - 1) * bb * bb + 4.0 * N * gg * bb + 2 * gg * gg +
-                          (p >= 2 ? 4.0 * (double)(p - 1) * Nk * bb * bb : 0.0));
+        fflops += factor_flops_std(N1, Nk, p, (double)b, (double)ng);
+        sflops += nrhs * solve_flops_std(N1, Nk, p, (double)b, (double)ng);
         fwords += N * b2 + (N - 1) * b2 + N * ng * b + ng * ng + fill + H;
         iwords += N * b2 + (N - 1) * b2 + N * ng * b + ng * ng;
     }
     P->nF = oF;
-    // items grouped by class, LPT (longest first) inside a class
-    int nitems = 0, ns3 = 0;
+    // classes: per block-size class the whole systems of the 16/24/32 groups (dense
+    // sweeps), then everything else (segmented dense-group systems; all systems of
+    // the 8 and 48 groups); items longest first (LPT) inside a class
     for (int cc = 0; cc < 2 * NCLS; ++cc) {
-        // per block-size class: whole systems of the 16/24/32 classes first (dense
-        // launch in the factor modes), then everything else
-        const int c = cc >> 1;
-        const bool dense = (cc & 1) == 0 && CLS_BP[c] >= 16;
-        if ((cc & 1) == 0 && !dense) continue;
+        const int c = cc >> 1, bp = CLS_BP[c];
+        const bool dense = (cc & 1) == 0;
+        if (dense && !dense_capable(bp)) continue;
         std::vector<std::pair<double, int2>> its;
-        int s3 = 0;
+        std::vector<int> reds;
         for (int s = 0; s < S; ++s) {
             if (cls_of[s] != c) continue;
             const SysDesc &sd = P->sys[s];
-            if (CLS_BP[c] >= 16 && (sd.p == 1) != dense) continue;
+            if (dense_capable(bp) && (sd.p == 1) != dense) continue;
             for (int k = 1; k <= sd.p; ++k) its.push_back({item_cost(sd, k), make_int2(s, k)});
-            if (sd.p > 1) s3 += sd.p - 1;
+            if (sd.p > 1) reds.push_back(s);
         }
         if (its.empty()) continue;
         std::stable_sort(its.begin(), its.end(), [](const std::pair<double, int2> &x, const std::pair<double, int2> &y) {
@@ -1069,38 +829,30 @@ int kkt_plan_create_tuned(kkt_plan **out, int32_t S, const kkt_dims *dims_in, in
         });
         kkt_plan::Cls C;
         C.cls = c;
-        C.bp = CLS_BP[c];
-        C.nt = nt_of_class(c);
-        C.item_off = nitems;
+        C.bp = bp;
+        C.kind = dense ? kkt_plan::K_DENSE : (dense_capable(bp) ? kkt_plan::K_DSEG : kkt_plan::K_WAVE);
+        C.item_off = (int)P->items.size();
         C.item_cnt = (int)its.size();
-        C.s3_off = ns3;
-        C.s3_cnt = s3;
-        C.lds = (size_t)lds_offsets(C.bp, nrhs).total * sizeof(double);
-        C.dense = dense;
-        C.dseg = !dense && CLS_BP[c] >= 16;
-        if (dense) C.lds_dense = (size_t)lds_offsets_dense(dense_width(C.bp), nrhs).total * sizeof(double);
-        if (C.dseg) {
-            C.lds_dense = (size_t)lds_offsets_dense(dense_width(C.bp), nrhs, true).total * sizeof(double);
-            C.red_off = (int)P->red.size();
-            for (int s = 0; s < S; ++s)
-                if (cls_of[s] == c && P->sys[s].p > 1) P->red.push_back(s);
-            C.red_cnt = (int)P->red.size() - C.red_off;
+        C.red_off = (int)P->red.size();
+        C.red_cnt = (int)reds.size();
+        C.s3_off = (int)P->s3.size();
+        for (auto &x : its) {
+            P->items.push_back(x.second);
+            if (P->sys[x.second.x].p > 1) P->s3.push_back(x.second);
         }
-        for (auto &x : its) P->items.push_back(x.second);
-        nitems += C.item_cnt;
-        ns3 += s3;
+        C.s3_cnt = (int)P->s3.size() - C.s3_off;
+        for (int s : reds) P->red.push_back(s);
+        if ((int)P->cls.size() >= kkt_plan::MAXC) { delete P; return KKT_EINTERNAL; }
         P->cls.push_back(C);
     }
-    // workspace layout
+    // workspace layout: tag (plan tag, size, refusal word), queue heads, tables, factor
     size_t o = 0;
-    P->o_tag = o; o = align256(o + 16);
+    P->o_tag = o; o = align256(o + 24);
     P->o_ctr = o; o = align256(o + sizeof(int) * 4 * P->cls.size());
     P->o_sys = o; o = align256(o + sizeof(SysDesc) * S);
-    P->o_items = o; o = align256(o + sizeof(int2) * std::max(1, nitems));
+    P->o_items = o; o = align256(o + sizeof(int2) * std::max<size_t>(1, P->items.size()));
     P->o_red = o; o = align256(o + sizeof(int) * std::max<size_t>(1, P->red.size()));
-    P->o_slot = o; o = align256(o + sizeof(int2) * std::max(1, ns3));
-    P->o_ready = o; o = align256(o + sizeof(int) * std::max(1, std::max(ns3, nitems)));
-    P->o_arrive = o; o = align256(o + sizeof(int) * S);
+    P->o_s3 = o; o = align256(o + sizeof(int2) * std::max<size_t>(1, P->s3.size()));
     P->o_fail = o; o = align256(o + sizeof(int) * S);
     P->o_status = o; o = align256(o + sizeof(int) * S);
     P->o_F = o; o = align256(o + sizeof(double) * (size_t)oF);
@@ -1108,7 +860,7 @@ int kkt_plan_create_tuned(kkt_plan **out, int32_t S, const kkt_dims *dims_in, in
     kkt_plan_info &I = P->info;
     I.num_systems = S;
     I.nrhs = nrhs;
-    I.num_items = nitems;
+    I.num_items = (int)P->items.size();
     I.num_classes = (int)P->cls.size();
     I.D_len = oD; I.C_len = oC; I.B_len = oB; I.corner_len = oCor; I.rhs_len = oR;
     I.workspace_bytes = (int64_t)P->bytes;
@@ -1147,27 +899,26 @@ int kkt_workspace_init(const kkt_plan *plan, void *workspace, hipStream_t stream
 {
     if (!plan || !workspace) return KKT_EPOINTER;
     if (((uintptr_t)workspace & 255) != 0) return KKT_EPOINTER;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return KKT_ELAUNCH;
+    std::lock_guard<std::mutex> guard(plan->mu);
+    const int rc = ensure_device(plan, dev);
+    if (rc != KKT_OK) return rc;
     char *ws = (char *)workspace;
-    if (hipMemcpyAsync(ws + plan->o_sys, plan->sys.data(), sizeof(SysDesc) * plan->S, hipMemcpyHostToDevice, stream) !=
-        hipSuccess)
-        return KKT_ELAUNCH;
-    if (!plan->items.empty() &&
-        hipMemcpyAsync(ws + plan->o_items, plan->items.data(), sizeof(int2) * plan->items.size(), hipMemcpyHostToDevice,
-                       stream) != hipSuccess)
-        return KKT_ELAUNCH;
-    if (!plan->red.empty() &&
-        hipMemcpyAsync(ws + plan->o_red, plan->red.data(), sizeof(int) * plan->red.size(), hipMemcpyHostToDevice,
-                       stream) != hipSuccess)
-        return KKT_ELAUNCH;
+    auto put = [&](size_t off, const void *src, size_t n) {
+        return n == 0 || hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, stream) == hipSuccess;
+    };
     std::vector<int> st(plan->S, 0);
-    if (hipMemcpyAsync(ws + plan->o_status, st.data(), sizeof(int) * plan->S, hipMemcpyHostToDevice, stream) !=
-        hipSuccess)
+    const long long tag[3] = {plan->tag, (long long)plan->bytes, 0};
+    if (!put(plan->o_sys, plan->sys.data(), sizeof(SysDesc) * plan->S) ||
+        !put(plan->o_items, plan->items.data(), sizeof(int2) * plan->items.size()) ||
+        !put(plan->o_red, plan->red.data(), sizeof(int) * plan->red.size()) ||
+        !put(plan->o_s3, plan->s3.data(), sizeof(int2) * plan->s3.size()) ||
+        !put(plan->o_status, st.data(), sizeof(int) * plan->S) || !put(plan->o_tag, tag, sizeof(tag)) ||
+        hipStreamSynchronize(stream) != hipSuccess)
         return KKT_ELAUNCH;
-    long long tag[2] = {PLAN_TAG, (long long)plan->bytes};
-    if (hipMemcpyAsync(ws + plan->o_tag, tag, sizeof(tag), hipMemcpyHostToDevice, stream) != hipSuccess)
-        return KKT_ELAUNCH;
-    if (hipStreamSynchronize(stream) != hipSuccess) return KKT_ELAUNCH;
-    plan->forget(workspace);
+    plan->ws_dev[workspace] = dev;
+    plan->factored.erase(workspace);
     return KKT_OK;
 }
 
@@ -1181,8 +932,11 @@ int kkt_factor(const kkt_plan *plan, const double *D, const double *C, const dou
         return KKT_EPOINTER;
     Args a = base_args(plan, workspace);
     a.D = D; a.C = C; a.B = B; a.corner = corner; a.info = info;
-    const int rc = launch_mode(plan, M_FACTOR, a, stream, info);
-    if (rc == KKT_OK) plan->mark_factored(workspace);
+    const int rc = launch_mode(plan, M_FACTOR, a, workspace, stream, info, false);
+    if (rc == KKT_OK) {
+        std::lock_guard<std::mutex> guard(plan->mu);
+        plan->factored.insert(workspace);
+    }
     return rc;
 }
 
@@ -1197,8 +951,11 @@ int kkt_factor_solve(const kkt_plan *plan, const double *D, const double *C, con
         return KKT_EPOINTER;
     Args a = base_args(plan, workspace);
     a.D = D; a.C = C; a.B = B; a.corner = corner; a.info = info; a.rhs = rhs;
-    const int rc = launch_mode(plan, M_FACTOR_SOLVE, a, stream, info);
-    if (rc == KKT_OK) plan->mark_factored(workspace);
+    const int rc = launch_mode(plan, M_FACTOR_SOLVE, a, workspace, stream, info, false);
+    if (rc == KKT_OK) {
+        std::lock_guard<std::mutex> guard(plan->mu);
+        plan->factored.insert(workspace);
+    }
     return rc;
 }
 
@@ -1206,10 +963,9 @@ int kkt_solve(const kkt_plan *plan, void *workspace, double *rhs, hipStream_t st
 {
     if (!plan || !workspace || !rhs) return KKT_EPOINTER;
     if (((uintptr_t)workspace & 255) || !aligned8(rhs)) return KKT_EPOINTER;
-    if (!plan->is_factored(workspace)) return KKT_ENOTFACTORED;
     Args a = base_args(plan, workspace);
     a.rhs = rhs;
-    return launch_mode(plan, M_SOLVE, a, stream, nullptr);
+    return launch_mode(plan, M_SOLVE, a, workspace, stream, nullptr, true);
 }
 
 int kkt_solve_adjoint(const kkt_plan *plan, void *workspace, const double *x, double *gx, double *dD, double *dC,
@@ -1221,49 +977,41 @@ int kkt_solve_adjoint(const kkt_plan *plan, void *workspace, const double *x, do
     if (((uintptr_t)workspace & 255) || !aligned8(x) || !aligned8(gx) || !aligned8(dD) || !aligned8(dC) ||
         !aligned8(dB) || !aligned8(dcorner))
         return KKT_EPOINTER;
-    if (!plan->is_factored(workspace)) return KKT_ENOTFACTORED;
     Args a = base_args(plan, workspace);
     a.rhs = gx; a.xp = x; a.dD = dD; a.dC = dC; a.dB = dB; a.dcorner = dcorner;
-    return launch_mode(plan, M_ADJOINT, a, stream, nullptr);
+    return launch_mode(plan, M_ADJOINT, a, workspace, stream, nullptr, true);
 }
 
 int kkt_workspace_error(const kkt_plan *plan, const void *workspace, hipStream_t stream, int32_t *flag)
 {
     if (!plan || !workspace || !flag) return KKT_EPOINTER;
-    std::vector<int> ctr(4 * plan->cls.size(), 0);
-    if (ctr.empty()) { *flag = 0; return KKT_OK; }
-    if (hipMemcpyAsync(ctr.data(), (const char *)workspace + plan->o_ctr, sizeof(int) * ctr.size(),
-                       hipMemcpyDeviceToHost, stream) != hipSuccess ||
+    int refused = 0;
+    if (hipMemcpyAsync(&refused, (const char *)workspace + plan->o_tag + 16, sizeof(int), hipMemcpyDeviceToHost,
+                       stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
         return KKT_ELAUNCH;
-    int f = 0;
-    for (size_t c = 0; c < plan->cls.size(); ++c) f |= ctr[4 * c + 3];
-    *flag = f;
-    return KKT_OK;
-}
-
-int kkt_plan_set_spin_limit(kkt_plan *plan, int32_t limit)
-{
-    if (!plan) return KKT_EPOINTER;
-    if (limit < 1) return KKT_EDIMS;
-    plan->spin_limit = limit;
+    *flag = refused ? KKT_WS_FOREIGN : 0;
     return KKT_OK;
 }
 
 int kkt_plan_class_info(const kkt_plan *plan, int32_t c, int32_t *block_pad, int32_t *num_items,
                         int32_t *threads, int64_t *lds_bytes, int32_t *grid)
 {
-    if (grid && plan && c >= 0 && c < (int)plan->cls.size()) {
-        // the item sweeps: the first launch of the factor modes
-        *grid = std::max(plan->grid[c][M_FACTOR * 3], plan->grid[c][M_FACTOR_SOLVE * 3]);
-    }
     if (!plan) return KKT_EPOINTER;
     if (c < 0 || c >= (int)plan->cls.size()) return KKT_EDIMS;
     const kkt_plan::Cls &C = plan->cls[c];
+    Launch L[3];
+    launches_of(C, M_FACTOR_SOLVE, plan->nrhs, L);
     if (block_pad) *block_pad = C.bp;
     if (num_items) *num_items = C.item_cnt;
-    if (threads) *threads = (C.dense || C.dseg) ? 64 : C.nt;
-    if (lds_bytes) *lds_bytes = (int64_t)((C.dense || C.dseg) ? C.lds_dense : C.lds);
+    if (threads) *threads = L[0].nt;
+    if (lds_bytes) *lds_bytes = (int64_t)L[0].lds;
+    if (grid) {
+        std::lock_guard<std::mutex> guard(plan->mu);
+        int dev = 0;
+        const kkt_plan::Dev *d = hipGetDevice(&dev) == hipSuccess ? plan->dev_state(dev) : nullptr;
+        *grid = d ? d->grid[c][M_FACTOR_SOLVE][0] : 0;
+    }
     return KKT_OK;
 }
 
@@ -1272,7 +1020,8 @@ int kkt_plan_class_kind(const kkt_plan *plan, int32_t c, int32_t *kind)
     if (!plan || !kind) return KKT_EPOINTER;
     if (c < 0 || c >= (int)plan->cls.size()) return KKT_EDIMS;
     const kkt_plan::Cls &C = plan->cls[c];
-    *kind = C.dense ? KKT_CLASS_DENSE : C.dseg ? KKT_CLASS_DENSE_SEGMENTED : KKT_CLASS_GENERAL;
+    *kind = C.kind == kkt_plan::K_DENSE ? KKT_CLASS_DENSE
+                                        : C.kind == kkt_plan::K_DSEG ? KKT_CLASS_DENSE_SEGMENTED : KKT_CLASS_ROWLANE;
     return KKT_OK;
 }
 
@@ -1280,6 +1029,7 @@ int kkt_plan_set_class_events(kkt_plan *plan, int32_t c, hipEvent_t start, hipEv
 {
     if (!plan) return KKT_EPOINTER;
     if (c < 0 || c >= (int)plan->cls.size()) return KKT_EDIMS;
+    std::lock_guard<std::mutex> guard(plan->mu);
     plan->ev_start[c] = start;
     plan->ev_stop[c] = stop;
     return KKT_OK;
@@ -1291,7 +1041,7 @@ const char *kkt_status_string(int status)
     case KKT_OK: return "ok";
     case KKT_EDIMS: return "unsupported dimensions";
     case KKT_EPOINTER: return "null or misaligned pointer";
-    case KKT_EWORKSPACE: return "workspace too small or not initialised";
+    case KKT_EWORKSPACE: return "workspace not initialised for this plan on this device";
     case KKT_ELAUNCH: return "HIP launch error";
     case KKT_ENOTFACTORED: return "solve before factorization in this workspace";
     case KKT_EINTERNAL: return "internal error";

@@ -1,26 +1,6 @@
-// Device-side building blocks of the segmented block Cholesky (gfx950, FP64).
-//
-// One workgroup processes one work item: a segment of one system (Algorithm 1,
-// parallel phase; Algorithm 2 parallel phase; Algorithm 3 parallel phase) or the
-// reduced separator/arrow chain of one system plus its corner block (Algorithm 1
-// sequential phase, Eq. 7; Algorithms 2-3 sequential phases).
-//
-// Lane roles inside a workgroup of K<BP>::NT threads (BP = padded block size):
-//   tid <  BP                   "D lane"  r = tid: row r of the working diagonal block
-//   BP <= tid < 2 BP            "E lane"  r = tid - BP: row r of the coupling block to
-//                               the next pivot (hat E, hat F_k, or hat H_k on the
-//                               reduced chain)
-//   2 BP <= tid < 2 BP + 16     "G lane"  q = tid - 2 BP: row q of the arrow block
-//   2 BP + 16 <= tid < 3 BP + 16 "F lane" r = tid - 2 BP - 16: row r of the separator
-//                               fill block hat B^T_{ik} (segments k >= 2 only)
-// Every lane holds its one row in registers.  A stage step is one right-looking
-// elimination of the tall matrix [D_w ; E ; G ; F] (b + b + ng + b rows, b
-// columns): it produces hat D (potrf) and the panel hat P = P D^{-T} (the trsm of
-// Eq. 5 / Algorithm 1) in one sweep over the b columns, with the right-hand side
-// of the diagonal rows carried along (forward substitution, Algorithm 2).  The
-// Gram matrix of the panel rows then gives every update of Eq. (6)/(8): the next
-// diagonal block, the next arrow and fill rows, and the separator accumulators
-// hat A_k, hat Q_k, hat R_k.
+// Device-side building blocks shared by the stage sweeps of the segmented block
+// Cholesky (gfx950, FP64): system descriptors, the per-segment scratch layout,
+// kernel arguments, and small load / store / broadcast helpers.
 //
 // Padding: a block of size b < BP is embedded in BP x BP with identity on the
 // padded diagonal and zeros elsewhere; this is exact (the padded part factors to
@@ -28,6 +8,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <climits>
 
 namespace kkt_dev {
 
@@ -64,81 +45,45 @@ struct Args {
     double *dD, *dC, *dB, *dcorner;
     double *F;                          // factor region base
     const SysDesc *sys;
-    const int2 *items;
+    const int2 *items;                  // phase-1 work list of the launch class: (system, segment)
     int n_items;
-    int2 *s3_slot;
-    int *s3_ready;
+    const int *red;                     // segmented systems of the class (phase 2)
+    int n_red;
+    const int2 *s3;                     // segments of the segmented systems (phase 3)
     int n_s3;
-    int *ctr;                           // [0] item head, [1] s3 reserve, [2] s3 head, [3] error
-    int *arrive;                        // per system
+    int *ctr;                           // queue heads [0] phase 1, [1] phase 2, [2] phase 3
+    const int *abort;                   // nonzero: the workspace does not belong to this plan
     int *failidx;                       // per system: first failing stage (1-based), INT_MAX = none
     int *status;                        // per system: final info of the last factorization
     int *info;                          // caller's info (factor modes), may be null
-    const int *red;                     // systems of a segmented dense class (sequential phase)
-    int n_red;
     int nr;
-    int spin_limit;
 };
 
-template <int BP>
-struct K {
-    static constexpr int NROWS = 3 * BP + NGM;
-    static constexpr int NT = ((NROWS + 63) / 64) * 64;
-    static constexpr int PITCH = BP + 1;
-    static constexpr int E0 = BP;
-    static constexpr int G0 = 2 * BP;
-    static constexpr int F0 = 2 * BP + NGM;
-    static constexpr int BPX = BP > NGM ? BP : NGM;
-};
+__device__ __forceinline__ int load_status(const int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Next entry of a work list: thread 0 takes it from the queue counter (or, when
+// the call was refused on the device, a value past every list), every thread of
+// the workgroup gets it through LDS.
+__device__ __forceinline__ int next_work(int *ctr, const int *abort, int *misc)
+{
+    if (threadIdx.x == 0) misc[0] = (*abort != 0) ? INT_MAX : atomicAdd(ctr, 1);
+    __syncthreads();
+    const int it = misc[0];
+    __syncthreads();
+    return it;
+}
 
 struct LdsOff {
     int col, P, A, Q, R, W, Y, RP, XN, XS, XC, XG, PN, PS, PC, PG, misc, total;
 };
 
-// LDS layout in doubles for block class BP and nrhs right-hand sides.
-__host__ __device__ __forceinline__ LdsOff lds_offsets(int BP, int nr)
-{
-    LdsOff o;
-    const int BPX = BP > NGM ? BP : NGM;
-    const int PITCH = BP + 1 > NGM + 1 ? BP + 1 : NGM + 1;
-    const int NROWS = 3 * BP + NGM;
-    int t = 0;
-    o.col = t; t += 2 * BPX;
-    o.P = t;   t += NROWS * PITCH;      // panel rows / staging of the next stage's blocks
-    o.A = t;   t += BP * PITCH;         // hat A_k accumulator / fill staging in the solve
-    o.Q = t;   t += NGM * PITCH;        // hat Q_k accumulator
-    o.R = t;   t += NGM * NGM;          // hat R_k accumulator
-    o.W = t;   t += BPX * nr;           // rhs of the diagonal rows
-    o.Y = t;   t += BPX * nr;           // y of the current stage
-    o.RP = t;  t += NROWS * nr;         // rhs of the panel rows
-    o.XN = t;  t += BPX * nr;           // backward: solution at the next stage
-    o.XS = t;  t += BPX * nr;           //           solution at the separator
-    o.XC = t;  t += BPX * nr;           //           solution at the current stage
-    o.XG = t;  t += NGM * nr;           //           solution at g
-    o.PN = t;  t += BPX * nr;           // adjoint: primal x at the next stage
-    o.PS = t;  t += BPX * nr;           //          primal x at the separator
-    o.PC = t;  t += BPX * nr;           //          primal x at the current stage
-    o.PG = t;  t += NGM * nr;           //          primal x at g
-    o.misc = t; t += 8;
-    o.total = t;
-    return o;
-}
-
 struct Lds {
     double *col, *P, *A, *Q, *R, *W, *Y, *RP, *XN, *XS, *XC, *XG, *PN, *PS, *PC, *PG;
     int *misc;
 };
-
-__device__ __forceinline__ Lds make_lds(double *base, int BP, int nr)
-{
-    const LdsOff o = lds_offsets(BP, nr);
-    Lds L;
-    L.col = base + o.col; L.P = base + o.P; L.A = base + o.A; L.Q = base + o.Q; L.R = base + o.R;
-    L.W = base + o.W; L.Y = base + o.Y; L.RP = base + o.RP; L.XN = base + o.XN; L.XS = base + o.XS;
-    L.XC = base + o.XC; L.XG = base + o.XG; L.PN = base + o.PN; L.PS = base + o.PS; L.PC = base + o.PC;
-    L.PG = base + o.PG; L.misc = reinterpret_cast<int *>(base + o.misc);
-    return L;
-}
 
 // ---------------------------------------------------------------- small helpers
 __device__ __forceinline__ int seg_first(const SysDesc &s, int k) { return k == 1 ? 0 : s.N1 + (k - 2) * (s.Nk + 1) + 1; }
@@ -304,7 +249,7 @@ __device__ __forceinline__ void store_block(double *dst, const double *lds, int 
 }
 
 // A word of zeros in device memory that nothing writes.
-__device__ double zero_word[2];
+static __device__ double zero_word[2];
 
 // src[i] if ok, else 0, with neither a branch nor a select after the load: the
 // address is chosen instead (the zero word when !ok), so the value can stay in
@@ -312,50 +257,6 @@ __device__ double zero_word[2];
 __device__ __forceinline__ double ld_or_zero(const double *src, int i, bool ok)
 {
     return *(ok ? src + i : zero_word);
-}
-
-// ---------------------------------------------------------------- elimination
-// Right-looking column elimination of the tall matrix held one row per lane:
-// D lanes (tid < BP) hold the working diagonal rows (lower part meaningful), all
-// other lanes a panel row (zero rows are harmless).  After the call D lanes hold
-// rows of hat D (lower) and panel lanes rows of hat P = P hat D^{-T}.  With fwd,
-// W (rows of the diagonal, pitch nr) is eliminated along and Y = hat D^{-1} W.
-// One barrier per column (the column buffer is double-buffered).  Returns true
-// if a pivot was not positive and finite.
-template <int BP>
-__device__ __forceinline__ bool eliminate(double (&row)[BP], const Lds &L, int nr, bool fwd)
-{
-    const int tid = threadIdx.x;
-    bool bad = false;
-#pragma unroll
-    for (int c = 0; c < BP; ++c) {
-        double *buf = L.col + (c & 1) * BP;
-        if (tid < BP && tid >= c) buf[tid] = row[c];
-        __syncthreads();
-        const double dcc = buf[c];
-        bad |= !(dcc > 0.0) || !isfinite(dcc);
-        double d, inv;
-        sqrt_rsqrt(dcc, d, inv);
-        const bool act = tid > c;                 // diagonal rows below the pivot, every panel row
-        const double v = row[c] * inv;            // hat D[tid][c] or hat P[row][c]
-        if (tid == c) row[c] = d;
-        else if (act) row[c] = v;
-        const double f = act ? v * inv : 0.0;
-#pragma unroll
-        for (int l = c + 1; l < BP; ++l) row[l] = fma(-f, buf[l], row[l]);
-        if (fwd) {
-            if (tid == c) {
-                for (int j = 0; j < nr; ++j) L.Y[c * nr + j] = L.W[c * nr + j] * inv;
-            } else if (act && tid < BP) {
-                for (int j = 0; j < nr; ++j) L.W[tid * nr + j] = fma(-f, L.W[c * nr + j], L.W[tid * nr + j]);
-            }
-        }
-        // materialise this column's updates here: without it the compiler sinks them
-        // past the next barriers and keeps every loaded column value live across steps
-        pin_row<BP>(row);
-    }
-    __syncthreads();
-    return bad;
 }
 
 // Lane c of wave 0 holds acc = (rhs)[c] and dcol[l] = T[l][c] of a lower

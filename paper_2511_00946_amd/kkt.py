@@ -13,7 +13,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkkt.so")
 
 KKT_OK = 0
-MAX_B, MAX_NG, MAX_NRHS = 32, 16, 8
+MAX_B, MAX_NG, MAX_NRHS = 48, 16, 8
+NUM_CLASSES = 5
+CLASS_BLOCKS = (8, 16, 24, 32, 48)
+WS_FOREIGN = 2
 
 
 class Dims(ctypes.Structure):
@@ -40,18 +43,21 @@ class SystemLayout(ctypes.Structure):
 
 
 class CostModel(ctypes.Structure):
-    """Per padded block-size class (8, 16, 24, 32): stage times of first segments,
+    """Per padded block-size class (8, 16, 24, 32, 48): stage times of first segments,
     fill-carrying segments and reduced stages, item overhead, concurrent items of
     unsegmented systems (workers) and of segmented ones (workers_seg, 0 = workers)."""
-    _fields_ = [("t_first", ctypes.c_double * 4), ("t_fill", ctypes.c_double * 4),
-                ("t_red", ctypes.c_double * 4), ("t_item", ctypes.c_double * 4),
-                ("workers", ctypes.c_double * 4), ("workers_seg", ctypes.c_double * 4)]
+    _fields_ = [("t_first", ctypes.c_double * NUM_CLASSES), ("t_fill", ctypes.c_double * NUM_CLASSES),
+                ("t_red", ctypes.c_double * NUM_CLASSES), ("t_item", ctypes.c_double * NUM_CLASSES),
+                ("workers", ctypes.c_double * NUM_CLASSES), ("workers_seg", ctypes.c_double * NUM_CLASSES)]
 
     @classmethod
     def from_dict(cls, d):
         m = cls()
         for k in ("t_first", "t_fill", "t_red", "t_item", "workers", "workers_seg"):
-            for i, v in enumerate(d.get(k, [0.0] * 4)):
+            vals = list(d.get(k, [0.0] * NUM_CLASSES))
+            if len(vals) != NUM_CLASSES:
+                raise ValueError("cost model field %s needs %d entries, got %d" % (k, NUM_CLASSES, len(vals)))
+            for i, v in enumerate(vals):
                 getattr(m, k)[i] = float(v)
         return m
 
@@ -89,13 +95,11 @@ def lib():
         L.kkt_plan_set_class_events.argtypes = [vp, i32, vp, vp]
         L.kkt_plan_class_kind.argtypes = [vp, i32, ctypes.POINTER(i32)]
         L.kkt_workspace_error.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
-        L.kkt_plan_set_spin_limit.argtypes = [vp, i32]
         L.kkt_status_string.restype = ctypes.c_char_p
         L.kkt_status_string.argtypes = [ctypes.c_int]
         for name in ("kkt_plan_create", "kkt_plan_create_tuned", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
                      "kkt_workspace_init", "kkt_factor", "kkt_solve", "kkt_factor_solve", "kkt_solve_adjoint",
-                     "kkt_plan_class_info", "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error",
-                     "kkt_plan_set_spin_limit"):
+                     "kkt_plan_class_info", "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -104,7 +108,7 @@ def lib():
 EXPORTED = ("kkt_plan_create", "kkt_plan_create_tuned", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
             "kkt_plan_factor_offset", "kkt_workspace_init", "kkt_factor", "kkt_solve",
             "kkt_factor_solve", "kkt_solve_adjoint", "kkt_status_string", "kkt_plan_class_info",
-            "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error", "kkt_plan_set_spin_limit")
+            "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error")
 
 
 def _check(rc, what):
@@ -259,7 +263,7 @@ class Plan:
         return out
 
     def classes(self, with_grid=False):
-        """[(padded block size, items, threads, lds bytes[, launched workgroups])] per persistent launch."""
+        """[(padded block size, items, threads, lds bytes[, workgroups])] per launch class (its first launch)."""
         out = []
         for c in range(self.info.num_classes):
             bp, it, nt, lds, gr = (ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(),
@@ -271,7 +275,7 @@ class Plan:
         return out
 
     def class_kinds(self):
-        """Kind of each launch class: 0 general, 1 dense (whole systems), 2 dense segmented."""
+        """Kind of each launch class: 0 row-lane, 1 dense (whole systems), 2 dense segmented."""
         out = []
         for c in range(self.info.num_classes):
             k = ctypes.c_int32()
@@ -280,13 +284,11 @@ class Plan:
         return out
 
     def workspace_error(self, ws, stream=None):
-        """Nonzero if a worker of the last call gave up waiting for a handover (results invalid)."""
+        """WS_FOREIGN if the last call on ws found another plan's tables there (its kernels
+        then returned without touching their outputs), else 0."""
         f = ctypes.c_int32()
         _check(lib().kkt_workspace_error(self._h, _ptr(ws), _stream(stream), ctypes.byref(f)), "kkt_workspace_error")
         return int(f.value)
-
-    def set_spin_limit(self, limit):
-        _check(lib().kkt_plan_set_spin_limit(self._h, int(limit)), "kkt_plan_set_spin_limit")
 
     def set_class_events(self, c, start, stop):
         """start / stop: raw hipEvent_t handles (ints) or None."""

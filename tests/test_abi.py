@@ -44,7 +44,7 @@ def test_plan_partition_matches_eq13(N, p):
 
 def test_plan_rejects_bad_dims():
     kkt = _kkt()
-    for d in [(0, 4, 0, 1), (5, 0, 0, 1), (5, 33, 0, 1), (5, 4, 17, 1), (5, 4, 0, 4), (10, 4, 0, 3, 5)]:
+    for d in [(0, 4, 0, 1), (5, 0, 0, 1), (5, 49, 0, 1), (5, 4, 17, 1), (5, 4, 0, 4), (10, 4, 0, 3, 5)]:
         with pytest.raises(kkt.KKTError):
             kkt.Plan([d])
     with pytest.raises(kkt.KKTError):
@@ -88,10 +88,13 @@ def test_factor_words_count_fill():
 
 # ---- segment-count choice from a cost model (host logic of the plan)
 
+CLS = (8, 16, 24, 32, 48)
+
+
 def _model(W=512.0):
-    b3 = [float(bp) ** 3 for bp in (8, 16, 24, 32)]
+    b3 = [float(bp) ** 3 for bp in CLS]
     return {"t_first": [7 / 3 * x for x in b3], "t_fill": [19 / 3 * x for x in b3],
-            "t_red": [10 / 3 * x for x in b3], "t_item": [0.0] * 4, "workers": [W] * 4}
+            "t_red": [10 / 3 * x for x in b3], "t_item": [0.0] * 5, "workers": [W] * 5}
 
 
 def _est(N, p, c, m):
@@ -113,13 +116,13 @@ def _est(N, p, c, m):
     return max(s1, sk) + (p - 1) * tr, s1 + (p - 1) * sk + (p - 1) * tr
 
 
-@pytest.mark.parametrize("N,b,ng", [(2048, 6, 8), (128, 32, 0), (256, 16, 4), (40, 24, 2)])
+@pytest.mark.parametrize("N,b,ng", [(2048, 6, 8), (128, 32, 0), (256, 16, 4), (40, 24, 2), (128, 42, 0)])
 def test_cost_model_single_system_near_optimal(N, b, ng):
     kkt = _kkt()
     m = _model()
     plan = kkt.Plan([(N, b, ng, 0)], cost_model=m)
     (p,) = plan.segments()
-    c = [8, 16, 24, 32].index(next(bp for bp in (8, 16, 24, 32) if b <= bp))
+    c = CLS.index(next(bp for bp in CLS if b <= bp))
     span = {q: max(_est(N, q, c, m)[1] / m["workers"][c], _est(N, q, c, m)[0])
             for q in range(1, (N + 1) // 2 + 1)}
     assert p > 1
@@ -140,7 +143,7 @@ def test_tuned_split_uses_the_model_balance():
     not the flop ratio 19/7); a system with p given keeps sigma = 19/7."""
     kkt = _kkt()
     b3 = float(32) ** 3
-    m = dict(_model(), t_first=[b3] * 4, t_fill=[1.4 * b3] * 4)
+    m = dict(_model(), t_first=[b3] * 5, t_fill=[1.4 * b3] * 5)
     N = 256
     plan = kkt.Plan([(N, 32, 4, 0)], cost_model=m)
     (p,) = plan.segments()
@@ -204,8 +207,8 @@ def test_cost_model_prices_segments_in_their_own_pool():
     them fit on the device at once, splitting costs more and is chosen less."""
     kkt = _kkt()
     dims = [(400, 16, 2, 0)] * 6 + [(24, 16, 2, 0)] * 40
-    wide = dict(_model(W=512.0), workers_seg=[512.0] * 4)
-    narrow = dict(_model(W=512.0), workers_seg=[2.0] * 4)
+    wide = dict(_model(W=512.0), workers_seg=[512.0] * 5)
+    narrow = dict(_model(W=512.0), workers_seg=[2.0] * 5)
     pw = kkt.Plan(dims, cost_model=wide).segments()
     pn = kkt.Plan(dims, cost_model=narrow).segments()
     assert pw[0] > 1 and pn[0] < pw[0]
@@ -220,3 +223,42 @@ def test_cost_model_keeps_fixed_segment_counts():
     assert ps[0] == 3 and ps[2] == 1 and ps[1] > 1
     d = kkt.Plan(dims)                                   # default model, same choice
     assert d.segments() == ps
+
+
+def test_cost_model_needs_every_class():
+    kkt = _kkt()
+    with pytest.raises(ValueError):
+        kkt.Plan([(64, 8, 2, 0)], cost_model=dict(_model(), t_item=[0.0] * 4))
+
+
+def test_calls_refuse_an_uninitialised_workspace():
+    """Every compute call checks that its workspace was initialised for the plan
+    (kkt_workspace_init) before it enqueues anything: KKT_EWORKSPACE (-3).  Pointers
+    that were never handed to the device are enough here, since no kernel runs."""
+    kkt = _kkt()
+    L = kkt.lib()
+    plan = kkt.Plan([(8, 4, 2, 1), (9, 6, 0, 2)], nrhs=1)
+    fake = ctypes.c_void_p(1 << 20)          # 256-byte aligned, never initialised
+    buf = ctypes.c_void_p(1 << 21)
+    assert L.kkt_factor(plan._h, buf, buf, buf, buf, fake, buf, None) == -3
+    assert L.kkt_factor_solve(plan._h, buf, buf, buf, buf, fake, buf, buf, None) == -3
+    assert L.kkt_solve(plan._h, fake, buf, None) == -3
+    assert L.kkt_solve_adjoint(plan._h, fake, buf, buf, buf, buf, buf, buf, None) == -3
+    # misaligned workspace: a pointer error, checked first
+    assert L.kkt_factor(plan._h, buf, buf, buf, buf, ctypes.c_void_p((1 << 20) + 8), buf, None) == -2
+
+
+def test_plan_flop_counts_are_the_standard_counts_of_the_algorithm():
+    """kkt_plan_info.factor_flops / solve_flops equal the operation lists of
+    Algorithms 1-3 (oracle/flops.py) priced with standard counts (potrf n^3/3,
+    trsm m n^2, syrk n^2 k, gemm 2 m n k, trsv n^2, gemv 2 m n)."""
+    from oracle import flops
+    kkt = _kkt()
+    for (N, b, ng, p, nr) in [(16, 4, 2, 1, 1), (40, 6, 8, 4, 4), (128, 42, 0, 8, 1), (37, 5, 3, 6, 2),
+                              (9, 3, 0, 2, 1), (64, 24, 4, 4, 1)]:
+        plan = kkt.Plan([(N, b, ng, p)], nrhs=nr)
+        seg = plan.segment_lengths(0)
+        f = sum(flops.std_cost(op, m, n, k) for _, op, m, n, k in flops.factor_ops(seg, b, ng))
+        sv = nr * sum(flops.std_cost(op, m, n, k) for _, op, m, n, k in flops.solve_ops(seg, b, ng))
+        assert plan.info.factor_flops == pytest.approx(float(f), rel=1e-12), (N, b, ng, p)
+        assert plan.info.solve_flops == pytest.approx(float(sv), rel=1e-12), (N, b, ng, p)

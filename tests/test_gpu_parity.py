@@ -138,6 +138,18 @@ def test_factor_then_solve_matches(p):
     check_solution(plan, x, systems)
 
 
+def test_factor_then_solve_every_group_segmented():
+    """The solve-only mode of segmented systems of every block group (row-lane
+    sweeps for all three phases), beside whole systems of the dense groups."""
+    dims = [(17, 7, 2), (19, 14, 3), (16, 22, 1), (15, 30, 4), (9, 16, 2), (8, 32, 0)]
+    systems = gen(78, dims, nrhs=3)
+    ps = [3, 4, 2, 3, 1, 1]
+    plan, pools, ws, x, info = run(systems, ps, 3, mode="separate")
+    assert (info == 0).all()
+    check_factor(plan, ws, systems)
+    check_solution(plan, x, systems)
+
+
 def test_small_workload_all_p():
     s = workloads.single("small")
     for p in (1, 2, 4, 8):
@@ -235,19 +247,23 @@ def test_repeat_runs_bitwise_identical():
 
 ADJ_CASES = {
     # the last three are whole (p = 1) systems of the dense classes
-    "mixed": ([(12, 6, 3), (9, 8, 0), (7, 16, 2), (6, 24, 4), (5, 32, 0)], 2),
+    "mixed": ([(12, 6, 3), (9, 8, 0), (7, 16, 2), (6, 24, 4), (5, 32, 0)], 2, None),
     # the maxima: block size 32, 16 arrow rows, 8 rhs
-    "maxima": ([(9, 8, 16), (6, 32, 16), (7, 16, 16)], 8),
+    "maxima": ([(9, 8, 16), (6, 32, 16), (7, 16, 16)], 8, None),
+    # segmented systems of every block group (their adjoint runs on the row-lane sweeps)
+    "segmented": ([(12, 12, 3), (14, 20, 2), (13, 28, 4), (11, 5, 1), (15, 32, 16)], 3, [3, 2, 3, 4, 2]),
 }
 
 
-@pytest.mark.parametrize("case", ["mixed", "maxima"])
+@pytest.mark.parametrize("case", ["mixed", "maxima", "segmented"])
 @pytest.mark.parametrize("p", [1, 3])
 def test_adjoint_matches_oracle(p, case):
     kkt = _kkt()
-    dims, nr = ADJ_CASES[case]
+    dims, nr, fixed = ADJ_CASES[case]
+    if fixed is not None and p == 1:
+        pytest.skip("the segmented case fixes its own segment counts")
     systems = gen(21, dims, nrhs=nr, with_w=True)
-    ps = [p, min(p, 2)] + [1] * (len(dims) - 2)
+    ps = fixed if fixed is not None else [p, min(p, 2)] + [1] * (len(dims) - 2)
     plan, pools, ws, x, info = run(systems, ps, nr)
     assert (info == 0).all()
     gx = torch.from_numpy(workloads.pack(systems)["w"]).cuda()
@@ -276,26 +292,30 @@ def test_adjoint_matches_oracle(p, case):
             assert err < 1e-9, (name, s, err)
 
 
-def test_spin_limit_error_is_reported():
-    """A worker whose bounded wait runs out raises the workspace error flag instead of hanging."""
+def test_foreign_workspace_is_refused_on_device():
+    """A workspace re-initialised by another plan still passes the first plan's
+    host-side registry; the reset kernel then finds the other plan's tag, every
+    kernel of the call returns at once (no output written) and kkt_workspace_error
+    reports it.  The first plan's own workspace is unaffected."""
     kkt = _kkt()
-    systems = gen(31, [(64, 8, 2)])
-    plan = kkt.Plan([(64, 8, 2, 16)], nrhs=1)
-    plan.set_spin_limit(1)
+    systems = gen(31, [(20, 8, 2), (12, 16, 0)])
+    plan_a = kkt.Plan([(20, 8, 2, 2), (12, 16, 0, 1)], nrhs=1)
+    plan_b = kkt.Plan([(20, 8, 2, 2), (12, 16, 0, 1)], nrhs=1)
     pools = kkt.pack_to_device(workloads.pack(systems))
-    ws = plan.new_workspace()
-    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = plan_a.new_workspace()
+    plan_b.init_workspace(ws)
+    info = torch.full((2,), -7, dtype=torch.int32, device="cuda")
     x = pools["r"].clone()
-    _say("gpu case: spin limit 1, N=64 b=8 ng=2 p=16")
-    plan.factor_solve(pools["D"], pools["C"], pools["B"], pools["corner"], ws, x, info)
+    _say("gpu case: foreign workspace")
+    plan_a.factor_solve(pools["D"], pools["C"], pools["B"], pools["corner"], ws, x, info)
     torch.cuda.synchronize()
-    assert plan.workspace_error(ws) != 0
-    plan.set_spin_limit(1 << 22)
-    x = pools["r"].clone()
-    plan.factor_solve(pools["D"], pools["C"], pools["B"], pools["corner"], ws, x, info)
+    assert plan_a.workspace_error(ws) == kkt.WS_FOREIGN
+    assert torch.equal(x, pools["r"]) and info.tolist() == [-7, -7]
+    plan_a.init_workspace(ws)
+    plan_a.factor_solve(pools["D"], pools["C"], pools["B"], pools["corner"], ws, x, info)
     torch.cuda.synchronize()
-    assert plan.workspace_error(ws) == 0
-    check_solution(plan, x, systems)
+    assert plan_a.workspace_error(ws) == 0 and info.tolist() == [0, 0]
+    check_solution(plan_a, x, systems)
 
 
 def test_workspaces_keep_their_own_factors():

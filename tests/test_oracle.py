@@ -312,3 +312,75 @@ def test_op_list_p1_equals_sequential_complexity():
     """p = 1 is the sequential method: O_seq = (7/3 N - 2) b^3 (Sec. 3.3)."""
     for N in (1, 2, 5, 40):
         assert flops.phase_totals(flops.factor_ops([N], 1))["first"] == partition.o_seq(N)
+
+
+# ---- the op lists with an arrow (n_g > 0), against a symbolic block Cholesky
+
+def _symbolic_block_cholesky_flops(N, seg, b, ng):
+    """Standard flops of the right-looking block Cholesky of P Psi P^T (Sec. 3.1
+    order: segment stages, separators, g) found by a symbolic factorization of the
+    block pattern (fill created as it appears), and of the two block triangular
+    solves with one rhs.  Written from the textbook definition, not from Algorithms
+    1-3: column j factors its diagonal block (potrf), solves every nonzero block
+    below it (trsm) and updates every pair of them (syrk on the diagonal, gemm off
+    it); a solve takes one trsv per diagonal block and one gemv per nonzero block
+    in each direction."""
+    order = kkt.elimination_order(N, seg)
+    pos = {s: i for i, s in enumerate(order)}
+    M = N + (1 if ng else 0)
+    size = [b] * N + ([ng] if ng else [])
+    nz = set()
+    for s in range(N - 1):
+        i, j = pos[s + 1], pos[s]
+        nz.add((max(i, j), min(i, j)))
+    if ng:
+        for s in range(N):
+            nz.add((N, pos[s]))
+    fac = Fraction(0)
+    sol = Fraction(0)
+    for j in range(M):
+        nj = size[j]
+        fac += Fraction(nj ** 3, 3)
+        sol += 2 * nj * nj
+        below = sorted(i for (i, jj) in nz if jj == j)
+        for i in below:
+            fac += size[i] * nj * nj
+            sol += 2 * (2 * size[i] * nj)
+        for x, i in enumerate(below):
+            for l in below[:x + 1]:
+                if i == l:
+                    fac += size[i] * size[i] * nj
+                else:
+                    fac += 2 * size[i] * size[l] * nj
+                    nz.add((i, l))
+    return fac, sol
+
+
+@pytest.mark.parametrize("N,seg,b,ng", [(16, [16], 4, 2), (40, [5, 4, 4, 4, 4, 4, 4, 4], 6, 8),
+                                        (30, [9, 6, 6, 6], 3, 5), (9, [3, 2, 2], 2, 1), (12, [4, 3, 3], 5, 0),
+                                        (21, [6, 4, 4, 4], 3, 4)])
+def test_op_lists_with_arrow_equal_symbolic_block_cholesky(N, seg, b, ng):
+    """The operation lists of Algorithms 1-3 with a global block (n_g > 0) cost
+    exactly what a symbolic right-looking block Cholesky of the permuted matrix
+    costs, plus the paper's separate accumulation of the corner partials (gead:
+    n_g^2 per segment for the factor, n_g per segment for a solve)."""
+    assert sum(seg) + len(seg) - 1 == N and len(set(seg[1:])) <= 1
+    p = len(seg)
+    fac, sol = _symbolic_block_cholesky_flops(N, seg, b, ng)
+    f = sum(flops.std_cost(op, m, n, k) for _, op, m, n, k in flops.factor_ops(seg, b, ng))
+    s = sum(flops.std_cost(op, m, n, k) for _, op, m, n, k in flops.solve_ops(seg, b, ng))
+    gead_f = ng * ng * p if ng else 0
+    gead_s = ng * p if ng else 0
+    assert f == fac + gead_f
+    assert s == sol + gead_s
+
+
+def test_symbolic_count_catches_a_dropped_arrow_term():
+    """The pin above is sensitive to the arrow terms: removing one gemm(ng, b, b)
+    from the op list of a segment with fill rows changes the total."""
+    seg, b, ng = [9, 6, 6, 6], 3, 5
+    fac, _ = _symbolic_block_cholesky_flops(30, seg, b, ng)
+    ops = flops.factor_ops(seg, b, ng)
+    i = next(x for x, o in enumerate(ops) if o[0] == "other" and o[1] == "gemm" and o[2] == ng)
+    f = sum(flops.std_cost(op, m, n, k) for _, op, m, n, k in ops[:i] + ops[i + 1:])
+    assert f != fac + ng * ng * len(seg)
