@@ -221,17 +221,19 @@ __device__ __forceinline__ int opaque_tid()
 // group right before its FMAs (a scheduling barrier per group keeps the
 // broadcast values from piling up in scalar registers).  After the call lanes
 // [0, W) hold the rows of L (entries right of the diagonal are stale) and panel
-// lanes the rows of P L^{-T}.  Returns true if a pivot was not positive and finite.
+// lanes the rows of P L^{-T}.  A pivot that is not positive and finite leaves a
+// NaN on the diagonal (the reciprocal square root of a value <= 0, 0 or infinity
+// makes sqrt_rsqrt return NaN), which the callers test once after the sweep
+// (testing every pivot here would keep all of them live to the end).
 // Step c of the elimination, then the steps after it: the steps are expanded by
 // template recursion, so every row index is a compile-time constant for any W
 // (a loop over the columns is too large to unroll for the widest blocks, and a
 // rolled loop would index the row at run time and force it out of registers).
 template <int W, int c>
-__device__ __forceinline__ void elim_step(double (&row)[W], bool panel, int lane, bool &bad)
+__device__ __forceinline__ void elim_step(double (&row)[W], bool panel, int lane)
 {
     if constexpr (c < W) {
         const double dcc = readlane_d(row[c], c);
-        bad |= !(dcc > 0.0) || !isfinite(dcc);
         double d, inv;
         sqrt_rsqrt(dcc, d, inv);
         const bool below = (lane < W && lane > c) || panel;
@@ -254,16 +256,21 @@ __device__ __forceinline__ void elim_step(double (&row)[W], bool panel, int lane
             }
             if (W > 16) __builtin_amdgcn_sched_barrier(0);
         }
-        elim_step<W, c + 1>(row, panel, lane, bad);
+        elim_step<W, c + 1>(row, panel, lane);
     }
 }
 
 template <int W>
-__device__ __forceinline__ bool elim_wave(double (&row)[W], bool panel, int lane)
+__device__ __forceinline__ void elim_wave(double (&row)[W], bool panel, int lane)
 {
-    bool bad = false;
-    elim_step<W, 0>(row, panel, lane, bad);
-    return bad;
+    elim_step<W, 0>(row, panel, lane);
+}
+
+// True on every lane of the wave if any lane with `mine` set holds a diagonal
+// entry that is not positive and finite.
+__device__ __forceinline__ bool any_bad_pivot(bool mine, double d)
+{
+    return __any(mine && !(d > 0.0 && isfinite(d)));
 }
 
 // Rows held by a wave other than the pivot wave: P <- P L^{-T} against L in LDS
@@ -275,13 +282,19 @@ __device__ __forceinline__ void trsm_step(double (&row)[W], const double *Lr, in
     if constexpr (c < W) {
         const double v = row[c] * dinv[c];
         row[c] = v;
+        // the column index behind an opaque copy that depends on this step's
+        // multiplier: the reads of column c cannot be issued before the step
+        // (their addresses are otherwise constants, and every column's reads would
+        // be issued at once and spilled)
+        int cc = c;
+        asm volatile("" : "+v"(cc) : "v"(v));
 #pragma unroll
         for (int m0 = 0; m0 < W; m0 += 8) {
             if (m0 + 8 <= c + 1) continue;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int m = m0 + q;
-                if (m > c && m < W) row[m] = fma(-v, Lr[m * P + c], row[m]);
+                if (m > c && m < W) row[m] = fma(-v, Lr[m * P + cc], row[m]);
             }
             if (W > 16) __builtin_amdgcn_sched_barrier(0);
         }
@@ -386,6 +399,31 @@ __device__ __forceinline__ void dot4(const double (&row)[W], const double *B, in
             }
         }
         if (W > 16) __builtin_amdgcn_sched_barrier(0);
+    }
+    s[0] = t0; s[1] = t1; s[2] = t2; s[3] = t3;
+}
+
+// The same with the own row read from LDS (own, contiguous), eight entries at a
+// time: used by the widest class, whose row registers would otherwise stay live
+// through the Gram.
+template <int W>
+__device__ __forceinline__ void dot4_lds(const double *own, const double *B, int P, double (&s)[4])
+{
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+#pragma unroll
+    for (int c0 = 0; c0 < W; c0 += 8) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int c = c0 + q;
+            if (c < W) {
+                const double o = own[c];
+                t0 = fma(o, B[c], t0);
+                t1 = fma(o, B[P + c], t1);
+                t2 = fma(o, B[2 * P + c], t2);
+                t3 = fma(o, B[3 * P + c], t3);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
     s[0] = t0; s[1] = t1; s[2] = t2; s[3] = t3;
 }
@@ -603,8 +641,7 @@ __device__ __forceinline__ int wave_factor(const Args &a, const SysDesc &sd, int
 
         // ---- (2) elimination: hat D, the panel rows, y (Algorithm 1 potrf / trsm, Algorithm 2)
         if (w0) {
-            const bool bad = elim_wave<BP>(row, panel, lane);
-            if (bad && !failed) failed = gs + 1;
+            elim_wave<BP>(row, panel, lane);
             double *dst = L.pnl + prow * P;
             if (isD || isG || (NW == 1 && panel)) {
 #pragma unroll
@@ -612,7 +649,9 @@ __device__ __forceinline__ int wave_factor(const Args &a, const SysDesc &sd, int
             }
             wave_sync();
             // the diagonal entry read back from LDS (not by indexing a register array)
-            const double dinv = isD ? 1.0 / dst[r] : 1.0;
+            const double dg = isD ? dst[r] : 1.0;
+            if (any_bad_pivot(isD, dg) && !failed) failed = gs + 1;
+            const double dinv = isD ? 1.0 / dg : 1.0;
             if (isD) L.dinv[r] = dinv;
             if (FWD) {
                 // forward substitution (Algorithm 2): y = hat D^{-1} w on the D rows, and the
@@ -649,7 +688,9 @@ __device__ __forceinline__ int wave_factor(const Args &a, const SysDesc &sd, int
 
         // ---- (4) Gram of the panel rows (Eqs. 4, 6, 8a, 8b).  Every thread dots
         // its own row with broadcast rows; threads without an output write to the
-        // sink row.
+        // sink row.  The widest class reads its own row back from LDS (OWN_LDS).
+        constexpr bool OWN_LDS = BP > 32;
+        const double *own = L.pnl + prow * P;
         gsync<NW>();
         if (hasE) {
             // with hat E (hat F_k at a segment end): E threads -hat E hat E^T (the next
@@ -662,7 +703,8 @@ __device__ __forceinline__ int wave_factor(const Args &a, const SysDesc &sd, int
 #pragma unroll 1
             for (int m0 = 0; m0 < BP; m0 += 4) {
                 double s4[4];
-                dot4<BP>(row, Eb + m0 * P, P, s4);
+                if (OWN_LDS) dot4_lds<BP>(own, Eb + m0 * P, P, s4);
+                else dot4<BP>(row, Eb + m0 * P, P, s4);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) o[m0 + q] = -s4[q];
             }
@@ -688,7 +730,8 @@ __device__ __forceinline__ int wave_factor(const Args &a, const SysDesc &sd, int
 #pragma unroll 1
             for (int q0 = 0; q0 < ng; q0 += 4) {
                 double s4[4];
-                dot4<BP>(row, Gb + q0 * P, P, s4);
+                if (OWN_LDS) dot4_lds<BP>(own, Gb + q0 * P, P, s4);
+                else dot4<BP>(row, Gb + q0 * P, P, s4);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) o[q0 + q] -= s4[q];
             }
@@ -700,7 +743,8 @@ __device__ __forceinline__ int wave_factor(const Args &a, const SysDesc &sd, int
 #pragma unroll 1
             for (int m0 = 0; m0 < BP; m0 += 4) {
                 double s4[4];
-                dot4<BP>(row, Fb + m0 * P, P, s4);
+                if (OWN_LDS) dot4_lds<BP>(own, Fb + m0 * P, P, s4);
+                else dot4<BP>(row, Fb + m0 * P, P, s4);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) o[m0 + q] -= s4[q];
             }
@@ -1184,7 +1228,7 @@ __device__ __forceinline__ bool corner_factor_w(const Args &a, const SysDesc &sd
         for (int m = 0; m < NGM; ++m) row[m] = (q < ng) ? (m < ng ? CR[q * PC + m] : 0.0) : (m == q ? 1.0 : 0.0);
 #pragma unroll
         for (int j = 0; j < MAX_NRHS_DEV; ++j) w[j] = (FWD && q < ng && j < nr) ? CW[q * RP + j] : 0.0;
-        bad = elim_wave<NGM>(row, false, q);
+        elim_wave<NGM>(row, false, q);
         double *Lg = a.F + sd.oLg;
         if (q < ng) {
 #pragma unroll
@@ -1196,6 +1240,7 @@ __device__ __forceinline__ bool corner_factor_w(const Args &a, const SysDesc &sd
             for (int m = 0; m < NGM; ++m) CR[q * PC + m] = (m <= q) ? row[m] : 0.0;
         }
         wave_sync();
+        bad = any_bad_pivot(q < ng, CR[(q < NGM ? q : 0) * PC + (q < NGM ? q : 0)]);
         if (FWD) {
             const double dq = (q < ng) ? 1.0 / CR[(q < NGM ? q : 0) * PC + (q < NGM ? q : 0)] : 1.0;
             fsub_wave<NGM>(row, w, nr, false, q, dq);
@@ -1320,41 +1365,43 @@ __global__ void __launch_bounds__(WC<BP>::NT) kkt_wave_p1(Args a)
         if (it >= a.n_items) break;
         const int2 w = a.items[it];
         const SysDesc sd = a.sys[w.x];
-        if (sd.p == 1) {
-            int info = 0;
+        const bool whole = sd.p == 1;
+        // one instance of each sweep serves whole systems (segment 1 of 1) and segments
+        int f = 0;
+        if (FACT) {
+            f = wave_factor<BP, FWD, false>(a, sd, whole ? 1 : w.y, L);
+            if (threadIdx.x == 0) {
+                if (!whole && f) atomicMin(&a.failidx[w.x], f);
+                L.misc[1] = f;
+            }
+        } else {
+            if (threadIdx.x == 0) L.misc[1] = load_status(&a.status[w.x]);
+            wave_forward<BP, false>(a, sd, whole ? 1 : w.y, L);
+        }
+        __syncthreads();
+        if (whole) {
+            int info = L.misc[1];
             if (FACT) {
-                const int f = wave_factor<BP, FWD, false>(a, sd, 1, L);
-                __syncthreads();
                 const bool cf = corner_factor_w<NT, FWD>(a, sd, L.nxt, L.nxt + NGM * (NGM + 1), nullptr, nullptr);
                 if (threadIdx.x == 0) {
-                    info = f ? f : (cf ? sd.N + 1 : 0);
+                    info = info ? info : (cf ? sd.N + 1 : 0);
                     a.status[w.x] = info;
                     if (a.info) a.info[w.x] = info;
                     L.misc[1] = info;
                 }
                 __syncthreads();
                 info = L.misc[1];
-                if (FWD) wave_backward<BP, false, false>(a, sd, 1, L);
             } else {
-                if (threadIdx.x == 0) L.misc[1] = load_status(&a.status[w.x]);
-                wave_forward<BP, false>(a, sd, 1, L);
-                __syncthreads();
-                info = L.misc[1];
                 corner_solve_w<NT>(a, sd, L.nxt, L.nxt + NGM * (NGM + 1), nullptr);
                 if (MODE == M_ADJOINT) corner_grad_w<NT>(a, sd);
-                __syncthreads();
-                wave_backward<BP, MODE == M_ADJOINT, false>(a, sd, 1, L);
             }
-            if (MODE != M_FACTOR && info != 0) nan_fill<NT>(a, sd, 0, sd.N, true);
             __syncthreads();
-        } else if (FACT) {
-            const int f = wave_factor<BP, FWD, false>(a, sd, w.y, L);
-            if (threadIdx.x == 0 && f) atomicMin(&a.failidx[w.x], f);
-            __syncthreads();
-        } else {
-            wave_forward<BP, false>(a, sd, w.y, L);
-            __syncthreads();
+            if (MODE != M_FACTOR) {
+                wave_backward<BP, MODE == M_ADJOINT, false>(a, sd, 1, L);
+                if (info != 0) nan_fill<NT>(a, sd, 0, sd.N, true);
+            }
         }
+        __syncthreads();
     }
 }
 

@@ -102,13 +102,17 @@ def test_race_line_system_full_size(p):
     _check(plan, x, [s], [0])
 
 
-@pytest.mark.skip(reason="block sizes above 32 are switched off: the 48-wide class faulted the GPU "
-                         "(memory aperture violation) with no cause shown yet")
 @pytest.mark.parametrize("p", [1, 4, 8, 16, 32])
 def test_chain_system_full_size(p):
+    """N 128, b 42, ng 0 (the 48-wide group); Eq. 13 splits p = 4 / 8 / 16 / 32 into
+    (59, 22), (30, 13), (8, 7), (4, 3)."""
     s = workloads.single("chain")
+    assert (s.N, s.b, s.ng) == (128, 42, 0)
+    _say("gpu case: chain system p=%d" % p)
     plan, pools, ws, x, info = _solve([s], [p], 1)
     assert info.tolist() == [0]
+    lay = plan.layouts[0]
+    assert (lay.N1, lay.Nk) == {1: (128, 0), 4: (59, 22), 8: (30, 13), 16: (8, 7), 32: (4, 3)}[p]
     _check(plan, x, [s], [0])
 
 

@@ -87,9 +87,6 @@ def check_solution(plan, x, systems):
         assert rel < 1e-10 and res < 1e-10, ("solution", s, (sysm.N, sysm.b, sysm.ng), seg, rel, res)
 
 
-LARGE_B_OFF = ("block sizes above 32 are switched off: the 48-wide class faulted the GPU "
-               "(memory aperture violation) with no cause shown yet")
-
 SINGLE_CASES = [
     # (N, b, ng, p, nrhs)
     (16, 4, 2, 1, 1),
@@ -109,8 +106,11 @@ SINGLE_CASES = [
     (8, 24, 4, 3, 1),
     (7, 32, 4, 1, 1),
     (9, 32, 2, 3, 1),
-    pytest.param(5, 42, 0, 2, 1, marks=pytest.mark.skip(reason=LARGE_B_OFF)),
-    pytest.param(7, 48, 1, 3, 1, marks=pytest.mark.skip(reason=LARGE_B_OFF)),
+    # the 48-wide group (three-wave row-lane sweeps): whole and segmented, every mode
+    (5, 42, 0, 2, 1),
+    (7, 48, 1, 3, 1),
+    (6, 33, 16, 1, 8),
+    (11, 45, 5, 3, 3),
     (40, 6, 8, 4, 4),
     # the maxima: block size 32, 16 arrow rows, 8 rhs (whole and segmented, dense path)
     (6, 32, 16, 1, 8),
@@ -141,9 +141,9 @@ def test_factor_then_solve_matches(p):
 def test_factor_then_solve_every_group_segmented():
     """The solve-only mode of segmented systems of every block group (row-lane
     sweeps for all three phases), beside whole systems of the dense groups."""
-    dims = [(17, 7, 2), (19, 14, 3), (16, 22, 1), (15, 30, 4), (9, 16, 2), (8, 32, 0)]
+    dims = [(17, 7, 2), (19, 14, 3), (16, 22, 1), (15, 30, 4), (9, 16, 2), (8, 32, 0), (13, 40, 3), (6, 47, 0)]
     systems = gen(78, dims, nrhs=3)
-    ps = [3, 4, 2, 3, 1, 1]
+    ps = [3, 4, 2, 3, 1, 1, 3, 1]
     plan, pools, ws, x, info = run(systems, ps, 3, mode="separate")
     assert (info == 0).all()
     check_factor(plan, ws, systems)
@@ -251,7 +251,8 @@ ADJ_CASES = {
     # the maxima: block size 32, 16 arrow rows, 8 rhs
     "maxima": ([(9, 8, 16), (6, 32, 16), (7, 16, 16)], 8, None),
     # segmented systems of every block group (their adjoint runs on the row-lane sweeps)
-    "segmented": ([(12, 12, 3), (14, 20, 2), (13, 28, 4), (11, 5, 1), (15, 32, 16)], 3, [3, 2, 3, 4, 2]),
+    "segmented": ([(12, 12, 3), (14, 20, 2), (13, 28, 4), (11, 5, 1), (15, 32, 16), (9, 44, 2), (7, 36, 4)], 3,
+                  [3, 2, 3, 4, 2, 3, 1]),
 }
 
 
