@@ -184,6 +184,21 @@ int kkt_factor_solve(const kkt_plan *plan, const double *D, const double *C, con
                      const double *corner, void *workspace, double *rhs, int32_t *info,
                      hipStream_t stream);
 
+/* kkt_factor_solve without a caller workspace and without any allocation, for
+ * callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, hosts that forbid hipMalloc).  The workspace is a device array
+ * inside the library, KKT_NOALLOC_MAX_BYTES bytes on each device it runs on,
+ * held until the process ends; plans whose workspace_bytes exceed it get
+ * KKT_EWORKSPACE.  The plan's tables are copied into the array (enqueued on
+ * stream) whenever it last served another plan.  Every class runs on the
+ * caller's stream (no side streams).  All calls on one device share the array:
+ * calls that overlap in time on one device race, so the caller orders them
+ * (one stream, or events); the factor left in the array is not usable by
+ * kkt_solve.  Arguments and results as kkt_factor_solve. */
+#define KKT_NOALLOC_MAX_BYTES (32ll << 20)
+int kkt_factor_solve_noalloc(const kkt_plan *plan, const double *D, const double *C, const double *B,
+                             const double *corner, double *rhs, int32_t *info, hipStream_t stream);
+
 /* Adjoint of x = Psi^{-1} r for a loss L(x) (Psi is symmetric, Eq. 3): given x and
  * gx = dL/dx (rhs pool layout, all nrhs columns), overwrite gx with
  * lambda = Psi^{-1} gx = dL/dr and write the gradients restricted to the block

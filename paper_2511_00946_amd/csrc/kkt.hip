@@ -33,6 +33,7 @@
 #include <vector>
 
 #include "kkt.h"
+
 #include "kkt_device.h"
 #include "kkt_internal.h"
 #include "kkt_wave.h"
@@ -498,6 +499,7 @@ struct kkt_plan {
     // caller's stream has a queue of its own.
     struct Dev {
         int dev = -1;
+        bool needs_streams = false;   // several active classes; side streams made when fork is set
         hipStream_t side[NSIDE] = {};
         hipEvent_t fork = nullptr, join[NSIDE] = {};
         int grid[MAXC][4][3] = {};
@@ -591,9 +593,14 @@ int work_of(const kkt_plan::Cls &c, int list) { return list == 0 ? c.item_cnt : 
 // The launch state of the current device: side streams and events, dynamic LDS
 // limits and the grid of every launch (as many workgroups as fit on the device
 // at once, at most one per work entry).  Called with the plan's lock held.
-int ensure_device(const kkt_plan *plan, int dev)
+int ensure_device(const kkt_plan *plan, int dev, bool streams = true)
 {
-    if (plan->dev_state(dev)) return KKT_OK;
+    if (const kkt_plan::Dev *have = plan->dev_state(dev)) {
+        if (!streams || have->fork || !have->needs_streams) return KKT_OK;
+        // made without side streams (by the no-allocation entry point): rebuild it with them
+        for (size_t i = 0; i < plan->devs.size(); ++i)
+            if (plan->devs[i].dev == dev) { plan->devs.erase(plan->devs.begin() + i); break; }
+    }
     kkt_plan::Dev d;
     d.dev = dev;
     int ncu = 0;
@@ -602,7 +609,8 @@ int ensure_device(const kkt_plan *plan, int dev)
     int nact = 0;
     for (const kkt_plan::Cls &c : plan->cls) nact += c.item_cnt > 0;
     bool ok = true;
-    if (nact > 1) {
+    d.needs_streams = nact > 1;
+    if (nact > 1 && streams) {
         ok = hipEventCreateWithFlags(&d.fork, hipEventDisableTiming) == hipSuccess;
         for (int j = 0; ok && j < kkt_plan::NSIDE && j < nact; ++j) {
             ok = hipStreamCreateWithFlags(&d.side[j], hipStreamNonBlocking) == hipSuccess &&
@@ -641,6 +649,31 @@ int ensure_device(const kkt_plan *plan, int dev)
     return KKT_OK;
 }
 
+// ------------------------------------------------------------------ no-allocation entry point
+// Device memory of the no-allocation entry point: one array per device, held
+// until the process ends.  In host code `scratch` names a host-side stand-in; the
+// device address comes from hipGetSymbolAddress, once per device, and only that
+// address is ever passed to kernels or copies.
+constexpr size_t NOALLOC_BYTES = (size_t)KKT_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAXDEV = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[NOALLOC_MAXDEV] = {};
+long long g_noalloc_owner[NOALLOC_MAXDEV] = {};   // tag of the plan whose tables the array holds
+
+// The array's device address on device dev (the current device); null on failure.
+void *noalloc_scratch(int dev)
+{
+    if (dev < 0 || dev >= NOALLOC_MAXDEV) return nullptr;
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_noalloc_ptr[dev] = ptr;
+    }
+    return g_noalloc_ptr[dev];
+}
+
 Args base_args(const kkt_plan *plan, void *workspace)
 {
     char *ws = (char *)workspace;
@@ -662,6 +695,9 @@ Args base_args(const kkt_plan *plan, void *workspace)
 // Enqueue one call: the reset kernel, then every class's launches (classes on
 // forked streams when there are several).  On an error after the fork, the side
 // streams used so far are still joined back into the caller's stream.
+int launch_locked(const kkt_plan *plan, const kkt_plan::Dev *d, int mode, const Args &base, const void *ws,
+                  hipStream_t stream, int *info, bool allow_fork);
+
 int launch_mode(const kkt_plan *plan, int mode, const Args &base, const void *ws, hipStream_t stream, int *info,
                 bool need_factor)
 {
@@ -674,6 +710,13 @@ int launch_mode(const kkt_plan *plan, int mode, const Args &base, const void *ws
     if (need_factor && plan->factored.count(ws) == 0) return KKT_ENOTFACTORED;
     const kkt_plan::Dev *d = plan->dev_state(dev);
     if (!d) return KKT_EWORKSPACE;
+    return launch_locked(plan, d, mode, base, ws, stream, info, true);
+}
+
+// Enqueue one call with the plan's lock held and its launch state d of the current device.
+int launch_locked(const kkt_plan *plan, const kkt_plan::Dev *d, int mode, const Args &base, const void *ws,
+                  hipStream_t stream, int *info, bool allow_fork)
+{
     const bool fact = mode == M_FACTOR || mode == M_FACTOR_SOLVE;
     const char *w = (const char *)ws;
     hipLaunchKernelGGL(kkt_reset, dim3(std::max(1, std::min(1024, (plan->S + 255) / 256))), dim3(256), 0, stream,
@@ -682,7 +725,7 @@ int launch_mode(const kkt_plan *plan, int mode, const Args &base, const void *ws
     if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
     int nact = 0;
     for (const kkt_plan::Cls &c : plan->cls) nact += c.item_cnt > 0;
-    const bool fork = nact > 1;
+    const bool fork = allow_fork && nact > 1 && d->fork;
     if (fork && hipEventRecord(d->fork, stream) != hipSuccess) return KKT_ELAUNCH;
     int rc = KKT_OK, nside = 0;
     for (size_t ci = 0; ci < plan->cls.size() && rc == KKT_OK; ++ci) {
@@ -957,6 +1000,41 @@ int kkt_factor_solve(const kkt_plan *plan, const double *D, const double *C, con
         plan->factored.insert(workspace);
     }
     return rc;
+}
+
+int kkt_factor_solve_noalloc(const kkt_plan *plan, const double *D, const double *C, const double *B,
+                             const double *corner, double *rhs, int32_t *info, hipStream_t stream)
+{
+    if (!plan || !D || !info || !rhs) return KKT_EPOINTER;
+    if (plan->info.C_len && !C) return KKT_EPOINTER;
+    if (plan->info.B_len && (!B || !corner)) return KKT_EPOINTER;
+    if (!aligned8(D) || !aligned8(C) || !aligned8(B) || !aligned8(corner) || !aligned8(rhs)) return KKT_EPOINTER;
+    if (plan->bytes > NOALLOC_BYTES) return KKT_EWORKSPACE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return KKT_ELAUNCH;
+    std::lock_guard<std::mutex> nguard(g_noalloc_mu);
+    void *ws = noalloc_scratch(dev);
+    if (!ws) return KKT_ELAUNCH;
+    std::lock_guard<std::mutex> guard(plan->mu);
+    int rc = ensure_device(plan, dev, false);
+    if (rc != KKT_OK) return rc;
+    if (g_noalloc_owner[dev] != plan->tag) {
+        // the array last held another plan's tables (or none): copy this plan's in
+        char *w = (char *)ws;
+        const long long tag[3] = {plan->tag, (long long)plan->bytes, 0};
+        auto put = [&](size_t off, const void *src, size_t n) {
+            return n == 0 || hipMemcpyAsync(w + off, src, n, hipMemcpyHostToDevice, stream) == hipSuccess;
+        };
+        if (!put(plan->o_sys, plan->sys.data(), sizeof(SysDesc) * plan->S) ||
+            !put(plan->o_items, plan->items.data(), sizeof(int2) * plan->items.size()) ||
+            !put(plan->o_red, plan->red.data(), sizeof(int) * plan->red.size()) ||
+            !put(plan->o_s3, plan->s3.data(), sizeof(int2) * plan->s3.size()) || !put(plan->o_tag, tag, sizeof(tag)))
+            return KKT_ELAUNCH;
+        g_noalloc_owner[dev] = plan->tag;
+    }
+    Args a = base_args(plan, ws);
+    a.D = D; a.C = C; a.B = B; a.corner = corner; a.info = info; a.rhs = rhs;
+    return launch_locked(plan, plan->dev_state(dev), M_FACTOR_SOLVE, a, ws, stream, info, false);
 }
 
 int kkt_solve(const kkt_plan *plan, void *workspace, double *rhs, hipStream_t stream)

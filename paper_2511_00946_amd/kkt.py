@@ -13,6 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkkt.so")
 
 KKT_OK = 0
+KKT_EDIMS, KKT_EPOINTER, KKT_EWORKSPACE, KKT_ELAUNCH, KKT_ENOTFACTORED = -1, -2, -3, -4, -5
 MAX_B, MAX_NG, MAX_NRHS = 48, 16, 8
 NUM_CLASSES = 5
 CLASS_BLOCKS = (8, 16, 24, 32, 48)
@@ -89,6 +90,7 @@ def lib():
         L.kkt_factor.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.kkt_solve.argtypes = [vp, vp, vp, vp]
         L.kkt_factor_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.kkt_factor_solve_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.kkt_solve_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.kkt_plan_class_info.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                           ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32)]
@@ -99,7 +101,7 @@ def lib():
         L.kkt_status_string.argtypes = [ctypes.c_int]
         for name in ("kkt_plan_create", "kkt_plan_create_tuned", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
                      "kkt_workspace_init", "kkt_factor", "kkt_solve", "kkt_factor_solve", "kkt_solve_adjoint",
-                     "kkt_plan_class_info", "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error"):
+                     "kkt_factor_solve_noalloc", "kkt_plan_class_info", "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -108,7 +110,10 @@ def lib():
 EXPORTED = ("kkt_plan_create", "kkt_plan_create_tuned", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
             "kkt_plan_factor_offset", "kkt_workspace_init", "kkt_factor", "kkt_solve",
             "kkt_factor_solve", "kkt_solve_adjoint", "kkt_status_string", "kkt_plan_class_info",
-            "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error")
+            "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error", "kkt_factor_solve_noalloc")
+
+# bytes of the no-allocation entry point's device array (plans above it are refused)
+NOALLOC_MAX_BYTES = 32 << 20
 
 
 def _check(rc, what):
@@ -217,6 +222,14 @@ class Plan:
         self._check_ws(ws)
         _check(lib().kkt_factor_solve(self._h, _ptr(D), _ptr(C), _ptr(B), _ptr(corner), _ptr(ws), _ptr(rhs),
                                       _ptr(info), _stream(stream)), "kkt_factor_solve")
+
+    def factor_solve_noalloc(self, D, C, B, corner, rhs, info, stream=None):
+        """factor_solve with the library's own device array as the workspace: no
+        allocation; calls that overlap on one device race."""
+        for t, n in ((D, "D"), (C, "C"), (B, "B"), (corner, "corner"), (rhs, "rhs")):
+            self._check_pool(t, n)
+        _check(lib().kkt_factor_solve_noalloc(self._h, _ptr(D), _ptr(C), _ptr(B), _ptr(corner), _ptr(rhs),
+                                              _ptr(info), _stream(stream)), "kkt_factor_solve_noalloc")
 
     def solve(self, ws, rhs, stream=None):
         self._check_pool(rhs, "rhs")

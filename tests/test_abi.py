@@ -262,3 +262,22 @@ def test_plan_flop_counts_are_the_standard_counts_of_the_algorithm():
         sv = nr * sum(flops.std_cost(op, m, n, k) for _, op, m, n, k in flops.solve_ops(seg, b, ng))
         assert plan.info.factor_flops == pytest.approx(float(f), rel=1e-12), (N, b, ng, p)
         assert plan.info.solve_flops == pytest.approx(float(sv), rel=1e-12), (N, b, ng, p)
+
+
+def test_noalloc_limit_and_host_side_refusals():
+    """The no-allocation entry point: the binding's limit is the header's, and a
+    plan above it or a null pointer is refused before any device work."""
+    kkt = _kkt()
+    hdr = open(os.path.join(ROOT, "include", "kkt.h")).read()
+    m = re.search(r"#define KKT_NOALLOC_MAX_BYTES \((\d+)ll << (\d+)\)", hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == kkt.NOALLOC_MAX_BYTES
+    L = kkt.lib()
+    big = kkt.Plan([(256, 32, 4, 1)] * 200)
+    assert big.info.workspace_bytes > kkt.NOALLOC_MAX_BYTES
+    fake = ctypes.c_void_p(1 << 20)      # never dereferenced: the call returns first
+    rc = L.kkt_factor_solve_noalloc(big._h, fake, fake, fake, fake, fake, fake, None)
+    assert rc == kkt.KKT_EWORKSPACE
+    small = kkt.Plan([(12, 8, 2, 1)])
+    assert L.kkt_factor_solve_noalloc(small._h, None, fake, fake, fake, fake, fake, None) == kkt.KKT_EPOINTER
+    assert L.kkt_factor_solve_noalloc(small._h, fake, fake, fake, fake, None, fake, None) == kkt.KKT_EPOINTER
+    assert L.kkt_factor_solve_noalloc(None, fake, fake, fake, fake, fake, fake, None) == kkt.KKT_EPOINTER
