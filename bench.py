@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 30
 SRC_FILES = ("paper_2511_00946_amd/csrc/kkt.hip", "paper_2511_00946_amd/csrc/kkt_wave.h",
+             "paper_2511_00946_amd/csrc/kkt_lane.h", "paper_2511_00946_amd/csrc/kkt_kernels.h",
              "paper_2511_00946_amd/csrc/kkt_wave_inst.hip", "paper_2511_00946_amd/csrc/kkt_internal.h",
              "paper_2511_00946_amd/csrc/kkt_dense.h", "paper_2511_00946_amd/csrc/kkt_device.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ragged4096.json")
@@ -60,18 +61,29 @@ class HipEvents:
         return float(ms.value)
 
 
+def oracle_core_seconds(okkt, systems):
+    """Seconds the oracle's C core spends on factor + solve of each system (steady
+    clock around the factor and solve calls only; the assembly of the block matrix
+    through the Python wrapper is left out)."""
+    tot = 0.0
+    for sy in systems:
+        f = okkt.KKTFactor(sy.D, sy.C, sy.B, sy.corner, factor=False)
+        t = time.perf_counter()
+        f.factor()
+        f.solve(sy.r)
+        tot += time.perf_counter() - t
+    return tot
+
+
 def _oracle_worker(job):
     """One worker of the all-cores oracle baseline (its own process): the oracle's
-    factor + solve over the systems idx of the ragged batch of S systems, timed."""
+    C core on the systems idx of the ragged batch of S systems, timed."""
     S, idx = job
     from oracle import kkt as okkt
     from paper_2511_00946_amd import workloads
     spec = workloads.ragged_batch_spec(S=S)
     systems = [spec.system(i) for i in idx]
-    t = time.perf_counter()
-    for sy in systems:
-        okkt.solve(sy.D, sy.C, sy.B, sy.corner, sy.r)
-    return time.perf_counter() - t
+    return oracle_core_seconds(okkt, systems)
 
 
 def oracle_all_cores(S, csamp, max_workers=16):
@@ -97,9 +109,11 @@ def build_pools(spec, idx=None):
     return systems, workloads.pack(systems)
 
 
-def alg_bytes(plan, systems):
-    """Algorithmic HBM bytes of one fused factor + solve per system: read Psi once,
-    write hat L once, read hat L once in the backward sweep, read r, write x."""
+def alg_bytes(plan, systems, adjoint=False):
+    """Algorithmic HBM bytes per system of one fused factor + solve: read Psi once,
+    write hat L once, read hat L once in the backward sweep, read r, write x.  With
+    adjoint, plus one adjoint solve: read hat L, x and the incoming gradient, write
+    lambda and the four gradient pools (the pattern of Psi)."""
     out = []
     for s, sy in enumerate(systems):
         lay = plan.layouts[s]
@@ -107,7 +121,8 @@ def alg_bytes(plan, systems):
         K = N * b * b + (N - 1) * b * b + N * ng * b + ng * ng
         fill = (p - 1) * (nk - 1) * b * b + max(p - 2, 0) * b * b if p > 1 else 0
         L = K + fill
-        out.append(8.0 * (K + 2 * L + 2 * sy.n * plan.nrhs))
+        n = sy.n * plan.nrhs
+        out.append(8.0 * (K + 2 * L + 2 * n + ((L + K + 3 * n) if adjoint else 0)))
     return np.asarray(out)
 
 
@@ -137,7 +152,7 @@ def measured_traffic(bp, p, S):
 
 
 KIND_ROWLANE, KIND_DENSE, KIND_DSEG = 0, 1, 2
-DENSE_GROUPS = (16, 24, 32)
+DENSE_GROUPS = (24, 32)
 
 
 def in_class(bp, kind, b, p):
@@ -195,7 +210,7 @@ def fd_check(torch, kkt, workloads, dsys, dplan, dev, grads, systems=(0, 511, 10
     return worst
 
 
-SINGLE_P = {"small": (1, 2, 4, 8), "race": (1, 2, 4, 8, 16, 32, 64, 128)}
+SINGLE_P = {"small": (1, 2, 4, 8), "race": (1, 2, 4, 8, 16, 32, 64, 128), "chain": (1, 4, 8, 16, 32)}
 
 
 def single_systems(torch, kkt, workloads, okkt, dev, cost_model=None, reps=50):
@@ -243,7 +258,6 @@ def single_systems(torch, kkt, workloads, okkt, dev, cost_model=None, reps=50):
                      "cost_model_p": auto,
                      "cost_model_segments": [tuned.layouts[0].N1, tuned.layouts[0].Nk]}
         log("single %s: %s" % (name, {p: round(v, 1) for p, v in res.items()}))
-    out["chain"] = "not run: block size 42 is above the supported maximum of 32"
     return out
 
 
@@ -409,7 +423,7 @@ def main():
     dom = int(np.argmax(cls_ms))
     dom_bp, dom_kind = classes[dom][0], kinds[dom]
     dom_dense = dom_kind == KIND_DENSE
-    dom_db = 16 if dom_bp <= 16 else 32
+    dom_db = 32
     dom_bytes = float(sum(bytes_sys[s] for s, sy in enumerate(systems)
                           if in_class(dom_bp, dom_kind, sy.b, plan.layouts[s].p)))
     achieved = dom_bytes / (cls_ms[dom] * 1e-3) / 1e9
@@ -419,7 +433,7 @@ def main():
                 "kernel": {KIND_DENSE: "kkt_dense<%d, factor_solve> + kkt_dense_bwd<%d>" % (dom_db, dom_db),
                            KIND_DSEG: "kkt_dense_seg<%d> + kkt_wave_p2<%d> + kkt_dense_seg_bwd<%d>"
                                       % (dom_db, dom_bp, dom_db)}.get(
-                               dom_kind, "kkt_wave_p1/p2/p3<%d, factor_solve>" % dom_bp),
+                               dom_kind, "kkt_wave_p1/p2/p3<%d, factor_solve, 1>" % dom_bp),
                 "kernel_ms": round(float(cls_ms[dom]), 4), "alg_bytes": dom_bytes}
 
     # plain single-system path: one call (one launch) per system, on a sample
@@ -451,15 +465,17 @@ def main():
         log("plain path: %d systems in %.2f ms -> %.0f systems/s" % (len(samp), plain_ms, plain_sps))
     del plain
 
-    # oracle on the host (bounded sample)
+    # oracle on the host (bounded sample): its C core alone, and the whole Python call
     csamp = np.random.default_rng(2).choice(S, size=min(args.cpu_sample, S), replace=False)
-    t1 = time.perf_counter()
-    for s in csamp:
-        sy = systems[s]
-        okkt.solve(sy.D, sy.C, sy.B, sy.corner, sy.r)
-    cpu_s = time.perf_counter() - t1
+    csys = [systems[s] for s in csamp]
+    cpu_s = oracle_core_seconds(okkt, csys)
     cpu_sps = len(csamp) / cpu_s if len(csamp) else None
-    log("oracle: %d systems in %.1fs -> %s systems/s" % (len(csamp), cpu_s, cpu_sps))
+    t1 = time.perf_counter()
+    for sy in csys[:256]:
+        okkt.solve(sy.D, sy.C, sy.B, sy.corner, sy.r)
+    wrapped_sps = min(256, len(csys)) / (time.perf_counter() - t1) if len(csys) else None
+    log("oracle C core: %d systems in %.1fs -> %s systems/s (with the Python wrapper %s)"
+        % (len(csamp), cpu_s, cpu_sps, wrapped_sps))
     cpu_all = None
     if len(csamp) and not args.skip_oracle_all_cores:
         sps_all, nw = oracle_all_cores(S, csamp)
@@ -516,9 +532,15 @@ def main():
             gerr = max(gerr, float(np.max(np.abs(gl - ref[0])) / np.max(np.abs(ref[0]))))
         fd_err = fd_check(torch, kkt, workloads, dsys, dplan, dev,
                           {"D": gD.cpu().numpy(), "C": gC.cpu().numpy(), "B": gB.cpu().numpy(), "r": lam_h})
+        dbytes = float(np.sum(alg_bytes(dplan, dsys, adjoint=True)))
+        dach = dbytes / (dms * 1e-3) / 1e9
         diff = {"workload": "1024 x (N=64, b=24, ng=4)", "fwd_bwd_systems_per_s": round(len(dsys) / (dms * 1e-3), 1),
                 "ms_per_step": round(dms, 4), "grad_max_rel_err_vs_oracle": gerr,
-                "grad_max_rel_err_vs_central_fd_h1e-6": fd_err}
+                "grad_max_rel_err_vs_central_fd_h1e-6": fd_err,
+                "roofline": {"bound": "hbm", "achieved": round(dach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(dach / HBM_PEAK_GBS, 5), "traffic": None,
+                             "kernel": "whole step (factor + solve, adjoint solve: every launch)",
+                             "alg_bytes": dbytes}}
         assert fd_err <= 1e-6, "finite-difference gradient check failed: %.3e" % fd_err
         log("diff workload: %.3f ms per fwd+bwd -> %.0f systems/s, grad err %.2e" % (dms, len(dsys) / (dms * 1e-3), gerr))
 
@@ -555,7 +577,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": {"value": None if cpu_sps is None else round(cpu_sps, 2), "unit": "systems/s", "cores": 1,
                          "kind": "oracle",
-                         "sample": "%d random systems of the batch, factor + solve each" % len(csamp)},
+                         "sample": "%d random systems of the batch, factor + solve each, the oracle's C core "
+                                   "timed with a steady clock (block assembly in Python left out)" % len(csamp)},
+        "cpu_baseline_python_wrapped": None if wrapped_sps is None else round(wrapped_sps, 2),
         "cpu_baseline_all_cores": cpu_all,
         "fp64": {"achieved_tflops": round(step_flops / (ms_per_step * 1e-3) / 1e12, 4), "peak_tflops": 78.6,
                  "frac": round(step_flops / (ms_per_step * 1e-3) / 1e12 / 78.6, 5),

@@ -69,7 +69,7 @@ def _dims(D, B):
 class KKTFactor:
     """hat L = chol(P Psi P^T) for the order given by ``seg_lens`` (default: p = 1)."""
 
-    def __init__(self, D, C, B, corner, seg_lens=None):
+    def __init__(self, D, C, B, corner, seg_lens=None, factor=True):
         D = np.asarray(D, dtype=np.float64)
         C = np.asarray(C, dtype=np.float64).reshape(-1, D.shape[1], D.shape[1])
         N, b, ng = _dims(D, B)
@@ -96,15 +96,22 @@ class KKTFactor:
             for s in range(N):
                 M.set(N, self.pos[s], B[s])
             M.set(N, N, sym(np.asarray(corner, dtype=np.float64)))
-        rc = M.cholesky()
+        self._M = M
+        self.info = None
+        if factor:
+            self.factor()
+
+    def factor(self):
+        """Block Cholesky of the assembled P Psi P^T (in place); sets ``info``.
+        Separate from the assembly so that a caller can time the C core alone."""
+        rc = self._M.cholesky()
         if rc < 0:
             raise RuntimeError("oracle block Cholesky failed on its input")
         if rc == 0:
             self.info = 0
         else:
             col = rc - 1
-            self.info = self.order[col] + 1 if col < N else N + 1
-        self._M = M
+            self.info = self.order[col] + 1 if col < self.N else self.N + 1
 
     def block(self, row, col):
         """hat L block at (row stage, col stage), natural labels (ints or 'g').

@@ -25,7 +25,10 @@ HIPCC_FLAGS = [
 def _units():
     units = [("kkt", os.path.join(CSRC, "kkt.hip"), [])]
     for bp in WAVE_CLASSES:
-        units.append(("kkt_wave%d" % bp, os.path.join(CSRC, "kkt_wave_inst.hip"), ["-DKKT_WAVE_BP=%d" % bp]))
+        # single-wave classes: one instance per right-hand-side count
+        for nr in ((1, 4, 8) if bp <= 16 else (8,)):
+            units.append(("kkt_wave%d_%d" % (bp, nr), os.path.join(CSRC, "kkt_wave_inst.hip"),
+                          ["-DKKT_WAVE_BP=%d" % bp, "-DKKT_WAVE_NR=%d" % nr]))
     return units
 
 

@@ -43,14 +43,17 @@ using namespace kkt_dev;
 
 namespace kkt_dev {
 
-kfun_t wave_kernel(int bp, int mode, int phase)
+kfun_t wave_kernel(int bp, int mode, int phase, int nr)
 {
+    // the single-wave classes have instances for 1, 4 and 8 right-hand sides
+    const int c = nr <= 1 ? 1 : (nr <= 4 ? 4 : 8);
     switch (bp) {
-    case 8: return wave_kernel_8(mode, phase);
-    case 16: return wave_kernel_16(mode, phase);
-    case 24: return wave_kernel_24(mode, phase);
-    case 32: return wave_kernel_32(mode, phase);
-    default: return wave_kernel_48(mode, phase);
+    case 8: return c == 1 ? wave_kernel_8_1(mode, phase) : (c == 4 ? wave_kernel_8_4(mode, phase) : wave_kernel_8_8(mode, phase));
+    case 16:
+        return c == 1 ? wave_kernel_16_1(mode, phase) : (c == 4 ? wave_kernel_16_4(mode, phase) : wave_kernel_16_8(mode, phase));
+    case 24: return wave_kernel_24_8(mode, phase);
+    case 32: return wave_kernel_32_8(mode, phase);
+    default: return wave_kernel_48_8(mode, phase);
     }
 }
 
@@ -206,8 +209,10 @@ int class_of(int b)
     return -1;
 }
 
-int dense_width(int bp) { return bp <= 16 ? 16 : 32; }
-bool dense_capable(int bp) { return bp >= 16 && bp <= 32; }
+// Padded sizes 24 and 32 run the dense single-wave sweeps on 32-wide tiles; 8 and
+// 16 the single-wave row-lane sweeps (measured faster for 16), 48 the multi-wave
+// row-lane sweeps.
+bool dense_capable(int bp) { return bp == 24 || bp == 32; }
 
 template <int DB>
 kfun_t dense_for(int mode)
@@ -558,32 +563,24 @@ int launches_of(const kkt_plan::Cls &c, int mode, int nr, Launch *out)
     const bool fact = mode == M_FACTOR || mode == M_FACTOR_SOLVE, fwd = mode == M_FACTOR_SOLVE;
     int n = 0;
     if (c.kind == kkt_plan::K_DENSE) {
-        const int db = dense_width(c.bp);
-        const size_t lds = (size_t)lds_offsets_dense(db, nr).total * sizeof(double);
-        out[n++] = {db == 16 ? dense_for<16>(mode) : dense_for<32>(mode), 64, lds, 0};
-        if (mode != M_FACTOR) {
-            kfun_t f = mode == M_ADJOINT ? (db == 16 ? kkt_dense_bwd<16, true> : kkt_dense_bwd<32, true>)
-                                         : (db == 16 ? kkt_dense_bwd<16, false> : kkt_dense_bwd<32, false>);
-            out[n++] = {f, 64, lds, 0};
-        }
+        const size_t lds = (size_t)lds_offsets_dense(32, nr).total * sizeof(double);
+        out[n++] = {dense_for<32>(mode), 64, lds, 0};
+        if (mode != M_FACTOR) out[n++] = {mode == M_ADJOINT ? kkt_dense_bwd<32, true> : kkt_dense_bwd<32, false>, 64, lds, 0};
         return n;
     }
     const int wnt = wave_threads(c.bp);
     const size_t wl = wave_lds_bytes(c.bp);
     if (c.kind == kkt_plan::K_DSEG && fact) {
-        const int db = dense_width(c.bp);
-        const size_t lds = (size_t)lds_offsets_dense(db, nr, true).total * sizeof(double);
-        kfun_t f1 = db == 16 ? (fwd ? kkt_dense_seg<16, true> : kkt_dense_seg<16, false>)
-                             : (fwd ? kkt_dense_seg<32, true> : kkt_dense_seg<32, false>);
-        out[n++] = {f1, 64, lds, 0};
-        out[n++] = {wave_kernel(c.bp, mode, 1), wnt, wl, 1};
-        if (fwd) out[n++] = {db == 16 ? kkt_dense_seg_bwd<16> : kkt_dense_seg_bwd<32>, 64, lds, 2};
+        const size_t lds = (size_t)lds_offsets_dense(32, nr, true).total * sizeof(double);
+        out[n++] = {fwd ? kkt_dense_seg<32, true> : kkt_dense_seg<32, false>, 64, lds, 0};
+        out[n++] = {wave_kernel(c.bp, mode, 1, nr), wnt, wl, 1};
+        if (fwd) out[n++] = {kkt_dense_seg_bwd<32>, 64, lds, 2};
         return n;
     }
-    out[n++] = {wave_kernel(c.bp, mode, 0), wnt, wl, 0};
+    out[n++] = {wave_kernel(c.bp, mode, 0, nr), wnt, wl, 0};
     if (c.red_cnt > 0) {
-        out[n++] = {wave_kernel(c.bp, mode, 1), wnt, wl, 1};
-        if (mode != M_FACTOR) out[n++] = {wave_kernel(c.bp, mode, 2), wnt, wl, 2};
+        out[n++] = {wave_kernel(c.bp, mode, 1, nr), wnt, wl, 1};
+        if (mode != M_FACTOR) out[n++] = {wave_kernel(c.bp, mode, 2, nr), wnt, wl, 2};
     }
     return n;
 }

@@ -23,16 +23,9 @@
 
 namespace kkt_dev {
 
-typedef double dx4 __attribute__((ext_vector_type(4)));
-
 // Phase boundary: the scheduler may not move instructions across it, so the live
 // ranges of consecutive phases of a stage do not overlap.
 __device__ __forceinline__ void phase_fence() { __builtin_amdgcn_sched_barrier(0); }
-
-__device__ __forceinline__ dx4 mfma4(double a, double b, dx4 c)
-{
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
 
 // Four independent 4x4x4 FP64 products per instruction (lane layout probed on
 // gfx950: with lane l = x + 4 blk + 16 y, A[blk][x][y], B[blk][y][x] and

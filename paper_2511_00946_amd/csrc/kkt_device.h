@@ -90,6 +90,16 @@ __device__ __forceinline__ int seg_first(const SysDesc &s, int k) { return k == 
 __device__ __forceinline__ int seg_len(const SysDesc &s, int k) { return k == 1 ? s.N1 : s.Nk; }
 __device__ __forceinline__ int sep_of(const SysDesc &s, int k) { return s.N1 + (k - 2) * (s.Nk + 1); }  // k >= 2
 
+// FP64 matrix-core product D = A B + C on 16 x 16 x 4 tiles (v_mfma_f64_16x16x4f64):
+// A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, D[4 v + lane / 16][lane % 16]
+// in element v of lane `lane`.
+typedef double dx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ dx4 mfma4(double a, double b, dx4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 __device__ __forceinline__ double readlane_d(double v, int lane)
 {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);

@@ -1347,139 +1347,4 @@ __device__ __forceinline__ void nan_fill(const Args &a, const SysDesc &sd, int s
         for (int e = threadIdx.x; e < sd.ng * nr; e += NT) X[(long long)sd.N * b * nr + e] = qnan;
 }
 
-// ---------------------------------------------------------------- kernels
-// Phase 1: every item of the class's first list.  A whole system (p = 1) runs
-// all phases: factor (+ forward) sweep, corner, backward sweep (Algorithms 1-3
-// with p = 1); a segment of a segmented system runs its parallel-phase factor
-// (+ forward) sweep (factor modes) or its forward sweep (solve modes).
-template <int BP, int MODE>
-__global__ void __launch_bounds__(WC<BP>::NT) kkt_wave_p1(Args a)
-{
-    using C = WC<BP>;
-    constexpr int NT = C::NT;
-    constexpr bool FACT = MODE == M_FACTOR || MODE == M_FACTOR_SOLVE, FWD = MODE == M_FACTOR_SOLVE;
-    extern __shared__ double lds_raw[];
-    const WaveLds L = make_wave_lds<BP>(lds_raw);
-    for (;;) {
-        const int it = next_work(a.ctr + 0, a.abort, L.misc);
-        if (it >= a.n_items) break;
-        const int2 w = a.items[it];
-        const SysDesc sd = a.sys[w.x];
-        const bool whole = sd.p == 1;
-        // one instance of each sweep serves whole systems (segment 1 of 1) and segments
-        int f = 0;
-        if (FACT) {
-            f = wave_factor<BP, FWD, false>(a, sd, whole ? 1 : w.y, L);
-            if (threadIdx.x == 0) {
-                if (!whole && f) atomicMin(&a.failidx[w.x], f);
-                L.misc[1] = f;
-            }
-        } else {
-            if (threadIdx.x == 0) L.misc[1] = load_status(&a.status[w.x]);
-            wave_forward<BP, false>(a, sd, whole ? 1 : w.y, L);
-        }
-        __syncthreads();
-        if (whole) {
-            int info = L.misc[1];
-            if (FACT) {
-                const bool cf = corner_factor_w<NT, FWD>(a, sd, L.nxt, L.nxt + NGM * (NGM + 1), nullptr, nullptr);
-                if (threadIdx.x == 0) {
-                    info = info ? info : (cf ? sd.N + 1 : 0);
-                    a.status[w.x] = info;
-                    if (a.info) a.info[w.x] = info;
-                    L.misc[1] = info;
-                }
-                __syncthreads();
-                info = L.misc[1];
-            } else {
-                corner_solve_w<NT>(a, sd, L.nxt, L.nxt + NGM * (NGM + 1), nullptr);
-                if (MODE == M_ADJOINT) corner_grad_w<NT>(a, sd);
-            }
-            __syncthreads();
-            if (MODE != M_FACTOR) {
-                wave_backward<BP, MODE == M_ADJOINT, false>(a, sd, 1, L);
-                if (info != 0) nan_fill<NT>(a, sd, 0, sd.N, true);
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// Phase 2 of a segmented system (after every segment's phase 1): the reduced
-// separator chain and the corner (Algorithm 1, 2 and 3 sequential phases).
-template <int BP, int MODE>
-__global__ void __launch_bounds__(WC<BP>::NT) kkt_wave_p2(Args a)
-{
-    using C = WC<BP>;
-    constexpr int NT = C::NT;
-    constexpr bool FACT = MODE == M_FACTOR || MODE == M_FACTOR_SOLVE, FWD = MODE == M_FACTOR_SOLVE;
-    extern __shared__ double lds_raw[];
-    const WaveLds L = make_wave_lds<BP>(lds_raw);
-    for (;;) {
-        const int it = next_work(a.ctr + 1, a.abort, L.misc);
-        if (it >= a.n_red) break;
-        const int s = a.red[it];
-        const SysDesc sd = a.sys[s];
-        int info;
-        if (FACT) {
-            const int rf = wave_factor<BP, FWD, true>(a, sd, 0, L);
-            __syncthreads();
-            const bool cf = corner_factor_w<NT, FWD>(a, sd, L.nxt, L.nxt + NGM * (NGM + 1), L.racc, L.yg);
-            if (threadIdx.x == 0) {
-                const int segf = load_status(&a.failidx[s]);
-                const int v = segf != INT_MAX ? segf : (rf ? rf : (cf ? sd.N + 1 : 0));
-                a.status[s] = v;
-                if (a.info) a.info[s] = v;
-                L.misc[1] = v;
-            }
-            __syncthreads();
-            info = L.misc[1];
-            if (FWD) wave_backward<BP, false, true>(a, sd, 0, L);
-        } else {
-            if (threadIdx.x == 0) L.misc[1] = load_status(&a.status[s]);
-            wave_forward<BP, true>(a, sd, 0, L);
-            __syncthreads();
-            info = L.misc[1];
-            corner_solve_w<NT>(a, sd, L.nxt, L.nxt + NGM * (NGM + 1), L.yg);
-            if (MODE == M_ADJOINT) corner_grad_w<NT>(a, sd);
-            __syncthreads();
-            wave_backward<BP, MODE == M_ADJOINT, true>(a, sd, 0, L);
-        }
-        if (MODE != M_FACTOR && info != 0) {
-            // NaN the separators and g (the segments do their own stages in phase 3)
-            for (int k = 2; k <= sd.p; ++k) {
-                const int sp = sep_of(sd, k);
-                nan_fill<NT>(a, sd, sp, sp + 1, false);
-            }
-            nan_fill<NT>(a, sd, 0, 0, true);
-        }
-        __syncthreads();
-    }
-}
-
-// Phase 3 of a segmented system (after its phase 2): the backward sweep of one
-// segment (Algorithm 3, parallel phase; with the adjoint, its gradients).
-template <int BP, int MODE>
-__global__ void __launch_bounds__(WC<BP>::NT) kkt_wave_p3(Args a)
-{
-    using C = WC<BP>;
-    constexpr int NT = C::NT;
-    extern __shared__ double lds_raw[];
-    const WaveLds L = make_wave_lds<BP>(lds_raw);
-    for (;;) {
-        const int it = next_work(a.ctr + 2, a.abort, L.misc);
-        if (it >= a.n_s3) break;
-        const int2 w = a.s3[it];
-        const SysDesc sd = a.sys[w.x];
-        wave_backward<BP, MODE == M_ADJOINT, false>(a, sd, w.y, L);
-        if (threadIdx.x == 0) L.misc[1] = load_status(&a.status[w.x]);
-        __syncthreads();
-        if (L.misc[1] != 0) {
-            const int f = seg_first(sd, w.y);
-            nan_fill<NT>(a, sd, f, f + seg_len(sd, w.y), false);
-        }
-        __syncthreads();
-    }
-}
-
 }  // namespace kkt_dev
