@@ -100,6 +100,28 @@ __device__ __forceinline__ dx4 mfma4(double a, double b, dx4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Range-checked access through a buffer resource (raw, no stride): an element
+// whose byte offset lies past the resource's byte count reads as zero and a store
+// there is dropped; the hardware checks every access.  Dword 3 holds the 32-bit
+// data format the gfx9 family expects for untyped buffer instructions.
+typedef __amdgpu_buffer_rsrc_t brsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ brsrc_t brsrc(const double *p, long long n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)(n * 8), 0x00020000);
+}
+
+__device__ __forceinline__ double bload(brsrc_t r, int e)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, e * 8, 0, 0));
+}
+
+__device__ __forceinline__ void bstore(brsrc_t r, int e, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, e * 8, 0, 0);
+}
+
 __device__ __forceinline__ double readlane_d(double v, int lane)
 {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);

@@ -20,11 +20,13 @@
 //      F rows), the others from running sums held in registers through the sweep
 //      (G G^T -> hat R_k, F G^T -> hat Q_k^T, F F^T -> hat A_k).
 // Memory: when a stage starts it issues the stores of the previous stage's
-// outputs (from LDS) and the loads of the next stage's blocks together, and
-// consumes the loads only at its end: loads and stores share one counter, so a
-// wait for a load with a younger store pending waits for every memory operation.
+// outputs (from LDS) and the loads of the next stage's blocks together, and waits
+// for them only at its end, where the blocks go to LDS: loads and stores share one
+// counter, so a wait for a load with a younger store pending waits for every
+// memory operation.  Blocks move as lane-contiguous elements through range-checked
+// buffer accesses (past a block a load reads zero and a store is dropped).
 //
-// Forward sweep (solve modes): the same lane layout with the factor rows fetched
+// Forward sweep (solve modes): the same lane layout with the factor rows staged
 // from HBM.  Backward sweep: lane c owns column c of the stage's blocks (staged
 // through LDS) and the back substitution broadcasts x_c with readlane.
 //
@@ -44,12 +46,53 @@ struct LC {
     static constexpr int KS = BP / 4;               // k-steps of 4 columns
     static constexpr int NTL = T2 * (T2 + 1) / 2;   // lower tiles
     static constexpr int NROW = 3 * BP + NGM;       // panel rows (lane t holds row t)
-    static constexpr int G0 = BP, F0 = BP + NGM;    // Gram coordinate of the first G / F row
+    static constexpr int F0 = BP + NGM;             // Gram coordinate of the first F row
+    static constexpr int MB = BP * BP / 64;         // elements per lane of a b x b block
+    static constexpr int MG = NGM * BP / 64;        // ... of an ng x b block
+    static constexpr int MY = 2;                    // ... of b x nr rhs rows
     static_assert(BP == 8 || BP == 16, "single-wave sweeps cover padded sizes 8 and 16");
     static_assert(NROW <= 64 && N2 % 16 == 0, "row placement");
+    static_assert(BP * MAX_NRHS_DEV <= 64 * MY, "rhs rows");
     static_assert(WC<BP>::NW == 1 && WC<BP>::TE == BP && WC<BP>::TG == 2 * BP && WC<BP>::TF == 2 * BP + NGM,
                   "lane t holds panel row t");
 };
+
+// Lane-contiguous elements e = t + 64 m of a row-major block with `cols` columns:
+// row er, column ec, and the LDS offset (pitch P) of that entry with the row
+// clamped to 15 (an element past the block then still reads inside the LDS areas).
+template <int M>
+struct Elems {
+    int er[M], ec[M], lo[M];
+    __device__ __forceinline__ void init(int t, int cols, int P)
+    {
+        const float inv = 1.0f / (float)cols;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            rc_of(t + 64 * m, cols, inv, er[m], ec[m]);
+            lo[m] = (er[m] < NGM ? er[m] : NGM - 1) * P + ec[m];
+        }
+    }
+};
+
+// A block of n elements from LDS (offsets in the first MU entries of E) to global
+// memory, range-checked; LOWER zeroes the entries right of the diagonal.  Every
+// LDS read before the first store.
+template <int MU, bool LOWER = false, int M>
+__device__ __forceinline__ void lstore(double *dst, long long n, const double *lds, const Elems<M> &E, int t,
+                                       double scale = 1.0)
+{
+    static_assert(MU <= M, "element count");
+    const brsrc_t r = brsrc(dst, n);
+    double v[MU];
+#pragma unroll
+    for (int m = 0; m < MU; ++m) {
+        const double x = lds[E.lo[m]];
+        v[m] = (LOWER && E.ec[m] > E.er[m]) ? 0.0 : scale * x;
+    }
+    pin_row<MU>(v);
+#pragma unroll
+    for (int m = 0; m < MU; ++m) bstore(r, t + 64 * m, v[m]);
+}
 
 // ---------------------------------------------------------------- elimination
 // Column c of the fused elimination, then the columns after it (template
@@ -82,102 +125,85 @@ __device__ __forceinline__ void lelim(double (&row)[W], double (&w)[NR], double 
     }
 }
 
-// Rows [0, rows) x [0, cols) of an LDS block (pitch P) to a row-major global block
-// from a single wave, with the (row, column) of each lane's elements given; LOWER
-// zeroes the entries right of the diagonal.  Every LDS read before the first store.
-template <int M, bool LOWER = false>
-__device__ __forceinline__ void lstore(double *dst, const double *lds, int P, int rows, int cols, const int (&er)[M],
-                                       const int (&ec)[M], double scale = 1.0)
-{
-    double v[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        const bool ok = er[m] < rows;
-        const double x = lds[(ok ? er[m] : 0) * P + (ok ? ec[m] : 0)];
-        v[m] = (LOWER && ec[m] > er[m]) ? 0.0 : scale * x;
-    }
-    pin_row<M>(v);
-#pragma unroll
-    for (int m = 0; m < M; ++m)
-        if (er[m] < rows) dst[er[m] * cols + ec[m]] = v[m];
-}
-
 // ---------------------------------------------------------------- factor loads
-// The blocks of stage j of a factor chain that the stage before consumes at its
-// end: the next diagonal block (both triangles, to symmetrize it) and arrow rows
-// in the Gram's tile layout (lane l, element v of tile row tr: row 16 tr + 4 v +
-// l / 16, column l % 16), the next coupling rows on the E lanes and the next rhs
-// rows on the D lanes.  Reduced chain: the partials minus hat F hat F^T, hat G
-// hat F^T, plus -hat F y of the segment before (Eqs. 7, 8c, 9d).
+// The blocks of stage j of a factor chain (lane-contiguous elements): the
+// diagonal block, the coupling block (its rows are the next E rows), the arrow
+// rows and the rhs rows.  Reduced chain: the partials minus hat F hat F^T,
+// hat G hat F^T, plus -hat F y of the segment before (Eqs. 7, 8c, 9d).
 template <int BP, int NR, bool RED>
 struct LanePre {
-    static constexpr int T2 = LC<BP>::T2;
-    double x1[T2][4], x2[T2][4], x3[T2][4], x4[T2][4];
-    double cr[BP];
-    double r1[NR], r2[NR];
+    using G = LC<BP>;
+    static constexpr int MB = G::MB, MG = G::MG, MY = G::MY;
+    double d[MB], c[MB], g[MG], r[MY];
+    double d2[RED ? MB : 1], g2[RED ? MG : 1], r2[RED ? MY : 1];
 
     __device__ __forceinline__ void load(const WChain<RED> &ch, int j, bool fwd, int t)
     {
         const Args &a = ch.a;
         const SysDesc &sd = ch.sd;
         const int b = sd.b, ng = sd.ng, nr = a.nr, s = ch.stage(j);
-        const long long b2 = (long long)b * b, gb = (long long)ng * b;
-        const double *Dp = RED ? a.F + sd.oLd + s * b2 : a.D + sd.oD + s * b2;
-        const double *Bp = RED ? a.F + sd.oLb + s * gb : a.B + sd.oB + s * gb;
-        const double *sc = RED ? ch.scr(j + 1) : a.F;
-        const int q = t & 15, p0 = t >> 4;
-#pragma unroll
-        for (int tr = 0; tr < T2; ++tr)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int pb = 16 * tr + 4 * v, p = pb + p0;
-                if (pb < BP) {
-                    const bool ok = p < b && q < b;
-                    const int e1 = ok ? p * b + q : 0, e2 = ok ? q * b + p : 0;
-                    x1[tr][v] = ld_or_zero(Dp, e1, ok);
-                    x2[tr][v] = ld_or_zero(Dp, e2, ok);
-                    x3[tr][v] = RED ? ld_or_zero(sc + scr_dA(b, ng, nr), e1, ok) : 0.0;
-                    x4[tr][v] = RED ? ld_or_zero(sc + scr_dA(b, ng, nr), e2, ok) : 0.0;
-                } else if (pb < BP + NGM) {
-                    const int qg = p - BP;
-                    const bool ok = qg < ng && q < b;
-                    const int e1 = ok ? qg * b + q : 0;
-                    x1[tr][v] = ld_or_zero(Bp, e1, ok);
-                    x3[tr][v] = RED ? ld_or_zero(sc + scr_dQ(b, ng, nr), e1, ok) : 0.0;
-                    x2[tr][v] = 0.0;
-                    x4[tr][v] = 0.0;
-                } else {
-                    x1[tr][v] = x2[tr][v] = x3[tr][v] = x4[tr][v] = 0.0;
-                }
-            }
+        const long long b2 = (long long)b * b, gb = (long long)ng * b, rb = fwd ? (long long)b * nr : 0;
         const bool hasE = ch.has_next(j);
-        const double *Cp = RED ? a.F + ch.coup_off(j) : a.C + sd.oC + s * b2;
-        const int r = t - BP;
-        const bool er = hasE && r >= 0 && r < b;
-        const int rb = er ? r * b : 0;
+        const brsrc_t rD = brsrc(RED ? a.F + sd.oLd + s * b2 : a.D + sd.oD + s * b2, b2);
+        const brsrc_t rC = brsrc(RED ? a.F + ch.coup_off(j) : a.C + sd.oC + s * b2, hasE ? b2 : 0);
+        const brsrc_t rB = brsrc(RED ? a.F + sd.oLb + s * gb : a.B + sd.oB + s * gb, gb);
+        const brsrc_t rR = brsrc(a.rhs + sd.oRhs + s * b * nr, rb);
 #pragma unroll
-        for (int m = 0; m < BP; ++m) cr[m] = ld_or_zero(Cp, rb + m, er && m < b);
-        const double *Rp = a.rhs + sd.oRhs + (long long)s * b * nr;
-        const bool dr = fwd && t < b;
-        const int ro = dr ? t * nr : 0;
+        for (int m = 0; m < MB; ++m) {
+            d[m] = bload(rD, t + 64 * m);
+            c[m] = bload(rC, t + 64 * m);
+        }
 #pragma unroll
-        for (int jj = 0; jj < NR; ++jj) {
-            r1[jj] = ld_or_zero(Rp, ro + jj, dr && jj < nr);
-            r2[jj] = RED ? ld_or_zero(sc + scr_dy(b, ng, nr), ro + jj, dr && jj < nr) : 0.0;
+        for (int m = 0; m < MG; ++m) g[m] = bload(rB, t + 64 * m);
+#pragma unroll
+        for (int m = 0; m < MY; ++m) r[m] = bload(rR, t + 64 * m);
+        if constexpr (RED) {
+            const double *sc = ch.scr(j + 1);
+            const brsrc_t rA = brsrc(sc + scr_dA(b, ng, nr), b2), rQ = brsrc(sc + scr_dQ(b, ng, nr), gb);
+            const brsrc_t rY = brsrc(sc + scr_dy(b, ng, nr), rb);
+#pragma unroll
+            for (int m = 0; m < MB; ++m) d2[m] = bload(rA, t + 64 * m);
+#pragma unroll
+            for (int m = 0; m < MG; ++m) g2[m] = bload(rQ, t + 64 * m);
+#pragma unroll
+            for (int m = 0; m < MY; ++m) r2[m] = bload(rY, t + 64 * m);
         }
     }
 
-    // Element v of tile row tr of the E-column tiles as the next stage starts it:
-    // the symmetrized diagonal block (identity on the padded diagonal), the arrow
-    // rows, or zero (fill rows).
-    __device__ __forceinline__ double fresh(int tr, int v, int t, int b) const
+    // The diagonal block and the arrow rows into cb (rows [0, BP) and [BP, BP + 16),
+    // pitch P: the Gram reads them as its accumulator input), the coupling rows into
+    // the E rows of the next-row area, the rhs rows into rn (pitch RP).
+    __device__ __forceinline__ void commit(double *cb, double *nxt, double *rn, int b, int ng, int nr,
+                                          const Elems<LC<BP>::MG> &E, const Elems<LC<BP>::MY> &Y, int t) const
     {
-        const int pb = 16 * tr + 4 * v, p = pb + (t >> 4), q = t & 15;
-        if (pb < BP) return 0.5 * ((x1[tr][v] - x3[tr][v]) + (x2[tr][v] - x4[tr][v])) + ((p == q && p >= b) ? 1.0 : 0.0);
-        if (pb < BP + NGM) return x1[tr][v] - x3[tr][v];
-        return 0.0;
+        constexpr int P = WC<BP>::P, RP = WC<BP>::RP;
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            if (t + 64 * m < b * b) {
+                cb[E.er[m] * P + E.ec[m]] = RED ? d[m] - d2[m] : d[m];
+                nxt[(BP + E.er[m]) * P + E.ec[m]] = c[m];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < MG; ++m)
+            if (t + 64 * m < ng * b) cb[(BP + E.er[m]) * P + E.ec[m]] = RED ? g[m] - g2[m] : g[m];
+#pragma unroll
+        for (int m = 0; m < MY; ++m)
+            if (t + 64 * m < b * nr) rn[Y.er[m] * RP + Y.ec[m]] = RED ? r[m] + r2[m] : r[m];
     }
 };
+
+// Element (p, q), q < BP, of the E-column tiles as the next stage starts it: the
+// symmetrized diagonal block (cb holds the identity on its padded diagonal), the
+// arrow rows, or zero for the fill rows.
+template <int BP>
+__device__ __forceinline__ double lfresh(const double *cb, int pb, int p, int q)
+{
+    constexpr int P = WC<BP>::P;
+    if (pb < BP) return 0.5 * (cb[p * P + q] + cb[q * P + p]);
+    if (pb < BP + NGM) return cb[p * P + q];
+    return 0.0;
+}
 
 // ---------------------------------------------------------------- factor sweep
 // Factor (and with FWD forward-substitute) one chain: segment k of a system
@@ -195,55 +221,45 @@ __device__ __forceinline__ int lane_factor(const Args &a, const SysDesc &sd, int
     using C = WC<BP>;
     using G = LC<BP>;
     constexpr int P = C::P, RP = C::RP, T2 = G::T2, KS = G::KS, NTL = G::NTL, NROW = G::NROW, F0 = G::F0;
-    constexpr int MB = BP * BP / 64, MG = NGM * BP / 64;
+    constexpr int MB = G::MB, MG = G::MG, MY = G::MY;
     const WChain<RED> ch{a, sd, k};
     const int b = sd.b, ng = sd.ng, nr = a.nr;
-    const long long b2 = (long long)b * b;
+    const long long b2 = (long long)b * b, gb = (long long)ng * b, rb = (long long)b * nr;
     double *F = a.F;
     const bool hasF = !RED && k > 1;
     const int len = ch.length();
     const int sep = hasF ? sep_of(sd, k) : 0;
     const int tid = threadIdx.x;
+    double *cb = L.acc_a;   // (BP + 16) x P: the next diagonal block and arrow rows
 
-    // (row, column) of this lane's elements of a b-column block, for the stores
-    int er[MG], ec[MG], yr[2], yc[2];
-    {
-        const float invb = 1.0f / (float)b, invr = 1.0f / (float)nr;
-#pragma unroll
-        for (int m = 0; m < MG; ++m) rc_of(tid + 64 * m, b, invb, er[m], ec[m]);
-#pragma unroll
-        for (int m = 0; m < 2; ++m) rc_of(tid + 64 * m, nr, invr, yr[m], yc[m]);
-    }
-    int erd[MB], ecd[MB];
-#pragma unroll
-    for (int m = 0; m < MB; ++m) { erd[m] = er[m]; ecd[m] = ec[m]; }
+    Elems<MG> E;   // elements of blocks with b columns
+    Elems<MY> Y;   // elements of rhs rows
+    E.init(tid, b, P);
+    Y.init(tid, nr, RP);
 
-    // ---- prologue: the next-row area with the identity on the padded diagonal,
-    // stage 0's diagonal and arrow rows as the Gram leaves them for later stages,
-    // its fill rows F_w = C_sep^T; the running sums (hat R_k = 0, hat A_k =
-    // sym(D_sep), hat Q_k = B_sep); the separator rhs on the F lanes
+    // ---- prologue: the next-row area and cb with the identity on the padded
+    // diagonal; stage 0's blocks; its diagonal and arrow rows where the Gram leaves
+    // them for later stages, its fill rows F_w = C_sep^T; the running sums (hat R_k
+    // = 0, hat A_k = sym(D_sep), hat Q_k = B_sep); the separator rhs on the F lanes
     for (int e = tid; e < (C::NROW + 2) * P; e += 64) {
         const int rr = e / P, cc = e - rr * P;
         L.nxt[e] = (rr < BP && rr == cc && rr >= b) ? 1.0 : 0.0;
+    }
+    for (int e = tid; e < (BP + NGM) * P; e += 64) {
+        const int rr = e / P, cc = e - rr * P;
+        cb[e] = (rr < BP && rr == cc && rr >= b) ? 1.0 : 0.0;
     }
     if (FWD)
         for (int e = tid; e < C::BPX * RP; e += 64) L.w[e] = 0.0;
     LanePre<BP, NR, RED> pre;
     pre.load(ch, 0, FWD, tid);
     wave_sync();
-    {
-        const int q = tid & 15, p0 = tid >> 4;
-        if (BP == 16 || q < BP) {
-#pragma unroll
-            for (int tr = 0; tr < T2; ++tr)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int pb = 16 * tr + 4 * v, p = pb + p0;
-                    if (pb < F0) L.nxt[(pb < BP ? p : BP + p) * P + q] = pre.fresh(tr, v, tid, b);
-                }
-        }
-    }
+    pre.commit(cb, L.nxt, L.rn, b, ng, nr, E, Y, tid);
     wave_sync();
+    for (int e = tid; e < (BP + NGM) * BP; e += 64) {
+        const int p = e / BP, q = e - p * BP;
+        L.nxt[(p < BP ? p : BP + p) * P + q] = lfresh<BP>(cb, p < BP ? 0 : BP, p, q);
+    }
     if (hasF) {
         const double *Cs = a.C + sd.oC + (long long)sep * b2;
         for (int e = tid; e < b * b; e += 64) {
@@ -300,19 +316,16 @@ __device__ __forceinline__ int lane_factor(const Args &a, const SysDesc &sd, int
         const bool isD = t < BP;
         const bool isE = t >= BP && t < 2 * BP;
 
-        // ---- (1) rows: D, G, F rows from the next-row area, E rows from registers
+        // ---- (1) rows from the next-row area; the D lanes' rhs
         {
             const double *src = L.nxt + (t < NROW ? t : C::ZROW) * P;
 #pragma unroll
-            for (int m = 0; m < BP; ++m) {
-                const double x = src[m];
-                row[m] = isE ? pre.cr[m] : x;
-            }
+            for (int m = 0; m < BP; ++m) row[m] = src[m];
             if (FWD) {
-                const double *lw = L.w + (isD ? t : 0) * RP;
+                const int tr = isD ? t : 0;
 #pragma unroll
                 for (int j = 0; j < NR; ++j) {
-                    const double x = lw[j] + (pre.r1[j] + pre.r2[j]);
+                    const double x = L.w[tr * RP + j] + L.rn[tr * RP + j];
                     w[j] = isD ? x : (isE ? 0.0 : w[j]);
                 }
             }
@@ -321,11 +334,11 @@ __device__ __forceinline__ int lane_factor(const Args &a, const SysDesc &sd, int
         // ---- (2) the previous stage's outputs leave, the next stage's blocks arrive
         if (i > 0) {
             const int ps = ch.stage(i - 1);
-            lstore<MB, true>(F + sd.oLd + (long long)ps * b2, L.pnl + C::RD * P, P, b, b, erd, ecd);
-            lstore<MB>(F + ch.coup_off(i - 1), L.pnl + C::RE * P, P, b, b, erd, ecd);
-            if (ng) lstore<MG>(F + sd.oLb + (long long)ps * ng * b, L.pnl + C::RG * P, P, ng, b, er, ec);
-            if (hasF) lstore<MB>(F + ch.fill_off(i - 1), L.pnl + C::RF * P, P, b, b, erd, ecd);
-            if (FWD) lstore<2>(a.rhs + sd.oRhs + (long long)ps * b * nr, L.y, RP, b, nr, yr, yc);
+            lstore<MB, true>(F + sd.oLd + (long long)ps * b2, b2, L.pnl + C::RD * P, E, t);
+            lstore<MB>(F + ch.coup_off(i - 1), b2, L.pnl + C::RE * P, E, t);
+            if (ng) lstore<MG>(F + sd.oLb + (long long)ps * gb, gb, L.pnl + C::RG * P, E, t);
+            if (hasF) lstore<MB>(F + ch.fill_off(i - 1), b2, L.pnl + C::RF * P, E, t);
+            if (FWD) lstore<MY>(a.rhs + sd.oRhs + (long long)ps * rb, rb, L.y, Y, t);
         }
         if (!last) pre.load(ch, i + 1, FWD, t);
 
@@ -334,7 +347,8 @@ __device__ __forceinline__ int lane_factor(const Args &a, const SysDesc &sd, int
         lelim<BP, NR, FWD, 0>(row, w, myinv, t);
         if (any_bad_pivot(t < b, myinv) && !failed) failed = gs + 1;
 
-        // ---- (4) rows to LDS: the Gram's operands, the factor rows and y for their stores
+        // ---- (4) rows to LDS: the Gram's operands, the factor rows and y for their
+        // stores; -hat E y for the next stage's rhs
         if (t < NROW) {
             double *dst = L.pnl + t * P;
 #pragma unroll
@@ -345,13 +359,13 @@ __device__ __forceinline__ int lane_factor(const Args &a, const SysDesc &sd, int
 #pragma unroll
                 for (int j = 0; j < NR; ++j) L.y[t * RP + j] = w[j] * myinv;
             } else if (isE && hasE) {
-                // -hat E y: the next stage's rhs once r_{i+1} is added (at a segment
-                // end -hat F_k y, for the scratch)
                 const int r = t - BP;
 #pragma unroll
                 for (int j = 0; j < NR; ++j) L.w[r * RP + j] = w[j];
             }
         }
+        // the next stage's blocks (their loads have arrived during the elimination)
+        if (!last) pre.commit(cb, L.nxt, L.rn, b, ng, nr, E, Y, t);
         wave_sync();
 
         // ---- (5) Gram of the E, G, F rows on the matrix cores
@@ -372,6 +386,7 @@ __device__ __forceinline__ int lane_factor(const Args &a, const SysDesc &sd, int
                 live[T2 - 1] = ng > 8 || hasF;
             }
             const bool fq = BP == 16 || q0 < BP;   // a column of the E rows
+            const bool fresh = !endS && !last;
 #pragma unroll
             for (int tr = 0; tr < T2; ++tr)
 #pragma unroll
@@ -382,7 +397,8 @@ __device__ __forceinline__ int lane_factor(const Args &a, const SysDesc &sd, int
                     if (tc == 0) {
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
-                            const double fv = endS ? 0.0 : pre.fresh(tr, v, t, b);
+                            const int pb = 16 * tr + 4 * v, p = pb + p0;
+                            const double fv = fresh ? lfresh<BP>(cb, pb, fq ? p : 0, fq ? q0 : 0) : 0.0;
                             cur[v] = fq ? fv : cur[v];
                         }
                     }
@@ -406,18 +422,18 @@ __device__ __forceinline__ int lane_factor(const Args &a, const SysDesc &sd, int
             wstore<64, BP * BP>(sc + scr_dA(b, ng, nr), L.nxt + C::RD * P, P, b, b, t, -1.0);
             if (ng) wstore<64, NGM * BP>(sc + scr_dQ(b, ng, nr), L.nxt + C::RG * P, P, ng, b, t, -1.0);
             if (hasF) wstore<64, BP * BP, true>(F + sd.oH + (long long)(k - 2) * b2, L.nxt + C::RF * P, P, b, b, t);
-            if (FWD) lstore<2>(sc + scr_dy(b, ng, nr), L.w, RP, b, nr, yr, yc);
+            if (FWD) lstore<MY>(sc + scr_dy(b, ng, nr), rb, L.w, Y, t);
         }
     }
 
     // ---- epilogue: the last stage's outputs, the running sums and the partials
     {
         const int ps = ch.stage(len - 1);
-        lstore<MB, true>(F + sd.oLd + (long long)ps * b2, L.pnl + C::RD * P, P, b, b, erd, ecd);
-        if (ch.has_next(len - 1)) lstore<MB>(F + ch.coup_off(len - 1), L.pnl + C::RE * P, P, b, b, erd, ecd);
-        if (ng) lstore<MG>(F + sd.oLb + (long long)ps * ng * b, L.pnl + C::RG * P, P, ng, b, er, ec);
-        if (hasF) lstore<MB>(F + ch.fill_off(len - 1), L.pnl + C::RF * P, P, b, b, erd, ecd);
-        if (FWD) lstore<2>(a.rhs + sd.oRhs + (long long)ps * b * nr, L.y, RP, b, nr, yr, yc);
+        lstore<MB, true>(F + sd.oLd + (long long)ps * b2, b2, L.pnl + C::RD * P, E, tid);
+        if (ch.has_next(len - 1)) lstore<MB>(F + ch.coup_off(len - 1), b2, L.pnl + C::RE * P, E, tid);
+        if (ng) lstore<MG>(F + sd.oLb + (long long)ps * gb, gb, L.pnl + C::RG * P, E, tid);
+        if (hasF) lstore<MB>(F + ch.fill_off(len - 1), b2, L.pnl + C::RF * P, E, tid);
+        if (FWD) lstore<MY>(a.rhs + sd.oRhs + (long long)ps * rb, rb, L.y, Y, tid);
     }
     {
         const int q0 = tid & 15, p0 = tid >> 4;
@@ -486,39 +502,65 @@ __device__ __forceinline__ int lane_factor(const Args &a, const SysDesc &sd, int
 }
 
 // ---------------------------------------------------------------- forward sweep
-// The factor rows of stage j on their lanes (the D row without its diagonal, which
-// comes separately), fetched from HBM, and the D lanes' rhs rows (RED: plus -hat F y).
+// The factor blocks of stage j of a chain (lane-contiguous elements) and the rhs
+// rows (RED: plus -hat F y), committed to the staging area: rows of L without
+// their diagonal (which goes to dv), hat E, hat G, the fill rows.
 template <int BP, int NR, bool RED>
 struct LaneRowPre {
-    double row[BP], diag, r1[NR], r2[NR];
+    using G = LC<BP>;
+    static constexpr int MB = G::MB, MG = G::MG, MY = G::MY;
+    double d[MB], e[MB], f[MB], g[MG], r[MY], r2[RED ? MY : 1];
 
     __device__ __forceinline__ void load(const WChain<RED> &ch, int j, bool hasF, int t)
     {
         const Args &a = ch.a;
         const SysDesc &sd = ch.sd;
         const int b = sd.b, ng = sd.ng, nr = a.nr, s = ch.stage(j);
-        const long long b2 = (long long)b * b;
+        const long long b2 = (long long)b * b, gb = (long long)ng * b, rb = (long long)b * nr;
         const bool hasE = ch.has_next(j);
-        const bool isD = t < BP, isE = t >= BP && t < 2 * BP, isG = t >= 2 * BP && t < 2 * BP + NGM;
-        const int r = isD ? t : (isE ? t - BP : (isG ? t - 2 * BP : t - 2 * BP - NGM));
-        const bool isF = hasF && t >= 2 * BP + NGM && r < BP;
-        const bool ok = isD ? r < b : (isE ? hasE && r < b : (isG ? r < ng : isF && r < b));
-        const long long off = isD ? sd.oLd + s * b2
-                                  : (isE ? ch.coup_off(j) : (isG ? sd.oLb + (long long)s * ng * b : (isF ? ch.fill_off(j) : 0)));
-        const double *src = a.F + off;
-        const int ro = ok ? r * b : 0;
+        const brsrc_t rD = brsrc(a.F + sd.oLd + s * b2, b2);
+        const brsrc_t rE = brsrc(a.F + ch.coup_off(j), hasE ? b2 : 0);
+        const brsrc_t rF = brsrc(a.F + (hasF ? ch.fill_off(j) : 0), hasF ? b2 : 0);
+        const brsrc_t rB = brsrc(a.F + sd.oLb + s * gb, gb);
+        const brsrc_t rR = brsrc(a.rhs + sd.oRhs + s * rb, rb);
 #pragma unroll
-        for (int m = 0; m < BP; ++m) row[m] = ld_or_zero(src, ro + m, ok && m < b && !(isD && m == t));
-        const bool dd = isD && t < b;
-        diag = dd ? ld_or_zero(src, ro + t, dd) : 1.0;
-        const double *Rp = a.rhs + sd.oRhs + (long long)s * b * nr;
-        const double *sc = RED ? ch.scr(j + 1) : a.F;
-        const int rr = dd ? t * nr : 0;
-#pragma unroll
-        for (int jj = 0; jj < NR; ++jj) {
-            r1[jj] = ld_or_zero(Rp, rr + jj, dd && jj < nr);
-            r2[jj] = RED ? ld_or_zero(sc + scr_dy(b, ng, nr), rr + jj, dd && jj < nr) : 0.0;
+        for (int m = 0; m < MB; ++m) {
+            d[m] = bload(rD, t + 64 * m);
+            e[m] = bload(rE, t + 64 * m);
+            f[m] = bload(rF, t + 64 * m);
         }
+#pragma unroll
+        for (int m = 0; m < MG; ++m) g[m] = bload(rB, t + 64 * m);
+#pragma unroll
+        for (int m = 0; m < MY; ++m) r[m] = bload(rR, t + 64 * m);
+        if constexpr (RED) {
+            const brsrc_t rY = brsrc(ch.scr(j + 1) + scr_dy(b, ng, nr), rb);
+#pragma unroll
+            for (int m = 0; m < MY; ++m) r2[m] = bload(rY, t + 64 * m);
+        }
+    }
+
+    __device__ __forceinline__ void commit(double *area, double *dv, double *rn, int b, int ng, int nr,
+                                          const Elems<LC<BP>::MG> &E, const Elems<LC<BP>::MY> &Y, int t) const
+    {
+        using C = WC<BP>;
+        constexpr int P = C::P, RP = C::RP;
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            if (t + 64 * m < b * b) {
+                const int rr = E.er[m], cc = E.ec[m];
+                area[(C::RD + rr) * P + cc] = (rr == cc) ? 0.0 : d[m];
+                if (rr == cc) dv[rr] = d[m];
+                area[(C::RE + rr) * P + cc] = e[m];
+                area[(C::RF + rr) * P + cc] = f[m];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < MG; ++m)
+            if (t + 64 * m < ng * b) area[(C::RG + E.er[m]) * P + E.ec[m]] = g[m];
+#pragma unroll
+        for (int m = 0; m < MY; ++m)
+            if (t + 64 * m < b * nr) rn[Y.er[m] * RP + Y.ec[m]] = RED ? r[m] + r2[m] : r[m];
     }
 };
 
@@ -530,19 +572,22 @@ template <int BP, int NR, bool RED>
 __device__ __forceinline__ void lane_forward(const Args &a, const SysDesc &sd, int k, const WaveLds &L)
 {
     using C = WC<BP>;
-    constexpr int RP = C::RP;
+    using G = LC<BP>;
+    constexpr int P = C::P, RP = C::RP, NROW = G::NROW, MY = G::MY;
     const WChain<RED> ch{a, sd, k};
     const int b = sd.b, ng = sd.ng, nr = a.nr;
+    const long long rb = (long long)b * nr;
     const bool hasF = !RED && k > 1;
     const int len = ch.length();
     const int sep = hasF ? sep_of(sd, k) : 0;
     const int tid = threadIdx.x;
-    int yr[2], yc[2];
-    {
-        const float invr = 1.0f / (float)nr;
-#pragma unroll
-        for (int m = 0; m < 2; ++m) rc_of(tid + 64 * m, nr, invr, yr[m], yc[m]);
-    }
+    double *area = L.pnl, *dv = L.dinv;
+    Elems<G::MG> E;
+    Elems<MY> Y;
+    E.init(tid, b, P);
+    Y.init(tid, nr, RP);
+    for (int e = tid; e < NROW * P; e += 64) area[e] = 0.0;
+    for (int e = tid; e < C::BPX; e += 64) dv[e] = 1.0;
     for (int e = tid; e < C::BPX * RP; e += 64) L.w[e] = 0.0;
     double w[NR];
     {
@@ -555,6 +600,8 @@ __device__ __forceinline__ void lane_forward(const Args &a, const SysDesc &sd, i
     LaneRowPre<BP, NR, RED> pre;
     pre.load(ch, 0, hasF, tid);
     wave_sync();
+    pre.commit(area, dv, L.rn, b, ng, nr, E, Y, tid);
+    wave_sync();
     double row[BP];
     for (int i = 0; i < len; ++i) {
         const bool hasE = ch.has_next(i);
@@ -563,21 +610,21 @@ __device__ __forceinline__ void lane_forward(const Args &a, const SysDesc &sd, i
         const int t = opaque_tid();
         const bool isD = t < BP;
         const bool isE = t >= BP && t < 2 * BP;
-#pragma unroll
-        for (int m = 0; m < BP; ++m) row[m] = pre.row[m];
-        const double diag = pre.diag;
         {
-            const double *lw = L.w + (isD ? t : 0) * RP;
+            const double *src = area + (t < NROW ? t : 0) * P;
+#pragma unroll
+            for (int m = 0; m < BP; ++m) row[m] = t < NROW ? src[m] : 0.0;
+            const int tr = isD ? t : 0;
 #pragma unroll
             for (int j = 0; j < NR; ++j) {
-                const double x = lw[j] + (pre.r1[j] + pre.r2[j]);
+                const double x = L.w[tr * RP + j] + L.rn[tr * RP + j];
                 w[j] = isD ? x : (isE ? 0.0 : w[j]);
             }
         }
+        const double myinv = 1.0 / dv[isD ? t : 0];
         wave_sync();
-        if (i > 0) lstore<2>(a.rhs + sd.oRhs + (long long)ch.stage(i - 1) * b * nr, L.y, RP, b, nr, yr, yc);
+        if (i > 0) lstore<MY>(a.rhs + sd.oRhs + (long long)ch.stage(i - 1) * rb, rb, L.y, Y, t);
         if (!last) pre.load(ch, i + 1, hasF, t);
-        const double myinv = 1.0 / diag;
 #pragma unroll
         for (int c = 0; c < BP; ++c) {
             const double ic = readlane_d(myinv, c);
@@ -592,10 +639,11 @@ __device__ __forceinline__ void lane_forward(const Args &a, const SysDesc &sd, i
 #pragma unroll
             for (int j = 0; j < NR; ++j) L.w[r * RP + j] = w[j];
         }
+        if (!last) pre.commit(area, dv, L.rn, b, ng, nr, E, Y, t);
         wave_sync();
-        if (endS) lstore<2>(ch.scr(k) + scr_dy(b, ng, nr), L.w, RP, b, nr, yr, yc);
+        if (endS) lstore<MY>(ch.scr(k) + scr_dy(b, ng, nr), rb, L.w, Y, t);
     }
-    lstore<2>(a.rhs + sd.oRhs + (long long)ch.stage(len - 1) * b * nr, L.y, RP, b, nr, yr, yc);
+    lstore<MY>(a.rhs + sd.oRhs + (long long)ch.stage(len - 1) * rb, rb, L.y, Y, tid);
     {
         const int r = tid - C::TG;
         if (r >= 0 && r < NGM) {
@@ -620,60 +668,54 @@ __device__ __forceinline__ void lane_forward(const Args &a, const SysDesc &sd, i
 }
 
 // ---------------------------------------------------------------- backward sweep
-// The factor blocks of stage i (lane-contiguous element loads) and its y rows
-// (with PRIMAL the primal solution rows too), committed to the staging area: L
-// without its diagonal (which goes to a vector), hat E, hat G, the fill rows.
+// The factor blocks of stage i (lane-contiguous elements) and its y rows (with
+// PRIMAL the primal solution rows too), committed to the staging area: L without
+// its diagonal (which goes to dv), hat E, hat G, the fill rows; y into Yl.
 template <int BP, int NR, bool RED>
 struct LaneColPre {
-    static constexpr int MB = BP * BP / 64, MG = NGM * BP / 64;
-    double d[MB], e[MB], f[MB], g[MG], y[2], px[2];
+    using G = LC<BP>;
+    static constexpr int MB = G::MB, MG = G::MG, MY = G::MY;
+    double d[MB], e[MB], f[MB], g[MG], y[MY], px[MY];
 
     template <bool PRIMAL>
-    __device__ __forceinline__ void load(const WChain<RED> &ch, int i, bool hasF, int t, const int (&er)[MG],
-                                         const int (&ec)[MG], const int (&yr)[2], const int (&yc)[2])
+    __device__ __forceinline__ void load(const WChain<RED> &ch, int i, bool hasF, int t)
     {
         const Args &a = ch.a;
         const SysDesc &sd = ch.sd;
         const int b = sd.b, ng = sd.ng, nr = a.nr, s = ch.stage(i);
-        const long long b2 = (long long)b * b;
+        const long long b2 = (long long)b * b, gb = (long long)ng * b, rb = (long long)b * nr;
         const bool hasE = ch.has_next(i);
-        const double *Ld = a.F + sd.oLd + s * b2, *Le = a.F + ch.coup_off(i);
-        const double *Lb = a.F + sd.oLb + (long long)s * ng * b;
-        const double *Lf = a.F + (hasF ? ch.fill_off(i) : 0);
-        const double *Y = a.rhs + sd.oRhs + (long long)s * b * nr;
-        const double *XP = PRIMAL ? a.xp + sd.oRhs + (long long)s * b * nr : Y;
+        const brsrc_t rD = brsrc(a.F + sd.oLd + s * b2, b2);
+        const brsrc_t rE = brsrc(a.F + ch.coup_off(i), hasE ? b2 : 0);
+        const brsrc_t rF = brsrc(a.F + (hasF ? ch.fill_off(i) : 0), hasF ? b2 : 0);
+        const brsrc_t rB = brsrc(a.F + sd.oLb + s * gb, gb);
+        const brsrc_t rY = brsrc(a.rhs + sd.oRhs + s * rb, rb);
+        const brsrc_t rP = brsrc(PRIMAL ? a.xp + sd.oRhs + s * rb : a.rhs, PRIMAL ? rb : 0);
 #pragma unroll
         for (int m = 0; m < MB; ++m) {
-            const bool in = er[m] < b;
-            const int x = in ? er[m] * b + ec[m] : 0;
-            d[m] = ld_or_zero(Ld, x, in);
-            e[m] = ld_or_zero(Le, x, hasE && in);
-            f[m] = ld_or_zero(Lf, x, hasF && in);
+            d[m] = bload(rD, t + 64 * m);
+            e[m] = bload(rE, t + 64 * m);
+            f[m] = bload(rF, t + 64 * m);
         }
 #pragma unroll
-        for (int m = 0; m < MG; ++m) {
-            const bool in = er[m] < ng;
-            g[m] = ld_or_zero(Lb, in ? er[m] * b + ec[m] : 0, in);
-        }
+        for (int m = 0; m < MG; ++m) g[m] = bload(rB, t + 64 * m);
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            const bool in = yr[m] < b;
-            const int x = in ? yr[m] * nr + yc[m] : 0;
-            y[m] = ld_or_zero(Y, x, in);
-            px[m] = PRIMAL ? ld_or_zero(XP, x, in) : 0.0;
+        for (int m = 0; m < MY; ++m) {
+            y[m] = bload(rY, t + 64 * m);
+            px[m] = PRIMAL ? bload(rP, t + 64 * m) : 0.0;
         }
     }
 
     template <bool PRIMAL>
-    __device__ __forceinline__ void commit(double *area, double *dv, double *Yl, double *Pl, int b, const int (&er)[MG],
-                                           const int (&ec)[MG], const int (&yr)[2], const int (&yc)[2]) const
+    __device__ __forceinline__ void commit(double *area, double *dv, double *Yl, double *Pl, int b, int ng, int nr,
+                                           const Elems<LC<BP>::MG> &E, const Elems<LC<BP>::MY> &Y, int t) const
     {
         using C = WC<BP>;
-        constexpr int P = C::P;
+        constexpr int P = C::P, RP = C::RP;
 #pragma unroll
         for (int m = 0; m < MB; ++m) {
-            if (er[m] < b) {
-                const int rr = er[m], cc = ec[m];
+            if (t + 64 * m < b * b) {
+                const int rr = E.er[m], cc = E.ec[m];
                 area[(C::RD + rr) * P + cc] = (rr == cc) ? 0.0 : d[m];
                 if (rr == cc) dv[rr] = d[m];
                 area[(C::RE + rr) * P + cc] = e[m];
@@ -682,12 +724,12 @@ struct LaneColPre {
         }
 #pragma unroll
         for (int m = 0; m < MG; ++m)
-            if (er[m] < NGM) area[(C::RG + er[m]) * P + ec[m]] = g[m];
+            if (t + 64 * m < ng * b) area[(C::RG + E.er[m]) * P + E.ec[m]] = g[m];
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            if (yr[m] < b) {
-                Yl[yr[m] * C::RP + yc[m]] = y[m];
-                if (PRIMAL) Pl[yr[m] * C::RP + yc[m]] = px[m];
+        for (int m = 0; m < MY; ++m) {
+            if (t + 64 * m < b * nr) {
+                Yl[Y.er[m] * RP + Y.ec[m]] = y[m];
+                if (PRIMAL) Pl[Y.er[m] * RP + Y.ec[m]] = px[m];
             }
         }
     }
@@ -702,10 +744,11 @@ template <int BP, int NR, bool ADJ, bool RED>
 __device__ __forceinline__ void lane_backward(const Args &a, const SysDesc &sd, int k, const WaveLds &L)
 {
     using C = WC<BP>;
-    constexpr int P = C::P, RP = C::RP, BPX = C::BPX, MG = NGM * BP / 64;
+    using G = LC<BP>;
+    constexpr int P = C::P, RP = C::RP, BPX = C::BPX, MY = G::MY;
     const WChain<RED> ch{a, sd, k};
     const int b = sd.b, ng = sd.ng, nr = a.nr, N = sd.N;
-    const long long b2 = (long long)b * b;
+    const long long b2 = (long long)b * b, rb = (long long)b * nr;
     const bool hasF = !RED && k > 1;
     const int len = ch.length();
     const int sep = hasF ? sep_of(sd, k) : 0;
@@ -715,14 +758,10 @@ __device__ __forceinline__ void lane_backward(const Args &a, const SysDesc &sd, 
     double *area = L.pnl;
     double *dv = L.dinv;
     const int tid = threadIdx.x;
-    int er[MG], ec[MG], yr[2], yc[2];
-    {
-        const float invb = 1.0f / (float)b, invr = 1.0f / (float)nr;
-#pragma unroll
-        for (int m = 0; m < MG; ++m) rc_of(tid + 64 * m, b, invb, er[m], ec[m]);
-#pragma unroll
-        for (int m = 0; m < 2; ++m) rc_of(tid + 64 * m, nr, invr, yr[m], yc[m]);
-    }
+    Elems<G::MG> E;
+    Elems<MY> Y;
+    E.init(tid, b, P);
+    Y.init(tid, nr, RP);
     for (int e = tid; e < C::NROW * P; e += 64) area[e] = 0.0;
     for (int e = tid; e < BPX; e += 64) dv[e] = 1.0;
     {
@@ -750,7 +789,7 @@ __device__ __forceinline__ void lane_backward(const Args &a, const SysDesc &sd, 
         }
     }
     LaneColPre<BP, NR, RED> pre;
-    pre.template load<ADJ>(ch, len - 1, hasF, tid, er, ec, yr, yc);
+    pre.template load<ADJ>(ch, len - 1, hasF, tid);
     wave_sync();
     for (int i = len - 1; i >= 0; --i) {
         const int gs = ch.stage(i);
@@ -758,10 +797,10 @@ __device__ __forceinline__ void lane_backward(const Args &a, const SysDesc &sd, 
         const int t = opaque_tid();
         // ---- (1) stage i's blocks and y into the staging area; x of the stage
         // after it leaves; stage i - 1's blocks arrive
-        pre.template commit<ADJ>(area, dv, xc, pc, b, er, ec, yr, yc);
+        pre.template commit<ADJ>(area, dv, xc, pc, b, ng, nr, E, Y, t);
         wave_sync();
-        if (i < len - 1) lstore<2>(X + (long long)ch.stage(i + 1) * b * nr, xn, RP, b, nr, yr, yc);
-        if (i > 0) pre.template load<ADJ>(ch, i - 1, hasF, t, er, ec, yr, yc);
+        if (i < len - 1) lstore<MY>(X + (long long)ch.stage(i + 1) * rb, rb, xn, Y, t);
+        if (i > 0) pre.template load<ADJ>(ch, i - 1, hasF, t);
         // ---- (2) lane c: acc = y_c - (hat E^T x_next)_c - (hat G^T x_g)_c - (hat B x_sep)_c
         const int c = t < BP ? t : 0;
         double acc[NR];
@@ -846,7 +885,7 @@ __device__ __forceinline__ void lane_backward(const Args &a, const SysDesc &sd, 
         double *tmp = xn; xn = xc; xc = tmp;
         tmp = pn; pn = pc; pc = tmp;
     }
-    lstore<2>(X + (long long)ch.stage(0) * b * nr, xn, RP, b, nr, yr, yc);
+    lstore<MY>(X + (long long)ch.stage(0) * rb, rb, xn, Y, tid);
     wave_sync();
 }
 

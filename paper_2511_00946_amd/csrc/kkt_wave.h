@@ -56,7 +56,7 @@ struct WC {
 // LDS layout in doubles.  The backward sweep reuses the panel area for its
 // staged blocks and the next-row area for its vectors.
 struct WaveLdsOff {
-    int pnl, nxt, w, y, dinv, acc_a, acc_q, racc, yg, misc, total;
+    int pnl, nxt, w, y, rn, dinv, acc_a, acc_q, racc, yg, misc, total;
     int xn, xc, xg, xs, pn, pc, pg, ps;
 };
 
@@ -78,6 +78,7 @@ __host__ __device__ constexpr WaveLdsOff wave_lds_offsets()
     }
     o.w = t;     t += C::BPX * C::RP;
     o.y = t;     t += C::BPX * C::RP;
+    o.rn = t;    t += C::NW == 1 ? C::BPX * C::RP : 0;   // single-wave sweeps only
     o.dinv = t;  t += C::BPX;
     o.acc_a = t; t += BP * C::P;
     o.acc_q = t; t += NGM * C::P;
@@ -89,7 +90,7 @@ __host__ __device__ constexpr WaveLdsOff wave_lds_offsets()
 }
 
 struct WaveLds {
-    double *pnl, *nxt, *w, *y, *dinv, *acc_a, *acc_q, *racc, *yg;
+    double *pnl, *nxt, *w, *y, *rn, *dinv, *acc_a, *acc_q, *racc, *yg;
     double *xn, *xc, *xg, *xs, *pn, *pc, *pg, *ps;
     int *misc;
 };
@@ -99,7 +100,8 @@ __device__ __forceinline__ WaveLds make_wave_lds(double *base)
 {
     constexpr WaveLdsOff o = wave_lds_offsets<BP>();
     WaveLds L;
-    L.pnl = base + o.pnl; L.nxt = base + o.nxt; L.w = base + o.w; L.y = base + o.y; L.dinv = base + o.dinv;
+    L.pnl = base + o.pnl; L.nxt = base + o.nxt; L.w = base + o.w; L.y = base + o.y; L.rn = base + o.rn;
+    L.dinv = base + o.dinv;
     L.acc_a = base + o.acc_a; L.acc_q = base + o.acc_q; L.racc = base + o.racc; L.yg = base + o.yg;
     L.xn = base + o.xn; L.xc = base + o.xc; L.xg = base + o.xg; L.xs = base + o.xs;
     L.pn = base + o.pn; L.pc = base + o.pc; L.pg = base + o.pg; L.ps = base + o.ps;
