@@ -50,7 +50,7 @@ class BlockMatrix:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _load is not None:   # module globals are cleared at interpreter exit
             _load().ob_free(h)
             self._h = None
 

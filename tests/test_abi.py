@@ -281,3 +281,17 @@ def test_noalloc_limit_and_host_side_refusals():
     assert L.kkt_factor_solve_noalloc(small._h, None, fake, fake, fake, fake, fake, None) == kkt.KKT_EPOINTER
     assert L.kkt_factor_solve_noalloc(small._h, fake, fake, fake, fake, None, fake, None) == kkt.KKT_EPOINTER
     assert L.kkt_factor_solve_noalloc(None, fake, fake, fake, fake, fake, fake, None) == kkt.KKT_EPOINTER
+
+
+@pytest.mark.parametrize("nrhs", [1, 8])
+def test_every_class_fits_the_lds_of_a_workgroup(nrhs):
+    """Each class's launches ask for at most the 160 KiB of LDS a gfx950 workgroup
+    can hold (a larger request makes the workspace init refuse the plan)."""
+    kkt = _kkt()
+    dims = []
+    for b in (8, 16, 24, 32, 48):
+        dims += [(40, b, 16, 1), (40, b, 16, 3)]
+    plan = kkt.Plan(dims, nrhs=nrhs)
+    for bp, items, nt, lds in plan.classes():
+        assert 0 < lds <= 160 * 1024, (bp, lds)
+        assert nt % 64 == 0 and nt <= 256, (bp, nt)

@@ -384,3 +384,30 @@ def test_symbolic_count_catches_a_dropped_arrow_term():
     i = next(x for x, o in enumerate(ops) if o[0] == "other" and o[1] == "gemm" and o[2] == ng)
     f = sum(flops.std_cost(op, m, n, k) for _, op, m, n, k in ops[:i] + ops[i + 1:])
     assert f != fac + ng * ng * len(seg)
+
+
+@pytest.mark.parametrize("seg", [None, [9, 4, 4, 4]])
+def test_solution_is_invariant_under_symmetric_diagonal_scaling(seg):
+    """Invariant: for S = diag(s_i^(1/2) I_b, s_g^(1/2) I_ng), the solution of
+    (S Psi S) x' = r is x' = S^-1 u with Psi u = S^-1 r.  The blocks of S Psi S are
+    s_i D_i, (s_i s_{i+1})^(1/2) C_i, (s_g s_i)^(1/2) B_i and s_g corner; a dropped or
+    misplaced block scale (or a transposed coupling) breaks the identity by far
+    more than rounding (scales from 1e-4 to 1e4).  Pins the scale handling of
+    every block against the unscaled solve."""
+    rng = np.random.default_rng(21)
+    N, b, ng = 24, 5, 3
+    sy = workloads.draw_system(rng, N, b, ng, nrhs=2, alpha=b, s_C=0.3, s_B=0.3)
+    s = 10.0 ** rng.uniform(-4, 4, size=N)
+    sg = 10.0 ** rng.uniform(-4, 4)
+    h = np.sqrt(s)
+    D = sy.D * s[:, None, None]
+    C = sy.C * (h[1:] * h[:-1])[:, None, None]
+    B = sy.B * (np.sqrt(sg) * h)[:, None, None]
+    corner = sy.corner * sg
+    S = np.concatenate([np.repeat(h, b), np.full(ng, np.sqrt(sg))])
+    xs = kkt.solve(D, C, B, corner, sy.r, seg)
+    u = kkt.solve(sy.D, sy.C, sy.B, sy.corner, sy.r / S[:, None], seg)
+    assert np.max(np.abs(S[:, None] * xs - u)) <= 1e-12 * np.max(np.abs(u))
+    # the check sees a transposed coupling block (the matrix stays definite)
+    xb = kkt.solve(D, np.swapaxes(C, 1, 2).copy(), B, corner, sy.r, seg)
+    assert np.max(np.abs(S[:, None] * xb - u)) > 1e-6 * np.max(np.abs(u))
