@@ -223,3 +223,58 @@ def adjoint(D, C, B, corner, x, gbar, seg_lens=None):
         dB = np.zeros((N, 0, b))
         dcorner = np.zeros((0, 0))
     return lam, dD, dC, dB, dcorner
+
+
+# ---------------------------------------------------------------- non-uniform stage sizes
+# Sec. 2 (Eqs. 1, 3) lets stage i carry its own size n_i: D[i] is n_i x n_i,
+# C[i] = Psi_{i+1,i} is n_{i+1} x n_i, B[i] is ng x n_i, r stacks the stage parts
+# (n_0 + ... + n_{N-1}) and then g.  The solution has a plain definition, so the
+# oracle is the block Cholesky of the natural-order matrix with those block sizes.
+
+
+def ragged_offsets(sizes):
+    return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+
+
+def solve_ragged(D, C, B, corner, r):
+    """x with Psi x = r for lists of blocks with per-stage sizes (natural order)."""
+    N = len(D)
+    sizes = [int(np.asarray(d).shape[0]) for d in D]
+    ng = 0 if corner is None else int(np.asarray(corner).shape[0])
+    M = BlockMatrix(sizes + ([ng] if ng else []))
+    for i in range(N):
+        M.set(i, i, sym(np.asarray(D[i], dtype=np.float64)))
+    for i in range(N - 1):
+        M.set(i + 1, i, np.asarray(C[i], dtype=np.float64))
+    if ng:
+        for i in range(N):
+            M.set(N, i, np.asarray(B[i], dtype=np.float64))
+        M.set(N, N, sym(np.asarray(corner, dtype=np.float64)))
+    rc = M.cholesky()
+    if rc != 0:
+        raise FloatingPointError("matrix is not positive definite (block %d)" % rc)
+    return M.solve(np.asarray(r, dtype=np.float64))
+
+
+def matvec_ragged(D, C, B, corner, x):
+    """Psi x for lists of blocks with per-stage sizes (symmetric parametrisation)."""
+    N = len(D)
+    sizes = [int(np.asarray(d).shape[0]) for d in D]
+    off = ragged_offsets(sizes)
+    ng = 0 if corner is None else int(np.asarray(corner).shape[0])
+    x = np.asarray(x, dtype=np.float64)
+    X = x[:, None] if x.ndim == 1 else x
+    Y = np.zeros_like(X)
+    for i in range(N):
+        Y[off[i]:off[i + 1]] += sym(np.asarray(D[i])) @ X[off[i]:off[i + 1]]
+        if i + 1 < N:
+            Ci = np.asarray(C[i])
+            Y[off[i + 1]:off[i + 2]] += Ci @ X[off[i]:off[i + 1]]
+            Y[off[i]:off[i + 1]] += Ci.T @ X[off[i + 1]:off[i + 2]]
+        if ng:
+            Bi = np.asarray(B[i])
+            Y[off[i]:off[i + 1]] += Bi.T @ X[off[N]:]
+            Y[off[N]:] += Bi @ X[off[i]:off[i + 1]]
+    if ng:
+        Y[off[N]:] += sym(np.asarray(corner)) @ X[off[N]:]
+    return Y[:, 0] if x.ndim == 1 else Y

@@ -411,3 +411,78 @@ def test_solution_is_invariant_under_symmetric_diagonal_scaling(seg):
     # the check sees a transposed coupling block (the matrix stays definite)
     xb = kkt.solve(D, np.swapaxes(C, 1, 2).copy(), B, corner, sy.r, seg)
     assert np.max(np.abs(S[:, None] * xb - u)) > 1e-6 * np.max(np.abs(u))
+
+
+def _ragged_system(rng, sizes, ng, nrhs):
+    N = len(sizes)
+    D = []
+    for n in sizes:
+        M = rng.standard_normal((n, n))
+        D.append(M @ M.T + n * np.eye(n) + np.eye(n))
+    C = [0.2 * rng.standard_normal((sizes[i + 1], sizes[i])) for i in range(N - 1)]
+    B = [0.2 * rng.standard_normal((ng, n)) for n in sizes]
+    R = rng.standard_normal((ng, ng))
+    corner = R @ R.T + (ng + N) * np.eye(ng) if ng else None
+    r = rng.standard_normal((int(sum(sizes)) + ng, nrhs))
+    return D, C, B, corner, r
+
+
+def _dense_ragged(D, C, B, corner):
+    sizes = [d.shape[0] for d in D]
+    off = kkt.ragged_offsets(sizes)
+    N = len(D)
+    ng = 0 if corner is None else corner.shape[0]
+    A = np.zeros((off[N] + ng, off[N] + ng))
+    for i in range(N):
+        A[off[i]:off[i + 1], off[i]:off[i + 1]] = 0.5 * (D[i] + D[i].T)
+        if i + 1 < N:
+            A[off[i + 1]:off[i + 2], off[i]:off[i + 1]] = C[i]
+            A[off[i]:off[i + 1], off[i + 1]:off[i + 2]] = C[i].T
+        if ng:
+            A[off[N]:, off[i]:off[i + 1]] = B[i]
+            A[off[i]:off[i + 1], off[N]:] = B[i].T
+    if ng:
+        A[off[N]:, off[N]:] = 0.5 * (corner + corner.T)
+    return A
+
+
+@pytest.mark.parametrize("sizes,ng", [([3, 1, 4, 2, 5], 2), ([1, 1, 1], 0), ([6, 2, 6, 3], 3), ([2], 1)])
+def test_ragged_solve_matches_lapack(sizes, ng):
+    """The non-uniform oracle against LAPACK on the assembled dense matrix (its
+    definition), and its mat-vec against the dense product."""
+    rng = np.random.default_rng(31)
+    D, C, B, corner, r = _ragged_system(rng, sizes, ng, 2)
+    A = _dense_ragged(D, C, B, corner)
+    x = kkt.solve_ragged(D, C, B, corner, r)
+    assert np.allclose(x, np.linalg.solve(A, r), rtol=1e-12, atol=1e-12)
+    assert np.allclose(kkt.matvec_ragged(D, C, B, corner, x), A @ x, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("seg", [None, [4, 2, 2]])
+def test_ragged_equals_identity_padded_uniform_solve(seg):
+    """Padding every stage to b = max n_i with the identity on the padded diagonal
+    and zeros in the couplings is exact: the uniform solve of the padded system
+    (any segmentation), restricted to the real entries, is the ragged solution."""
+    rng = np.random.default_rng(32)
+    sizes, ng = [3, 5, 1, 4, 5, 2, 3, 4, 2, 5], 3
+    D, C, B, corner, r = _ragged_system(rng, sizes, ng, 2)
+    N, b = len(sizes), max(sizes)
+    Dp = np.zeros((N, b, b))
+    Cp = np.zeros((N - 1, b, b))
+    Bp = np.zeros((N, ng, b))
+    rp = np.zeros((N * b + ng, 2))
+    off = kkt.ragged_offsets(sizes)
+    for i, n in enumerate(sizes):
+        Dp[i] = np.eye(b)
+        Dp[i, :n, :n] = D[i]
+        Bp[i, :, :n] = B[i]
+        rp[i * b:i * b + n] = r[off[i]:off[i + 1]]
+        if i + 1 < N:
+            Cp[i, :sizes[i + 1], :n] = C[i]
+    rp[N * b:] = r[off[N]:]
+    xp = kkt.solve(Dp, Cp, Bp, corner, rp, seg)
+    x = kkt.solve_ragged(D, C, B, corner, r)
+    back = np.concatenate([xp[i * b:i * b + n] for i, n in enumerate(sizes)] + [xp[N * b:]])
+    assert np.allclose(back, x, rtol=1e-12, atol=1e-13)
+    for i, n in enumerate(sizes):
+        assert np.all(np.abs(xp[i * b + n:(i + 1) * b]) < 1e-14)
