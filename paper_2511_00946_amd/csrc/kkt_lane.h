@@ -249,8 +249,10 @@ __device__ __forceinline__ int lane_factor(const Args &a, const SysDesc &sd, int
         const int rr = e / P, cc = e - rr * P;
         cb[e] = (rr < BP && rr == cc && rr >= b) ? 1.0 : 0.0;
     }
+    // rhs staging: the commits write the rows of the block only, so the padded rows
+    // (read by the padded D lanes) must start as zeros
     if (FWD)
-        for (int e = tid; e < C::BPX * RP; e += 64) L.w[e] = 0.0;
+        for (int e = tid; e < C::BPX * RP; e += 64) L.w[e] = L.rn[e] = 0.0;
     LanePre<BP, NR, RED> pre;
     pre.load(ch, 0, FWD, tid);
     wave_sync();
@@ -588,7 +590,9 @@ __device__ __forceinline__ void lane_forward(const Args &a, const SysDesc &sd, i
     Y.init(tid, nr, RP);
     for (int e = tid; e < NROW * P; e += 64) area[e] = 0.0;
     for (int e = tid; e < C::BPX; e += 64) dv[e] = 1.0;
-    for (int e = tid; e < C::BPX * RP; e += 64) L.w[e] = 0.0;
+    // rhs staging: the commits write the rows of the block only, so the padded rows
+    // (read by the padded D lanes) must start as zeros
+    for (int e = tid; e < C::BPX * RP; e += 64) L.w[e] = L.rn[e] = 0.0;
     double w[NR];
     {
         const int r = tid - C::TF;
