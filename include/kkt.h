@@ -244,6 +244,37 @@ int kkt_plan_set_class_events(kkt_plan *plan, int32_t c, hipEvent_t start, hipEv
 
 const char *kkt_status_string(int status);
 
+/* ---- Non-uniform stage sizes (Sec. 2, Eqs. 1 and 3: stage i of a system has its
+ * own size n_i; the method of Sec. 3 assumes one size b).  A system with sizes
+ * n_0..n_{N-1} is solved by the plan of the same system with b >= max n_i: each
+ * stage is embedded in b x b with the identity on the padded diagonal and zeros in
+ * the padded rows and columns of its coupling and arrow blocks, which decouples the
+ * padded variables (their solution is 0) and leaves the real ones unchanged (exact).
+ * Non-uniform pools, per system, system after system, row-major FP64:
+ *   D_i [n_i, n_i], C_i = Psi_{i+1,i} [n_{i+1}, n_i] (i < N-1), B_i [ng, n_i],
+ *   corner [ng, ng], rhs [(n_0 + ... + n_{N-1} + ng), nrhs] (stage parts, then g). */
+typedef struct kkt_ragged kkt_ragged;   /* opaque: per-stage copy tables on the device */
+
+/* stage_sizes: host array, the N sizes of system 0, then of system 1, ... (plan
+ * order); each 1 <= n_i <= b of its system.  Allocates the device tables on the
+ * current device (one hipMalloc) and synchronises.  KKT_EDIMS for a size out of
+ * range (checked before any device call).  The tables hold offsets only: the plan
+ * may be destroyed first. */
+int kkt_ragged_create(const kkt_plan *plan, const int32_t *stage_sizes, kkt_ragged **out);
+int kkt_ragged_destroy(kkt_ragged *ragged);
+/* Lengths (doubles) of the non-uniform pools. */
+int kkt_ragged_lengths(const kkt_ragged *ragged, int64_t *D_len, int64_t *C_len, int64_t *B_len,
+                       int64_t *corner_len, int64_t *rhs_len);
+/* Non-uniform pools (device, read) -> the plan's padded pools (device, written
+ * entirely, padding included); enqueued on stream.  Pointers 8-byte aligned; the
+ * padded pools are the plan's D/C/B/corner/rhs pools. */
+int kkt_ragged_pad(const kkt_ragged *ragged, const double *D, const double *C, const double *B,
+                   const double *corner, const double *rhs, double *Dp, double *Cp, double *Bp,
+                   double *cornerp, double *rhsp, hipStream_t stream);
+/* The real entries of a padded solution (device, the plan's rhs layout) -> x in the
+ * non-uniform rhs layout (device); enqueued on stream. */
+int kkt_ragged_unpad(const kkt_ragged *ragged, const double *xp, double *x, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -97,6 +97,14 @@ def lib():
         L.kkt_plan_set_class_events.argtypes = [vp, i32, vp, vp]
         L.kkt_plan_class_kind.argtypes = [vp, i32, ctypes.POINTER(i32)]
         L.kkt_workspace_error.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
+        L.kkt_ragged_create.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(vp)]
+        L.kkt_ragged_destroy.argtypes = [vp]
+        L.kkt_ragged_lengths.argtypes = [vp] + [ctypes.POINTER(i64)] * 5
+        L.kkt_ragged_pad.argtypes = [vp] * 11 + [vp]
+        L.kkt_ragged_unpad.argtypes = [vp, vp, vp, vp]
+        for name in ("kkt_ragged_create", "kkt_ragged_destroy", "kkt_ragged_lengths", "kkt_ragged_pad",
+                     "kkt_ragged_unpad"):
+            getattr(L, name).restype = ctypes.c_int
         L.kkt_status_string.restype = ctypes.c_char_p
         L.kkt_status_string.argtypes = [ctypes.c_int]
         for name in ("kkt_plan_create", "kkt_plan_create_tuned", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
@@ -110,7 +118,8 @@ def lib():
 EXPORTED = ("kkt_plan_create", "kkt_plan_create_tuned", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
             "kkt_plan_factor_offset", "kkt_workspace_init", "kkt_factor", "kkt_solve",
             "kkt_factor_solve", "kkt_solve_adjoint", "kkt_status_string", "kkt_plan_class_info",
-            "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error", "kkt_factor_solve_noalloc")
+            "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error", "kkt_factor_solve_noalloc",
+            "kkt_ragged_create", "kkt_ragged_destroy", "kkt_ragged_lengths", "kkt_ragged_pad", "kkt_ragged_unpad")
 
 # bytes of the no-allocation entry point's device array (plans above it are refused)
 NOALLOC_MAX_BYTES = 32 << 20
@@ -315,6 +324,39 @@ class Plan:
     def segment_lengths(self, s):
         lay = self.layouts[s]
         return [lay.N1] + [lay.Nk] * (lay.p - 1)
+
+
+class Ragged:
+    """Non-uniform stage sizes on top of a plan whose systems have b >= every n_i:
+    ``sizes`` lists, per system of the plan, its N stage sizes.  pad() writes the
+    plan's padded pools from the non-uniform ones, unpad() the real entries of a
+    padded solution back (both on the device, in the library's kernels)."""
+
+    def __init__(self, plan, sizes):
+        flat = [int(n) for per in sizes for n in per]
+        arr = (ctypes.c_int32 * max(1, len(flat)))(*flat)
+        h = ctypes.c_void_p()
+        _check(lib().kkt_ragged_create(plan._h, arr, ctypes.byref(h)), "kkt_ragged_create")
+        self._h = h
+        self.plan = plan
+        lens = [ctypes.c_int64() for _ in range(5)]
+        _check(lib().kkt_ragged_lengths(h, *[ctypes.byref(x) for x in lens]), "kkt_ragged_lengths")
+        self.lengths = dict(zip(("D", "C", "B", "corner", "rhs"), (int(x.value) for x in lens)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.kkt_ragged_destroy(h)
+            self._h = None
+
+    def pad(self, src, dst, stream=None):
+        """src: non-uniform pools {D, C, B, corner, r}; dst: the plan's pools (device)."""
+        _check(lib().kkt_ragged_pad(self._h, _ptr(src["D"]), _ptr(src["C"]), _ptr(src["B"]), _ptr(src["corner"]),
+                                    _ptr(src["r"]), _ptr(dst["D"]), _ptr(dst["C"]), _ptr(dst["B"]),
+                                    _ptr(dst["corner"]), _ptr(dst["r"]), _stream(stream)), "kkt_ragged_pad")
+
+    def unpad(self, xp, x, stream=None):
+        _check(lib().kkt_ragged_unpad(self._h, _ptr(xp), _ptr(x), _stream(stream)), "kkt_ragged_unpad")
 
 
 def pack_to_device(pools, device="cuda"):

@@ -133,3 +133,38 @@ def pack(systems):
     if systems and systems[0].w is not None:
         pools["w"] = cat([s.w for s in systems])
     return pools
+
+
+@dataclass
+class RaggedSystem:
+    """A system with a size n_i per stage (lists of blocks)."""
+    sizes: list
+    ng: int
+    D: list
+    C: list
+    B: list
+    corner: np.ndarray
+    r: np.ndarray
+
+
+def draw_ragged_system(rng, sizes, ng, nrhs=1, s_C=0.05, s_B=0.05):
+    """One non-uniform system by the recipe above, stage by stage (alpha = n_i)."""
+    N = len(sizes)
+    D = []
+    for n in sizes:
+        M = rng.standard_normal((n, n))
+        D.append(M @ M.T + n * np.eye(n))
+    C = [s_C * rng.standard_normal((sizes[i + 1], sizes[i])) for i in range(N - 1)]
+    B = [s_B * rng.standard_normal((ng, n)) for n in sizes]
+    R = rng.standard_normal((ng, ng))
+    corner = R @ R.T + (ng + N) * np.eye(ng)
+    r = rng.standard_normal((int(sum(sizes)) + ng, nrhs))
+    return RaggedSystem(list(sizes), ng, D, C, B, corner, r)
+
+
+def pack_ragged(systems):
+    """Non-uniform pools, system after system (the layout of kkt_ragged_pad)."""
+    cat = lambda xs: np.concatenate([np.ascontiguousarray(x, dtype=np.float64).ravel() for x in xs]) if xs else np.zeros(0)
+    return dict(D=cat([d for s in systems for d in s.D]), C=cat([c for s in systems for c in s.C]),
+                B=cat([b for s in systems for b in s.B]), corner=cat([s.corner for s in systems]),
+                r=cat([s.r for s in systems]))

@@ -295,3 +295,19 @@ def test_every_class_fits_the_lds_of_a_workgroup(nrhs):
     for bp, items, nt, lds in plan.classes():
         assert 0 < lds <= 160 * 1024, (bp, lds)
         assert nt % 64 == 0 and nt <= 256, (bp, nt)
+
+
+def test_ragged_refuses_sizes_out_of_range_on_the_host():
+    """kkt_ragged_create checks every stage size against its system's block size
+    before any device call (0 and b + 1 are refused), and null pointers."""
+    kkt = _kkt()
+    L = kkt.lib()
+    plan = kkt.Plan([(4, 6, 2, 1), (3, 8, 0, 1)])
+    h = ctypes.c_void_p()
+    for bad in ([3, 6, 0, 2, 8, 8, 8], [3, 6, 7, 2, 8, 8, 8], [3, 6, 6, 2, 8, 9, 1]):
+        arr = (ctypes.c_int32 * len(bad))(*bad)
+        assert L.kkt_ragged_create(plan._h, arr, ctypes.byref(h)) == kkt.KKT_EDIMS
+    arr = (ctypes.c_int32 * 7)(3, 6, 6, 2, 8, 8, 1)
+    assert L.kkt_ragged_create(None, arr, ctypes.byref(h)) == kkt.KKT_EPOINTER
+    assert L.kkt_ragged_create(plan._h, None, ctypes.byref(h)) == kkt.KKT_EPOINTER
+    assert L.kkt_ragged_pad(None, *([None] * 10), None) == kkt.KKT_EPOINTER
