@@ -16,6 +16,11 @@ lists the segment stages first (segment 1, then 2, ...), then the separators
 (``blockchol``); p = 1 is the sequential method the paper compares against
 (Sec. 3.3, O_seq).
 
+Recursive segmentation (the multi-level method that Sec. 5 names as future
+work): the separators' reduced system is again a block-tridiagonal arrow chain
+(``reduced_system``), so it is segmented in turn; ``nested_order`` gives the
+resulting elimination order and ``KKTFactor(..., nest=...)`` its unique factor.
+
 Readings where the paper is silent:
   * failure: ``info`` is the 1-based natural stage index of the first diagonal
     block, in elimination order, whose pivot is not positive and finite; N + 1
@@ -59,6 +64,72 @@ def elimination_order(N, seg_lens):
     return [i for seg in segments for i in seg] + separators
 
 
+def nested_order(N, levels):
+    """Stage order of recursive (multi-level) segmentation.
+
+    Sec. 3.1's permutation eliminates the segment stages first and leaves the
+    separators, whose reduced system (Eqs. 8, 9) is again block tridiagonal with
+    the same arrow.  Segmenting that chain the same way, and so on, is the
+    multi-level method that Sec. 5 names as future work.  ``levels[0]`` are the
+    segment lengths of the whole chain, ``levels[1]`` those of the chain of its
+    p - 1 separators (taken in natural order), and so on; the separators left by
+    the last level close the order (g is last).  One level gives
+    ``elimination_order``."""
+    chain = list(range(N))
+    order = []
+    for seg_lens in levels:
+        segments, separators = stage_layout(len(chain), seg_lens)
+        order += [chain[i] for seg in segments for i in seg]
+        chain = [chain[j] for j in separators]
+    return order + chain
+
+
+def reduced_system(D, C, B, corner, seg_lens, r=None):
+    """The system left on the separators and g once the segment stages of
+    ``seg_lens`` are eliminated (Sec. 3.2, Eqs. 8, 9), from its definition: the
+    Schur complement S = Psi_SS - Psi_SI Psi_II^{-1} Psi_IS of the assembled matrix
+    (I: segment stages, S: separators in natural order, then g) and the reduced
+    rhs r_S - Psi_SI Psi_II^{-1} r_I.
+
+    Returned as block arrays of a system with p - 1 stages:
+    (D', C', B', corner', r') with D'_j = S_jj, C'_j = S_{j+1,j}, B'_j = S_gj,
+    corner' = S_gg (r' is None without r)."""
+    D = np.asarray(D, dtype=np.float64)
+    N, b, ng = _dims(D, B)
+    segments, separators = stage_layout(N, seg_lens)
+    if not separators:
+        raise ValueError("one segment leaves no reduced system")
+    n = N * b + ng
+    K = np.zeros((n, n))
+    Cm = np.asarray(C, dtype=np.float64).reshape(-1, b, b)
+    for i in range(N):
+        K[i * b:(i + 1) * b, i * b:(i + 1) * b] = sym(D[i])
+    for i in range(N - 1):
+        K[(i + 1) * b:(i + 2) * b, i * b:(i + 1) * b] = Cm[i]
+        K[i * b:(i + 1) * b, (i + 1) * b:(i + 2) * b] = Cm[i].T
+    if ng:
+        Bm = np.asarray(B, dtype=np.float64)
+        for i in range(N):
+            K[N * b:, i * b:(i + 1) * b] = Bm[i]
+            K[i * b:(i + 1) * b, N * b:] = Bm[i].T
+        K[N * b:, N * b:] = sym(np.asarray(corner, dtype=np.float64))
+    I = [s * b + t for seg in segments for s in seg for t in range(b)]
+    S = [s * b + t for s in separators for t in range(b)] + [N * b + t for t in range(ng)]
+    KII, KSI = K[np.ix_(I, I)], K[np.ix_(S, I)]
+    Smat = K[np.ix_(S, S)] - KSI @ np.linalg.solve(KII, KSI.T)
+    M = len(separators)
+    Dr = np.stack([Smat[j * b:(j + 1) * b, j * b:(j + 1) * b] for j in range(M)])
+    Cr = np.stack([Smat[(j + 1) * b:(j + 2) * b, j * b:(j + 1) * b] for j in range(M - 1)]) \
+        if M > 1 else np.zeros((0, b, b))
+    Br = np.stack([Smat[M * b:, j * b:(j + 1) * b] for j in range(M)]) if ng else None
+    cr = Smat[M * b:, M * b:] if ng else None
+    rr = None
+    if r is not None:
+        R = np.asarray(r, dtype=np.float64)
+        rr = R[S] - KSI @ np.linalg.solve(KII, R[I])
+    return Dr, Cr, Br, cr, rr
+
+
 def _dims(D, B):
     D = np.asarray(D)
     N, b = D.shape[0], D.shape[1]
@@ -67,9 +138,11 @@ def _dims(D, B):
 
 
 class KKTFactor:
-    """hat L = chol(P Psi P^T) for the order given by ``seg_lens`` (default: p = 1)."""
+    """hat L = chol(P Psi P^T) for the order given by ``seg_lens`` (default: p = 1);
+    ``nest``: segment lengths of the reduced chain at each deeper level
+    (``nested_order``), None for the single-level method."""
 
-    def __init__(self, D, C, B, corner, seg_lens=None, factor=True):
+    def __init__(self, D, C, B, corner, seg_lens=None, factor=True, nest=None):
         D = np.asarray(D, dtype=np.float64)
         C = np.asarray(C, dtype=np.float64).reshape(-1, D.shape[1], D.shape[1])
         N, b, ng = _dims(D, B)
@@ -77,7 +150,8 @@ class KKTFactor:
             seg_lens = [N]
         self.N, self.b, self.ng = N, b, ng
         self.seg_lens = list(seg_lens)
-        self.order = elimination_order(N, seg_lens)
+        self.nest = [list(v) for v in (nest or [])]
+        self.order = nested_order(N, [self.seg_lens] + self.nest)
         self.pos = {s: i for i, s in enumerate(self.order)}
         if ng:
             self.pos["g"] = N
@@ -155,8 +229,8 @@ class KKTFactor:
         return float(tot)
 
 
-def solve(D, C, B, corner, r, seg_lens=None):
-    return KKTFactor(D, C, B, corner, seg_lens).solve(r)
+def solve(D, C, B, corner, r, seg_lens=None, nest=None):
+    return KKTFactor(D, C, B, corner, seg_lens, nest=nest).solve(r)
 
 
 def matvec(D, C, B, corner, x):

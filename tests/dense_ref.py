@@ -46,3 +46,27 @@ def scalar_permutation(seg_lens, b, ng):
 def dense_factor(K, perm):
     """numpy (LAPACK) Cholesky of P K P^T."""
     return np.linalg.cholesky(K[np.ix_(perm, perm)])
+
+
+def nested_stage_order(N, levels):
+    """Recursive segmentation, written as a recursion over the chain: the stages
+    inside the segments of levels[0], then the same rule applied to the chain of
+    the separators with levels[1:], the last separators at the end."""
+    def rec(chain, lv):
+        if not lv:
+            return list(chain)
+        inner, seps, pos = [], [], 0
+        for k, nk in enumerate(lv[0]):
+            if k:
+                seps.append(chain[pos])
+                pos += 1
+            inner.extend(chain[pos:pos + nk])
+            pos += nk
+        assert pos == len(chain), "segment lengths do not tile the chain"
+        return inner + rec(seps, lv[1:])
+    return rec(list(range(N)), list(levels))
+
+
+def nested_scalar_permutation(N, levels, b, ng):
+    order = nested_stage_order(N, levels)
+    return np.asarray([s * b + t for s in order for t in range(b)] + [N * b + t for t in range(ng)])

@@ -486,3 +486,112 @@ def test_ragged_equals_identity_padded_uniform_solve(seg):
     assert np.allclose(back, x, rtol=1e-12, atol=1e-13)
     for i, n in enumerate(sizes):
         assert np.all(np.abs(xp[i * b + n:(i + 1) * b]) < 1e-14)
+
+
+# ---------------------------------------------------------------- recursive segmentation
+def test_nested_order_hand_examples():
+    """Two and three levels, written out by hand."""
+    assert kkt.nested_order(15, [[3, 3, 3, 3], [1, 1]]) == [0, 1, 2, 4, 5, 6, 8, 9, 10, 12, 13, 14, 3, 11, 7]
+    lev0 = [i for i in range(31) if i % 4 != 3]
+    assert kkt.nested_order(31, [[3] * 8, [1] * 4, [1, 1]]) == lev0 + [3, 11, 19, 27, 7, 23, 15]
+    assert kkt.nested_order(11, [[3, 3, 3]]) == kkt.elimination_order(11, [3, 3, 3])
+    # a one-segment level eliminates the whole chain of separators in order
+    assert kkt.nested_order(11, [[3, 3, 3], [2]]) == kkt.elimination_order(11, [3, 3, 3])
+
+
+NEST_CASES = [
+    # (N, b, ng, seg_lens, nest)
+    (15, 2, 2, [3, 3, 3, 3], [[1, 1]]),
+    (19, 3, 0, [2, 2, 2, 2, 2, 2, 1], [[2, 1, 1]]),
+    (31, 2, 3, [3] * 8, [[1] * 4, [1, 1]]),
+    (23, 3, 1, [4, 3, 3, 3, 3, 2], [[2, 2]]),
+]
+
+
+def _dense_blocks_check(f, N, b, ng, levels, s):
+    K = dense_ref.assemble(s.D, s.C, s.B, s.corner)
+    L = dense_ref.dense_factor(K, dense_ref.nested_scalar_permutation(N, levels, b, ng))
+    order = dense_ref.nested_stage_order(N, levels) + (["g"] if ng else [])
+    size = {o: (ng if o == "g" else b) for o in order}
+    start, o0 = {}, 0
+    for o in order:
+        start[o] = o0
+        o0 += size[o]
+    for i, ri in enumerate(order):
+        for cj in order[: i + 1]:
+            ref = L[start[ri]:start[ri] + size[ri], start[cj]:start[cj] + size[cj]]
+            got = f.block(ri, cj)
+            if got is None:
+                assert np.max(np.abs(ref), initial=0.0) < 1e-15, (ri, cj)
+            else:
+                np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13 * max(1.0, np.max(np.abs(ref))))
+
+
+@pytest.mark.parametrize("N,b,ng,seg,nest", NEST_CASES)
+def test_nested_factor_equals_dense_cholesky(N, b, ng, seg, nest):
+    """Every block of the multi-level factor equals LAPACK's Cholesky of the matrix
+    permuted by an independently written nested order."""
+    s = tiny_system(500 + N + b, N, b, ng)
+    f = kkt.KKTFactor(s.D, s.C, s.B, s.corner, seg, nest=nest)
+    assert f.info == 0
+    _dense_blocks_check(f, N, b, ng, [seg] + nest, s)
+
+
+@pytest.mark.parametrize("N,b,ng,seg,nest", NEST_CASES)
+def test_nested_solve_equals_dense_solve(N, b, ng, seg, nest):
+    s = tiny_system(600 + N + b, N, b, ng, nrhs=2)
+    x = kkt.solve(s.D, s.C, s.B, s.corner, s.r, seg, nest=nest)
+    K = dense_ref.assemble(s.D, s.C, s.B, s.corner)
+    np.testing.assert_allclose(x, np.linalg.solve(K, s.r), rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("N,b,ng,seg,nest", NEST_CASES)
+def test_reduced_system_is_a_chain_and_carries_the_nested_factor(N, b, ng, seg, nest):
+    """The Schur complement on the separators couples only neighbouring separators
+    (a block-tridiagonal arrow chain); its solution is the separators' part of x;
+    and segmenting it gives exactly the separator blocks of the multi-level factor."""
+    s = tiny_system(700 + N + b, N, b, ng, nrhs=2)
+    # structure, from the dense matrix: separators two apart are not coupled
+    K = dense_ref.assemble(s.D, s.C, s.B, s.corner)
+    _, seps = kkt.stage_layout(N, seg)
+    I = [st * b + t for st in range(N) if st not in seps for t in range(b)]
+    S = [st * b + t for st in seps for t in range(b)] + [N * b + t for t in range(ng)]
+    Sm = K[np.ix_(S, S)] - K[np.ix_(S, I)] @ np.linalg.solve(K[np.ix_(I, I)], K[np.ix_(I, S)])
+    M = len(seps)
+    for i in range(M):
+        for j in range(i + 2, M):
+            assert np.max(np.abs(Sm[j * b:(j + 1) * b, i * b:(i + 1) * b])) < 1e-13
+    Dr, Cr, Br, cr, rr = kkt.reduced_system(s.D, s.C, s.B, s.corner, seg, s.r)
+    assert Dr.shape == (M, b, b) and Cr.shape == (M - 1, b, b)
+    np.testing.assert_allclose(Dr, np.swapaxes(Dr, 1, 2), rtol=0, atol=1e-13)
+    # the reduced solve gives the separators and g of the full solution
+    x = np.linalg.solve(K, s.r)
+    xr = kkt.solve(Dr, Cr, Br, cr, rr, None)
+    xs = np.concatenate([x[st * b:(st + 1) * b] for st in seps] + ([x[N * b:]] if ng else []))
+    np.testing.assert_allclose(xr, xs, rtol=1e-11, atol=1e-12)
+    # the nested factor's separator blocks are the factor of the segmented chain
+    f = kkt.KKTFactor(s.D, s.C, s.B, s.corner, seg, nest=nest)
+    fr = kkt.KKTFactor(Dr, Cr, Br, cr, nest[0], nest=nest[1:])
+    lab = {j: st for j, st in enumerate(seps)}
+    keys = list(range(M)) + (["g"] if ng else [])
+    for i, ri in enumerate(fr.order + (["g"] if ng else [])):
+        for cj in (fr.order + (["g"] if ng else []))[: i + 1]:
+            got = fr.block(ri, cj)
+            ref = f.block(lab.get(ri, ri), lab.get(cj, cj))
+            if got is None:
+                assert ref is None or np.max(np.abs(ref)) < 1e-14
+            else:
+                np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * max(1.0, np.max(np.abs(ref))))
+    assert len(keys) == M + (1 if ng else 0)
+
+
+def test_nested_failure_is_first_in_the_nested_order():
+    """Two indefinite separator blocks: the one eliminated first under the nested
+    order is reported, which differs from the single-level order's choice."""
+    N, b = 15, 2
+    s = tiny_system(31, N, b, 2)
+    D = s.D.copy()
+    D[7] = -np.eye(b)    # level-1 separator: eliminated last
+    D[11] = -np.eye(b)   # level-1 segment stage: eliminated before it
+    assert kkt.KKTFactor(D, s.C, s.B, s.corner, [3, 3, 3, 3]).info == 8
+    assert kkt.KKTFactor(D, s.C, s.B, s.corner, [3, 3, 3, 3], nest=[[1, 1]]).info == 12
