@@ -142,14 +142,57 @@ int kkt_plan_create(kkt_plan **plan, int32_t num_systems, const kkt_dims *dims, 
  * smallest T that the resulting summed work also meets is kept (systems of one
  * class and length get equal p).  Fixed p are honoured and enter the estimate.
  * The default model follows the flop ratios of Table 1 (7/3, 19/3 and 10/3 b^3
- * per stage); a measured one (paper_2511_00946_amd/autotune.py) can be passed. */
+ * per stage, t_level = 64 t_first); a measured one
+ * (paper_2511_00946_amd/autotune.py) can be passed. */
 typedef struct {
     double t_first[KKT_NUM_CLASSES], t_fill[KKT_NUM_CLASSES], t_red[KKT_NUM_CLASSES], t_item[KKT_NUM_CLASSES];
     double workers[KKT_NUM_CLASSES], workers_seg[KKT_NUM_CLASSES];
+    double t_level[KKT_NUM_CLASSES];   /* fixed cost of one more level of recursive
+                                          segmentation (its extra launches), below */
 } kkt_cost_model;
 
 int kkt_plan_create_tuned(kkt_plan **plan, int32_t num_systems, const kkt_dims *dims, int32_t nrhs,
                           const kkt_cost_model *model);
+
+/* Recursive (multi-level) segmentation.  Once the segment stages of a system are
+ * eliminated, its p - 1 separators carry a reduced system (Sec. 3.2, Eqs. 8-9:
+ * diagonal blocks hat A_k, couplings hat H_k between neighbouring separators,
+ * arrow blocks hat Q_k, the corner's partial sums) that is itself a
+ * block-tridiagonal arrow chain of the same b and ng.  Algorithms 1-3 sweep it
+ * sequentially; here it can instead be segmented in turn, and its own reduced
+ * chain again, which bounds the sequential depth by the number of levels (the
+ * O(log N) method that Sec. 5 names as future work).  p[0] is the segment count
+ * of the system's reduced chain, p[1] that of the reduced chain of that chain,
+ * and so on; a 0 or 1 ends the recursion (that chain is swept sequentially).
+ * Level l needs a chain of M >= 2 p[l] - 1 stages (M = p - 1 for level 0,
+ * p[l-1] - 1 below); every level's segments follow Eq. 13's balance.  The
+ * factor of a nested system is that of the elimination order the recursion
+ * defines: segment stages of the whole chain, then those of the reduced chain,
+ * and so on; the separators' blocks live with the reduced systems
+ * (kkt_plan_reduced), and info names the first failing block in that order. */
+#define KKT_MAX_LEVELS 4
+typedef struct {
+    int32_t p[KKT_MAX_LEVELS];
+} kkt_nest;
+
+/* As kkt_plan_create_tuned (model may be NULL: the default model), with nest[s]
+ * the recursion of system s (nest may be NULL: none).  nest is read for systems
+ * with a given p; for systems with p = 0 the cost model chooses p and the
+ * recursion together (a reduced chain of M stages is segmented when the longest
+ * path through its levels, t_level each, beats M t_red).  KKT_EDIMS if a level's
+ * chain is too short for its segment count. */
+int kkt_plan_create_nested(kkt_plan **plan, int32_t num_systems, const kkt_dims *dims, const kkt_nest *nest,
+                           int32_t nrhs, const kkt_cost_model *model);
+
+/* Where the reduced chain of system s is factored when it is segmented: *child
+ * receives the plan of the reduced systems (owned by plan: do not destroy it),
+ * *child_system the index of s's chain in it, and *workspace_offset the byte
+ * offset inside plan's workspace of the child's own workspace (its factor region
+ * at that offset plus kkt_plan_factor_offset(child)).  The child's systems read
+ * their couplings hat H_k from plan's factor region (their off_C is relative to
+ * it).  *child is NULL if the chain of s is swept sequentially. */
+int kkt_plan_reduced(const kkt_plan *plan, int32_t s, const kkt_plan **child, int32_t *child_system,
+                     int64_t *workspace_offset);
 /* Releases the plan and its side streams and events.  No call of the plan may be
  * in flight on the host; work already enqueued is unaffected. */
 int kkt_plan_destroy(kkt_plan *plan);

@@ -180,6 +180,158 @@ __global__ void __launch_bounds__(64, DB == 16 ? 2 : 1) kkt_dense_seg_bwd(Args a
     }
 }
 
+// ------------------------------------------------------------------ recursive segmentation
+// A nested system's reduced chain is handed to the child plan as an ordinary
+// system: after phase 1, stage j of the chain (separator k = j + 2) has
+//   D'_j = hat A_k partial (factor slot of the separator) - hat F_{k-1} hat F_{k-1}^T
+//   B'_j = hat Q_k partial - hat G_{N_{k-1}, k-1} hat F_{k-1}^T
+//   r'_j = separator rhs partial + (-hat F_{k-1} hat y_{N_{k-1}, k-1})
+// (Eqs. 8c, 9d), the couplings hat H_k where phase 1 left them (read in place),
+// corner' = sym(corner) + sum_k tilde R_k and r'_g = r_g + sum_k tilde y_{g,k}
+// (Eqs. 8b, 9c, 10).  The child's solution is the separators' and g's part of x.
+struct NestArgs {
+    const int2 *pairs;     // (system, child system)
+    const int2 *units;     // (pair, separator j; -1: corner and arrow rhs)
+    const SysDesc *csys;   // child systems
+    const int *cstatus;    // child per-system status
+    double *cD, *cB, *cCor, *cR;
+};
+
+template <int MODE>
+__global__ void __launch_bounds__(256) kkt_nest_gather(Args a, NestArgs na)
+{
+    constexpr bool FACT = MODE == M_FACTOR || MODE == M_FACTOR_SOLVE, RHS = MODE != M_FACTOR;
+    if (*a.abort) return;
+    const int2 u = na.units[blockIdx.x];
+    const int2 pr = na.pairs[u.x];
+    const SysDesc sd = a.sys[pr.x];
+    const SysDesc cd = na.csys[pr.y];
+    const int b = sd.b, ng = sd.ng, nr = a.nr, t = threadIdx.x;
+    const long long b2 = (long long)b * b, gb = (long long)ng * b, rb = (long long)b * nr;
+    const double *F = a.F;
+    if (u.y >= 0) {
+        const int j = u.y, sep = sep_of(sd, j + 2);
+        const double *sc = F + sd.oScr + (long long)j * sd.scrStride;   // segment j + 1 ends on separator j + 2
+        if (FACT) {
+            const double *As = F + sd.oLd + sep * b2, *Qs = F + sd.oLb + sep * gb;
+            double *Dc = na.cD + cd.oD + j * b2, *Bc = na.cB + cd.oB + j * gb;
+            for (int e = t; e < b2; e += 256) Dc[e] = As[e] - sc[scr_dA(b, ng, nr) + e];
+            for (int e = t; e < gb; e += 256) Bc[e] = Qs[e] - sc[scr_dQ(b, ng, nr) + e];
+        }
+        if (RHS) {
+            const double *rs = a.rhs + sd.oRhs + sep * rb;
+            double *Rc = na.cR + cd.oRhs + j * rb;
+            for (int e = t; e < rb; e += 256) Rc[e] = rs[e] + sc[scr_dy(b, ng, nr) + e];
+        }
+    } else {
+        const double *sc0 = F + sd.oScr;
+        if (FACT) {
+            const double *cor = a.corner + sd.oCorner;
+            for (int e = t; e < ng * ng; e += 256) {
+                const int q = e / ng, c = e - q * ng;
+                double v = 0.5 * (cor[e] + cor[c * ng + q]);
+                for (int k = 0; k < sd.p; ++k) v += sc0[(long long)k * sd.scrStride + scr_Rk(b, ng, nr) + e];
+                na.cCor[cd.oCorner + e] = v;
+            }
+        }
+        if (RHS) {
+            const double *rg = a.rhs + sd.oRhs + (long long)sd.N * rb;
+            double *Rc = na.cR + cd.oRhs + (long long)cd.N * rb;
+            for (int e = t; e < ng * nr; e += 256) {
+                double v = rg[e];
+                for (int k = 0; k < sd.p; ++k) v += sc0[(long long)k * sd.scrStride + scr_yg(b, ng, nr) + e];
+                Rc[e] = v;
+            }
+        }
+    }
+}
+
+// After the child's call: the nested system's info (factor modes: its segments'
+// first failure, else the child's failure mapped to the separator or corner it
+// names), then (solve modes) the separators' and g's solution, NaN if the system
+// failed, and with the adjoint their gradient blocks (dD, dB of the separators,
+// dcorner) as the sequential sweep would write them.  One workgroup per system.
+template <int MODE>
+__global__ void __launch_bounds__(256) kkt_nest_finish(Args a, NestArgs na)
+{
+    constexpr bool FACT = MODE == M_FACTOR || MODE == M_FACTOR_SOLVE;
+    if (*a.abort) return;
+    const int2 pr = na.pairs[blockIdx.x];
+    const SysDesc sd = a.sys[pr.x];
+    const SysDesc cd = na.csys[pr.y];
+    const int b = sd.b, ng = sd.ng, nr = a.nr, t = threadIdx.x, M = cd.N;
+    const long long rb = (long long)b * nr;
+    __shared__ int st;
+    if (t == 0) {
+        if (FACT) {
+            const int segf = load_status(&a.failidx[pr.x]);
+            const int c = load_status(&na.cstatus[pr.y]);
+            const int v = segf != INT_MAX ? segf : (c == 0 ? 0 : (c <= M ? sep_of(sd, c + 1) + 1 : sd.N + 1));
+            a.status[pr.x] = v;
+            if (a.info) a.info[pr.x] = v;
+            st = v;
+        } else {
+            st = load_status(&a.status[pr.x]);
+        }
+    }
+    __syncthreads();
+    if (MODE == M_FACTOR) return;
+    const bool bad = st != 0;
+    const double qnan = __longlong_as_double(0x7ff8000000000000LL);
+    double *X = a.rhs + sd.oRhs;
+    const double *Xc = na.cR + cd.oRhs;
+    for (int j = 0; j < M; ++j) {
+        const long long o = (long long)sep_of(sd, j + 2) * rb;
+        for (int e = t; e < rb; e += 256) X[o + e] = bad ? qnan : Xc[j * rb + e];
+    }
+    const long long og = (long long)sd.N * rb, ocg = (long long)M * rb;
+    for (int e = t; e < ng * nr; e += 256) X[og + e] = bad ? qnan : Xc[ocg + e];
+    if (MODE != M_ADJOINT) return;
+    // lambda (just written, read back from the child) and the primal x
+    const double *XP = a.xp + sd.oRhs;
+    auto lam = [&](long long o) { return bad ? qnan : Xc[o]; };
+    const long long b2 = (long long)b * b;
+    for (int j = 0; j < M; ++j) {
+        const int sep = sep_of(sd, j + 2);
+        const long long os = (long long)sep * rb, oc = (long long)j * rb;
+        double *dD = a.dD + sd.oD + sep * b2, *dB = a.dB + sd.oB + (long long)sep * ng * b;
+        for (int e = t; e < b2; e += 256) {
+            const int r = e / b, c = e - r * b;
+            double v = 0.0;
+            for (int q = 0; q < nr; ++q)
+                v += lam(oc + r * nr + q) * XP[os + c * nr + q] + XP[os + r * nr + q] * lam(oc + c * nr + q);
+            dD[e] = -0.5 * v;
+        }
+        for (int e = t; e < ng * b; e += 256) {
+            const int g = e / b, c = e - g * b;
+            double v = 0.0;
+            for (int q = 0; q < nr; ++q)
+                v += lam(ocg + g * nr + q) * XP[os + c * nr + q] + XP[og + g * nr + q] * lam(oc + c * nr + q);
+            dB[e] = -v;
+        }
+    }
+    double *dR = a.dcorner + sd.oCorner;
+    for (int e = t; e < ng * ng; e += 256) {
+        const int g = e / ng, c = e - g * ng;
+        double v = 0.0;
+        for (int q = 0; q < nr; ++q)
+            v += lam(ocg + g * nr + q) * XP[og + c * nr + q] + XP[og + g * nr + q] * lam(ocg + c * nr + q);
+        dR[e] = -0.5 * v;
+    }
+}
+
+typedef void (*nfun_t)(Args, NestArgs);
+
+nfun_t nest_kernel(int mode, bool finish)
+{
+    switch (mode) {
+    case M_FACTOR: return finish ? kkt_nest_finish<M_FACTOR> : kkt_nest_gather<M_FACTOR>;
+    case M_FACTOR_SOLVE: return finish ? kkt_nest_finish<M_FACTOR_SOLVE> : kkt_nest_gather<M_FACTOR_SOLVE>;
+    case M_SOLVE: return finish ? kkt_nest_finish<M_SOLVE> : kkt_nest_gather<M_SOLVE>;
+    default: return finish ? kkt_nest_finish<M_ADJOINT> : kkt_nest_gather<M_ADJOINT>;
+    }
+}
+
 // Start of every call: check that the workspace holds this plan's tables (a
 // mismatch makes every later kernel of the call return at once and is reported
 // by kkt_workspace_error), then clear the queue heads and the per-system failure
@@ -284,15 +436,65 @@ struct ItemEst {
     double longest, total;
 };
 
-// Estimated longest item and total work of one system split into p segments.
-ItemEst estimate(int N, int p, int cls, const kkt_cost_model &m)
+// The reduced chain of M separators, swept sequentially (M t_red) or segmented
+// recursively: at each level q segments balanced by Eq. 13 with the model's
+// sigma, then the chain of their q - 1 separators, t_level per extra level.  The
+// estimate keeps the shortest longest path; p[] holds the segment counts per
+// level that reach it (0: sequential).
+struct ChainEst {
+    double longest = 0.0, total = 0.0;
+    int p[KKT_MAX_LEVELS] = {};
+};
+
+struct ChainModel {
+    const kkt_cost_model &m;
+    int cls;
+    std::map<std::pair<int, int>, ChainEst> memo;
+
+    ChainModel(const kkt_cost_model &model, int c) : m(model), cls(c) {}
+
+    ChainEst best(int M, int depth)
+    {
+        ChainEst serial;
+        serial.longest = serial.total = M * m.t_red[cls];
+        if (depth <= 0 || M < 3) return serial;
+        const auto key = std::make_pair(M, depth);
+        const auto it = memo.find(key);
+        if (it != memo.end()) return it->second;
+        ChainEst b = serial;
+        for (int q = 2; 2 * q - 1 <= M; ++q) {
+            int N1 = 0, Nk = 0;
+            if (!partition_sigma(M, q, m.t_first[cls], m.t_fill[cls], &N1, &Nk)) continue;
+            const double seg1 = m.t_item[cls] + N1 * m.t_first[cls], segk = m.t_item[cls] + Nk * m.t_fill[cls];
+            const ChainEst sub = best(q - 1, depth - 1);
+            const double lg = std::max(seg1, segk) + sub.longest + m.t_level[cls];
+            if (lg < b.longest) {
+                b.longest = lg;
+                b.total = seg1 + (q - 1) * segk + sub.total + m.t_level[cls];
+                b.p[0] = q;
+                for (int l = 1; l < KKT_MAX_LEVELS; ++l) b.p[l] = sub.p[l - 1];
+            }
+        }
+        memo[key] = b;
+        return b;
+    }
+};
+
+// Estimated longest item and total work of one system split into p segments,
+// its reduced chain as cm chooses (sequential if cm is null); *nest receives the
+// chain's segment counts.
+ItemEst estimate(int N, int p, int cls, const kkt_cost_model &m, ChainModel *cm = nullptr, kkt_nest *nest = nullptr)
 {
     int N1 = N, Nk = 0;
     if (p > 1 && !partition_sigma(N, p, m.t_first[cls], m.t_fill[cls], &N1, &Nk)) return {1e300, 1e300};
     const double seg1 = m.t_item[cls] + N1 * m.t_first[cls];
     const double segk = p > 1 ? m.t_item[cls] + Nk * m.t_fill[cls] : 0.0;
-    const double red = (p - 1) * m.t_red[cls];
-    return {std::max(seg1, segk) + red, seg1 + (p - 1) * segk + red};
+    ChainEst red;
+    red.longest = red.total = (p - 1) * m.t_red[cls];
+    if (cm && p > 1) red = cm->best(p - 1, KKT_MAX_LEVELS);
+    if (nest)
+        for (int l = 0; l < KKT_MAX_LEVELS; ++l) nest->p[l] = red.p[l];
+    return {std::max(seg1, segk) + red.longest, seg1 + (p - 1) * segk + red.total};
 }
 
 // Items of class cls the device runs at once, for systems of p segments.
@@ -311,8 +513,11 @@ double pool(const kkt_cost_model &m, int cls, int p)
 // values themselves, searched by bisection, and the two candidates around the
 // crossing are compared.  Systems of one class and length always get equal p (a
 // greedy split of one system at a time stalls on such ties).
-void choose_segments(std::vector<kkt_dims> &dims, const std::vector<int> &cls_of, const kkt_cost_model &m)
+void choose_segments(std::vector<kkt_dims> &dims, std::vector<kkt_nest> &nest, const std::vector<int> &cls_of,
+                     const kkt_cost_model &m)
 {
+    std::vector<ChainModel> chains;
+    for (int c = 0; c < NCLS; ++c) chains.emplace_back(m, c);
     double fixed_work = 0.0, fixed_longest = 0.0;
     std::map<std::pair<int, int>, int> count;      // tuned systems per (class, N)
     for (size_t s = 0; s < dims.size(); ++s) {
@@ -335,9 +540,9 @@ void choose_segments(std::vector<kkt_dims> &dims, const std::vector<int> &cls_of
     for (const auto &kv : count) {
         const int c = kv.first.first, N = kv.first.second;
         Len L{c, N, kv.second, {}};
-        const int pmax = std::max(1, std::min((N + 1) / 2, 256));
+        const int pmax = std::max(1, std::min((N + 1) / 2, 1024));
         for (int p = 1; p <= pmax; ++p) {
-            L.est.push_back(estimate(N, p, c, m));
+            L.est.push_back(estimate(N, p, c, m, &chains[c]));
             if (L.est.back().longest < 1e299) cand.push_back(std::max(L.est.back().longest, fixed_longest));
         }
         lens.push_back(std::move(L));
@@ -388,6 +593,7 @@ void choose_segments(std::vector<kkt_dims> &dims, const std::vector<int> &cls_of
         if (dims[s].p != 0) continue;
         const int c = cls_of[s], p = p_of[{c, dims[s].N}];
         dims[s].p = p;
+        estimate(dims[s].N, p, c, m, &chains[c], &nest[s]);
         int N1 = 0, Nk = 0;
         if (p > 1 && dims[s].N1 == 0 && partition_sigma(dims[s].N, p, m.t_first[c], m.t_fill[c], &N1, &Nk))
             dims[s].N1 = N1;
@@ -405,6 +611,7 @@ kkt_cost_model default_cost_model()
         m.t_item[c] = 0.0;
         m.workers[c] = 512.0;
         m.workers_seg[c] = 512.0;
+        m.t_level[c] = 64.0 * m.t_first[c];
     }
     return m;
 }
@@ -412,8 +619,9 @@ kkt_cost_model default_cost_model()
 // Standard flop counts (potrf n^3/3, trsm m n^2, syrk n^2 k, gemm 2 m n k, matrix
 // additions m n per term) of the operations of Algorithm 1 for one system with
 // segment lengths N1, Nk (p segments): the parallel phase of every segment, then
-// the sequential phase on the separators and the corner.
-double factor_flops_std(int N1, int Nk, int p, double b, double g)
+// the sequential phase on the separators and the corner (seq false: without the
+// sequential phase and the corner factor, which a segmented reduced chain counts).
+double factor_flops_std(int N1, int Nk, int p, double b, double g, bool seq = true)
 {
     const double potrf = b * b * b / 3.0, trsm = b * b * b, syrk = b * b * b, gemm = 2.0 * b * b * b;
     const double trsm_g = g * b * b, syrk_g = g * g * b, gemm_g = 2.0 * g * b * b;
@@ -430,6 +638,7 @@ double factor_flops_std(int N1, int Nk, int p, double b, double g)
         if (k < p) f += trsm;
         if (k > 1 && k < p) f += gemm;
     }
+    if (!seq) return f + (g > 0 ? g * g * p : 0.0);
     for (int k = 2; k <= p; ++k) {
         f += syrk + potrf;
         if (k < p) f += trsm + syrk;
@@ -443,7 +652,7 @@ double factor_flops_std(int N1, int Nk, int p, double b, double g)
 }
 
 // The same for one solve with one right-hand side (trsv n^2, gemv 2 m n), Algorithms 2 and 3.
-double solve_flops_std(int N1, int Nk, int p, double b, double g)
+double solve_flops_std(int N1, int Nk, int p, double b, double g, bool seq = true)
 {
     const double trsv = b * b, gemv = 2.0 * b * b, gemv_g = 2.0 * g * b;
     double f = 0.0;
@@ -454,6 +663,7 @@ double solve_flops_std(int N1, int Nk, int p, double b, double g)
         // backward: the same products transposed, and hat F_k^T x_{k+1}
         f += n * trsv + (n - 1) * gemv + (k > 1 ? n * gemv : 0.0) + (g > 0 ? n * gemv_g : 0.0) + (k < p ? gemv : 0.0);
     }
+    if (!seq) return f + (g > 0 ? g * p : 0.0);
     for (int k = 2; k <= p; ++k) {
         f += gemv + 2 * trsv + (k < p ? 2 * gemv : 0.0) + (g > 0 ? 2 * gemv_g : 0.0);
     }
@@ -489,6 +699,14 @@ struct kkt_plan {
     std::vector<int> red;
     size_t o_tag = 0, o_ctr = 0, o_sys = 0, o_items = 0, o_red = 0, o_s3 = 0, o_fail = 0, o_status = 0, o_F = 0,
            bytes = 0;
+    // Recursive segmentation: the reduced chains of the nested systems form the
+    // systems of a child plan, whose input pools (D, B, corner, rhs; C is read in
+    // this plan's factor region) and workspace sit at the end of this workspace.
+    kkt_plan *child = nullptr;
+    std::vector<int2> npairs;   // (system, child system) per nested system
+    std::vector<int2> nunits;   // gather units: (pair, separator j along the chain; -1 the corner)
+    std::vector<int> child_of;  // per system: its child system or -1
+    size_t o_npairs = 0, o_nunits = 0, o_cD = 0, o_cB = 0, o_cCor = 0, o_cR = 0, o_child = 0;
     long long nF = 0;
     long long tag = 0;
     kkt_plan_info info{};
@@ -526,6 +744,7 @@ struct kkt_plan {
     }
     ~kkt_plan()
     {
+        delete child;
         // teardown: a failure to destroy leaves nothing to recover, so it is ignored
         for (Dev &d : devs) {
             for (int j = 0; j < NSIDE; ++j) {
@@ -544,6 +763,21 @@ bool valid_dims(const kkt_dims &d)
     if (d.N < 1 || d.b < 1 || d.b > KKT_MAX_B || d.ng < 0 || d.ng > KKT_MAX_NG) return false;
     if (d.p < 0) return false;
     if (d.p > 1 && d.N < 2 * d.p - 1) return false;
+    return true;
+}
+
+// The recursion of a system of p segments: each level's chain long enough for
+// its segment count (a count <= 1 ends it).
+bool valid_nest(int p, const kkt_nest &n)
+{
+    int M = p - 1;
+    for (int l = 0; l < KKT_MAX_LEVELS; ++l) {
+        const int q = n.p[l];
+        if (q < 0) return false;
+        if (q <= 1) return true;
+        if (M < 2 * q - 1) return false;
+        M = q - 1;
+    }
     return true;
 }
 
@@ -573,15 +807,13 @@ int launches_of(const kkt_plan::Cls &c, int mode, int nr, Launch *out)
     if (c.kind == kkt_plan::K_DSEG && fact) {
         const size_t lds = (size_t)lds_offsets_dense(32, nr, true).total * sizeof(double);
         out[n++] = {fwd ? kkt_dense_seg<32, true> : kkt_dense_seg<32, false>, 64, lds, 0};
-        out[n++] = {wave_kernel(c.bp, mode, 1, nr), wnt, wl, 1};
+        if (c.red_cnt > 0) out[n++] = {wave_kernel(c.bp, mode, 1, nr), wnt, wl, 1};
         if (fwd) out[n++] = {kkt_dense_seg_bwd<32>, 64, lds, 2};
         return n;
     }
     out[n++] = {wave_kernel(c.bp, mode, 0, nr), wnt, wl, 0};
-    if (c.red_cnt > 0) {
-        out[n++] = {wave_kernel(c.bp, mode, 1, nr), wnt, wl, 1};
-        if (mode != M_FACTOR) out[n++] = {wave_kernel(c.bp, mode, 2, nr), wnt, wl, 2};
-    }
+    if (c.red_cnt > 0) out[n++] = {wave_kernel(c.bp, mode, 1, nr), wnt, wl, 1};
+    if (c.s3_cnt > 0 && mode != M_FACTOR) out[n++] = {wave_kernel(c.bp, mode, 2, nr), wnt, wl, 2};
     return n;
 }
 
@@ -590,7 +822,16 @@ int work_of(const kkt_plan::Cls &c, int list) { return list == 0 ? c.item_cnt : 
 // The launch state of the current device: side streams and events, dynamic LDS
 // limits and the grid of every launch (as many workgroups as fit on the device
 // at once, at most one per work entry).  Called with the plan's lock held.
+int ensure_device_one(const kkt_plan *plan, int dev, bool streams);
+
 int ensure_device(const kkt_plan *plan, int dev, bool streams = true)
+{
+    int rc = ensure_device_one(plan, dev, streams);
+    if (rc == KKT_OK && plan->child) rc = ensure_device(plan->child, dev, streams);
+    return rc;
+}
+
+int ensure_device_one(const kkt_plan *plan, int dev, bool streams)
 {
     if (const kkt_plan::Dev *have = plan->dev_state(dev)) {
         if (!streams || have->fork || !have->needs_streams) return KKT_OK;
@@ -671,6 +912,34 @@ void *noalloc_scratch(int dev)
     return g_noalloc_ptr[dev];
 }
 
+// Copy a plan's tables (and its child's, into its sub-workspace) into a
+// workspace; with zero_status also clear the per-system status words.
+bool put_tables(const kkt_plan *plan, char *ws, hipStream_t stream, bool zero_status)
+{
+    auto put = [&](size_t off, const void *src, size_t n) {
+        return n == 0 || hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, stream) == hipSuccess;
+    };
+    const long long tag[3] = {plan->tag, (long long)plan->bytes, 0};
+    if (!put(plan->o_sys, plan->sys.data(), sizeof(SysDesc) * plan->S) ||
+        !put(plan->o_items, plan->items.data(), sizeof(int2) * plan->items.size()) ||
+        !put(plan->o_red, plan->red.data(), sizeof(int) * plan->red.size()) ||
+        !put(plan->o_s3, plan->s3.data(), sizeof(int2) * plan->s3.size()) || !put(plan->o_tag, tag, sizeof(tag)))
+        return false;
+    if (zero_status) {
+        std::vector<int> st(plan->S, 0);
+        if (!put(plan->o_status, st.data(), sizeof(int) * plan->S)) return false;
+        // the copy must not outlive st
+        if (hipStreamSynchronize(stream) != hipSuccess) return false;
+    }
+    if (plan->child) {
+        if (!put(plan->o_npairs, plan->npairs.data(), sizeof(int2) * plan->npairs.size()) ||
+            !put(plan->o_nunits, plan->nunits.data(), sizeof(int2) * plan->nunits.size()))
+            return false;
+        return put_tables(plan->child, ws + plan->o_child, stream, zero_status);
+    }
+    return true;
+}
+
 Args base_args(const kkt_plan *plan, void *workspace)
 {
     char *ws = (char *)workspace;
@@ -710,24 +979,28 @@ int launch_mode(const kkt_plan *plan, int mode, const Args &base, const void *ws
     return launch_locked(plan, d, mode, base, ws, stream, info, true);
 }
 
-// Enqueue one call with the plan's lock held and its launch state d of the current device.
-int launch_locked(const kkt_plan *plan, const kkt_plan::Dev *d, int mode, const Args &base, const void *ws,
-                  hipStream_t stream, int *info, bool allow_fork)
+// The launches of every class whose work list is in lists (bit l: list l), the
+// classes on forked streams when there are several, joined back into stream.  On
+// an error after the fork, the side streams used so far are still joined.
+int enqueue_classes(const kkt_plan *plan, const kkt_plan::Dev *d, int mode, const Args &base, hipStream_t stream,
+                    bool allow_fork, int lists, bool rec_start, bool rec_stop)
 {
-    const bool fact = mode == M_FACTOR || mode == M_FACTOR_SOLVE;
-    const char *w = (const char *)ws;
-    hipLaunchKernelGGL(kkt_reset, dim3(std::max(1, std::min(1024, (plan->S + 255) / 256))), dim3(256), 0, stream,
-                       (const long long *)(w + plan->o_tag), plan->tag, (int *)(w + plan->o_tag + 16), base.ctr,
-                       4 * (int)plan->cls.size(), fact ? base.failidx : nullptr, plan->S, fact ? info : nullptr);
-    if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
-    int nact = 0;
-    for (const kkt_plan::Cls &c : plan->cls) nact += c.item_cnt > 0;
+    Launch L[kkt_plan::MAXC][3];
+    int n[kkt_plan::MAXC] = {}, nact = 0;
+    for (size_t ci = 0; ci < plan->cls.size(); ++ci) {
+        const kkt_plan::Cls &c = plan->cls[ci];
+        n[ci] = c.item_cnt > 0 ? launches_of(c, mode, plan->nrhs, L[ci]) : 0;
+        bool any = false;
+        for (int l = 0; l < n[ci]; ++l) any |= ((lists >> L[ci][l].list) & 1) != 0;
+        if (!any) n[ci] = 0;
+        nact += n[ci] > 0;
+    }
     const bool fork = allow_fork && nact > 1 && d->fork;
     if (fork && hipEventRecord(d->fork, stream) != hipSuccess) return KKT_ELAUNCH;
     int rc = KKT_OK, nside = 0;
     for (size_t ci = 0; ci < plan->cls.size() && rc == KKT_OK; ++ci) {
         const kkt_plan::Cls &c = plan->cls[ci];
-        if (c.item_cnt == 0) continue;
+        if (n[ci] == 0) continue;
         const bool on_side = fork && nside < kkt_plan::NSIDE;
         hipStream_t st = on_side ? d->side[nside] : stream;
         if (on_side && hipStreamWaitEvent(st, d->fork, 0) != hipSuccess) {
@@ -742,14 +1015,14 @@ int launch_locked(const kkt_plan *plan, const kkt_plan::Dev *d, int mode, const 
         a.s3 = base.s3 + c.s3_off;
         a.n_s3 = c.s3_cnt;
         a.ctr = base.ctr + 4 * ci;
-        if (plan->ev_start[ci] && hipEventRecord(plan->ev_start[ci], st) != hipSuccess) rc = KKT_ELAUNCH;
-        Launch L[3];
-        const int n = launches_of(c, mode, plan->nrhs, L);
-        for (int l = 0; l < n && rc == KKT_OK; ++l) {
-            hipLaunchKernelGGL(L[l].fn, dim3(d->grid[ci][mode][l]), dim3(L[l].nt), L[l].lds, st, a);
+        if (rec_start && plan->ev_start[ci] && hipEventRecord(plan->ev_start[ci], st) != hipSuccess) rc = KKT_ELAUNCH;
+        for (int l = 0; l < n[ci] && rc == KKT_OK; ++l) {
+            if (((lists >> L[ci][l].list) & 1) == 0) continue;
+            hipLaunchKernelGGL(L[ci][l].fn, dim3(d->grid[ci][mode][l]), dim3(L[ci][l].nt), L[ci][l].lds, st, a);
             if (hipGetLastError() != hipSuccess) rc = KKT_ELAUNCH;
         }
-        if (rc == KKT_OK && plan->ev_stop[ci] && hipEventRecord(plan->ev_stop[ci], st) != hipSuccess) rc = KKT_ELAUNCH;
+        if (rc == KKT_OK && rec_stop && plan->ev_stop[ci] && hipEventRecord(plan->ev_stop[ci], st) != hipSuccess)
+            rc = KKT_ELAUNCH;
         if (on_side) {
             if (hipEventRecord(d->join[nside], st) != hipSuccess) rc = KKT_ELAUNCH;
             ++nside;
@@ -760,6 +1033,52 @@ int launch_locked(const kkt_plan *plan, const kkt_plan::Dev *d, int mode, const 
     for (int j = 0; j < nside; ++j)
         if (hipStreamWaitEvent(stream, d->join[j], 0) != hipSuccess) rc = KKT_ELAUNCH;
     return rc;
+}
+
+// Enqueue one call with the plan's lock held and its launch state d of the current
+// device.  Without reduced chains to segment, each class runs its phases back to
+// back on its stream.  Otherwise every class runs phases 1 and 2, then on the
+// caller's stream the nested systems' chains are gathered, the child plan makes
+// its own call (recursively) and the results are scattered back, and then every
+// class runs phase 3.
+int launch_locked(const kkt_plan *plan, const kkt_plan::Dev *d, int mode, const Args &base, const void *ws,
+                  hipStream_t stream, int *info, bool allow_fork)
+{
+    const bool fact = mode == M_FACTOR || mode == M_FACTOR_SOLVE;
+    const char *w = (const char *)ws;
+    hipLaunchKernelGGL(kkt_reset, dim3(std::max(1, std::min(1024, (plan->S + 255) / 256))), dim3(256), 0, stream,
+                       (const long long *)(w + plan->o_tag), plan->tag, (int *)(w + plan->o_tag + 16), base.ctr,
+                       4 * (int)plan->cls.size(), fact ? base.failidx : nullptr, plan->S, fact ? info : nullptr);
+    if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
+    if (!plan->child) return enqueue_classes(plan, d, mode, base, stream, allow_fork, 7, true, true);
+    int rc = enqueue_classes(plan, d, mode, base, stream, allow_fork, 3, true, false);
+    if (rc != KKT_OK) return rc;
+    const kkt_plan *ch = plan->child;
+    const kkt_plan::Dev *cdv = ch->dev_state(d->dev);
+    if (!cdv) return KKT_EWORKSPACE;
+    char *cw = (char *)ws + plan->o_child;
+    NestArgs na;
+    na.pairs = (const int2 *)(w + plan->o_npairs);
+    na.units = (const int2 *)(w + plan->o_nunits);
+    na.csys = (const SysDesc *)(cw + ch->o_sys);
+    na.cstatus = (const int *)(cw + ch->o_status);
+    na.cD = (double *)(w + plan->o_cD);
+    na.cB = (double *)(w + plan->o_cB);
+    na.cCor = (double *)(w + plan->o_cCor);
+    na.cR = (double *)(w + plan->o_cR);
+    hipLaunchKernelGGL(nest_kernel(mode, false), dim3((unsigned)plan->nunits.size()), dim3(256), 0, stream, base, na);
+    if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
+    Args ca = base_args(ch, cw);
+    ca.D = na.cD;
+    ca.C = base.F;   // the couplings hat H_k, in place (child offsets point there)
+    ca.B = na.cB;
+    ca.corner = na.cCor;
+    ca.rhs = mode != M_FACTOR ? na.cR : nullptr;
+    rc = launch_locked(ch, cdv, mode == M_ADJOINT ? M_SOLVE : mode, ca, cw, stream, nullptr, allow_fork);
+    if (rc != KKT_OK) return rc;
+    hipLaunchKernelGGL(nest_kernel(mode, true), dim3((unsigned)plan->npairs.size()), dim3(256), 0, stream, base, na);
+    if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
+    return enqueue_classes(plan, d, mode, base, stream, allow_fork, 4, false, true);
 }
 
 bool aligned8(const void *p) { return ((uintptr_t)p & 7) == 0; }
@@ -776,19 +1095,31 @@ int kkt_plan_create(kkt_plan **out, int32_t S, const kkt_dims *dims, int32_t nrh
 int kkt_plan_create_tuned(kkt_plan **out, int32_t S, const kkt_dims *dims_in, int32_t nrhs,
                           const kkt_cost_model *model)
 {
+    return kkt_plan_create_nested(out, S, dims_in, nullptr, nrhs, model);
+}
+
+int kkt_plan_create_nested(kkt_plan **out, int32_t S, const kkt_dims *dims_in, const kkt_nest *nest_in,
+                           int32_t nrhs, const kkt_cost_model *model)
+{
     if (!out) return KKT_EPOINTER;
     *out = nullptr;
     if (S < 1 || !dims_in) return S < 1 ? KKT_EDIMS : KKT_EPOINTER;
     if (nrhs < 1 || nrhs > KKT_MAX_NRHS) return KKT_EDIMS;
     std::vector<kkt_dims> dims(dims_in, dims_in + S);
+    std::vector<kkt_nest> nest(S);
+    std::memset(nest.data(), 0, sizeof(kkt_nest) * S);
+    const kkt_cost_model m = model ? *model : default_cost_model();
     {
         std::vector<int> cls0(S);
         for (int s = 0; s < S; ++s) {
             if (!valid_dims(dims[s])) return KKT_EDIMS;
             cls0[s] = class_of(dims[s].b);
+            if (dims[s].p != 0 && nest_in) {
+                nest[s] = nest_in[s];
+                if (!valid_nest(dims[s].p, nest[s])) return KKT_EDIMS;
+            }
         }
-        const kkt_cost_model m = model ? *model : default_cost_model();
-        choose_segments(dims, cls0, m);
+        choose_segments(dims, nest, cls0, m);
     }
     kkt_plan *P = new (std::nothrow) kkt_plan;
     if (!P) return KKT_EINTERNAL;
@@ -841,8 +1172,9 @@ int kkt_plan_create_tuned(kkt_plan **out, int32_t S, const kkt_dims *dims_in, in
         L.off_D = sd.oD; L.off_C = sd.oC; L.off_B = sd.oB; L.off_corner = sd.oCorner; L.off_rhs = sd.oRhs;
         L.off_Ld = sd.oLd; L.off_Lc = sd.oLc; L.off_Lb = sd.oLb; L.off_Lg = sd.oLg; L.off_fill = sd.oFill;
         L.off_H = sd.oH;
-        fflops += factor_flops_std(N1, Nk, p, (double)b, (double)ng);
-        sflops += nrhs * solve_flops_std(N1, Nk, p, (double)b, (double)ng);
+        const bool seq = !(p >= 2 && nest[s].p[0] >= 2);
+        fflops += factor_flops_std(N1, Nk, p, (double)b, (double)ng, seq);
+        sflops += nrhs * solve_flops_std(N1, Nk, p, (double)b, (double)ng, seq);
         fwords += N * b2 + (N - 1) * b2 + N * ng * b + ng * ng + fill + H;
         iwords += N * b2 + (N - 1) * b2 + N * ng * b + ng * ng;
     }
@@ -861,7 +1193,7 @@ int kkt_plan_create_tuned(kkt_plan **out, int32_t S, const kkt_dims *dims_in, in
             const SysDesc &sd = P->sys[s];
             if (dense_capable(bp) && (sd.p == 1) != dense) continue;
             for (int k = 1; k <= sd.p; ++k) its.push_back({item_cost(sd, k), make_int2(s, k)});
-            if (sd.p > 1) reds.push_back(s);
+            if (sd.p > 1 && nest[s].p[0] < 2) reds.push_back(s);
         }
         if (its.empty()) continue;
         std::stable_sort(its.begin(), its.end(), [](const std::pair<double, int2> &x, const std::pair<double, int2> &y) {
@@ -885,6 +1217,47 @@ int kkt_plan_create_tuned(kkt_plan **out, int32_t S, const kkt_dims *dims_in, in
         if ((int)P->cls.size() >= kkt_plan::MAXC) { delete P; return KKT_EINTERNAL; }
         P->cls.push_back(C);
     }
+    // the reduced chains of the nested systems: the child plan (recursively)
+    P->child_of.assign(S, -1);
+    {
+        std::vector<kkt_dims> cdims;
+        std::vector<kkt_nest> cnest;
+        for (int s = 0; s < S; ++s) {
+            const SysDesc &sd = P->sys[s];
+            if (sd.p < 2 || nest[s].p[0] < 2) continue;
+            kkt_dims cd;
+            cd.N = sd.p - 1; cd.b = sd.b; cd.ng = sd.ng; cd.p = nest[s].p[0]; cd.N1 = 0;
+            if (dims_in[s].p == 0) {
+                // the cost model's balance, as its estimate assumed
+                int N1 = 0, Nk = 0;
+                if (partition_sigma(cd.N, cd.p, m.t_first[sd.cls], m.t_fill[sd.cls], &N1, &Nk)) cd.N1 = N1;
+            }
+            kkt_nest cn;
+            std::memset(&cn, 0, sizeof(cn));
+            for (int l = 1; l < KKT_MAX_LEVELS; ++l) cn.p[l - 1] = nest[s].p[l];
+            P->child_of[s] = (int)cdims.size();
+            P->npairs.push_back(make_int2(s, (int)cdims.size()));
+            cdims.push_back(cd);
+            cnest.push_back(cn);
+        }
+        if (!cdims.empty()) {
+            kkt_plan *ch = nullptr;
+            const int rc = kkt_plan_create_nested(&ch, (int)cdims.size(), cdims.data(), cnest.data(), nrhs, model);
+            if (rc != KKT_OK) { delete P; return rc; }
+            P->child = ch;
+            for (size_t i = 0; i < P->npairs.size(); ++i) {
+                const int2 pr = P->npairs[i];
+                // the chain's couplings hat H_k are read where phase 1 leaves them
+                ch->sys[pr.y].oC = P->sys[pr.x].oH;
+                ch->lay[pr.y].off_C = P->sys[pr.x].oH;
+                for (int j = 0; j < P->sys[pr.x].p - 1; ++j) P->nunits.push_back(make_int2((int)i, j));
+                P->nunits.push_back(make_int2((int)i, -1));
+            }
+            fflops += ch->info.factor_flops;
+            sflops += ch->info.solve_flops;
+            fwords += ch->info.factor_words;
+        }
+    }
     // workspace layout: tag (plan tag, size, refusal word), queue heads, tables, factor
     size_t o = 0;
     P->o_tag = o; o = align256(o + 24);
@@ -896,6 +1269,16 @@ int kkt_plan_create_tuned(kkt_plan **out, int32_t S, const kkt_dims *dims_in, in
     P->o_fail = o; o = align256(o + sizeof(int) * S);
     P->o_status = o; o = align256(o + sizeof(int) * S);
     P->o_F = o; o = align256(o + sizeof(double) * (size_t)oF);
+    if (P->child) {
+        const kkt_plan *ch = P->child;
+        P->o_npairs = o; o = align256(o + sizeof(int2) * P->npairs.size());
+        P->o_nunits = o; o = align256(o + sizeof(int2) * P->nunits.size());
+        P->o_cD = o; o = align256(o + sizeof(double) * (size_t)ch->info.D_len);
+        P->o_cB = o; o = align256(o + sizeof(double) * (size_t)ch->info.B_len);
+        P->o_cCor = o; o = align256(o + sizeof(double) * (size_t)ch->info.corner_len);
+        P->o_cR = o; o = align256(o + sizeof(double) * (size_t)ch->info.rhs_len);
+        P->o_child = o; o = align256(o + ch->bytes);
+    }
     P->bytes = o;
     kkt_plan_info &I = P->info;
     I.num_systems = S;
@@ -933,6 +1316,18 @@ int kkt_plan_system(const kkt_plan *plan, int32_t s, kkt_system_layout *out)
     return KKT_OK;
 }
 
+int kkt_plan_reduced(const kkt_plan *plan, int32_t s, const kkt_plan **child, int32_t *child_system,
+                     int64_t *workspace_offset)
+{
+    if (!plan || !child || !child_system || !workspace_offset) return KKT_EPOINTER;
+    if (s < 0 || s >= plan->S) return KKT_EDIMS;
+    const int cs = plan->child_of[s];
+    *child = cs >= 0 ? plan->child : nullptr;
+    *child_system = cs;
+    *workspace_offset = cs >= 0 ? (int64_t)plan->o_child : -1;
+    return KKT_OK;
+}
+
 int64_t kkt_plan_factor_offset(const kkt_plan *plan) { return plan ? (int64_t)plan->o_F : -1; }
 
 int kkt_workspace_init(const kkt_plan *plan, void *workspace, hipStream_t stream)
@@ -944,18 +1339,7 @@ int kkt_workspace_init(const kkt_plan *plan, void *workspace, hipStream_t stream
     std::lock_guard<std::mutex> guard(plan->mu);
     const int rc = ensure_device(plan, dev);
     if (rc != KKT_OK) return rc;
-    char *ws = (char *)workspace;
-    auto put = [&](size_t off, const void *src, size_t n) {
-        return n == 0 || hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, stream) == hipSuccess;
-    };
-    std::vector<int> st(plan->S, 0);
-    const long long tag[3] = {plan->tag, (long long)plan->bytes, 0};
-    if (!put(plan->o_sys, plan->sys.data(), sizeof(SysDesc) * plan->S) ||
-        !put(plan->o_items, plan->items.data(), sizeof(int2) * plan->items.size()) ||
-        !put(plan->o_red, plan->red.data(), sizeof(int) * plan->red.size()) ||
-        !put(plan->o_s3, plan->s3.data(), sizeof(int2) * plan->s3.size()) ||
-        !put(plan->o_status, st.data(), sizeof(int) * plan->S) || !put(plan->o_tag, tag, sizeof(tag)) ||
-        hipStreamSynchronize(stream) != hipSuccess)
+    if (!put_tables(plan, (char *)workspace, stream, true) || hipStreamSynchronize(stream) != hipSuccess)
         return KKT_ELAUNCH;
     plan->ws_dev[workspace] = dev;
     plan->factored.erase(workspace);
@@ -1017,16 +1401,7 @@ int kkt_factor_solve_noalloc(const kkt_plan *plan, const double *D, const double
     if (rc != KKT_OK) return rc;
     if (g_noalloc_owner[dev] != plan->tag) {
         // the array last held another plan's tables (or none): copy this plan's in
-        char *w = (char *)ws;
-        const long long tag[3] = {plan->tag, (long long)plan->bytes, 0};
-        auto put = [&](size_t off, const void *src, size_t n) {
-            return n == 0 || hipMemcpyAsync(w + off, src, n, hipMemcpyHostToDevice, stream) == hipSuccess;
-        };
-        if (!put(plan->o_sys, plan->sys.data(), sizeof(SysDesc) * plan->S) ||
-            !put(plan->o_items, plan->items.data(), sizeof(int2) * plan->items.size()) ||
-            !put(plan->o_red, plan->red.data(), sizeof(int) * plan->red.size()) ||
-            !put(plan->o_s3, plan->s3.data(), sizeof(int2) * plan->s3.size()) || !put(plan->o_tag, tag, sizeof(tag)))
-            return KKT_ELAUNCH;
+        if (!put_tables(plan, (char *)ws, stream, false)) return KKT_ELAUNCH;
         g_noalloc_owner[dev] = plan->tag;
     }
     Args a = base_args(plan, ws);

@@ -25,6 +25,14 @@ class Dims(ctypes.Structure):
                 ("p", ctypes.c_int32), ("N1", ctypes.c_int32)]
 
 
+MAX_LEVELS = 4
+
+
+class Nest(ctypes.Structure):
+    """Recursive segmentation of one system: p[l] segments of the level-l reduced chain (0 ends it)."""
+    _fields_ = [("p", ctypes.c_int32 * MAX_LEVELS)]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("num_systems", ctypes.c_int32), ("nrhs", ctypes.c_int32), ("num_items", ctypes.c_int32),
                 ("num_classes", ctypes.c_int32), ("D_len", ctypes.c_int64), ("C_len", ctypes.c_int64),
@@ -46,15 +54,21 @@ class SystemLayout(ctypes.Structure):
 class CostModel(ctypes.Structure):
     """Per padded block-size class (8, 16, 24, 32, 48): stage times of first segments,
     fill-carrying segments and reduced stages, item overhead, concurrent items of
-    unsegmented systems (workers) and of segmented ones (workers_seg, 0 = workers)."""
+    unsegmented systems (workers) and of segmented ones (workers_seg, 0 = workers),
+    and the fixed cost of one more level of recursive segmentation (t_level;
+    64 t_first when a dict leaves it out)."""
     _fields_ = [("t_first", ctypes.c_double * NUM_CLASSES), ("t_fill", ctypes.c_double * NUM_CLASSES),
                 ("t_red", ctypes.c_double * NUM_CLASSES), ("t_item", ctypes.c_double * NUM_CLASSES),
-                ("workers", ctypes.c_double * NUM_CLASSES), ("workers_seg", ctypes.c_double * NUM_CLASSES)]
+                ("workers", ctypes.c_double * NUM_CLASSES), ("workers_seg", ctypes.c_double * NUM_CLASSES),
+                ("t_level", ctypes.c_double * NUM_CLASSES)]
 
     @classmethod
     def from_dict(cls, d):
         m = cls()
-        for k in ("t_first", "t_fill", "t_red", "t_item", "workers", "workers_seg"):
+        d = dict(d)
+        if "t_level" not in d:
+            d["t_level"] = [64.0 * float(v) for v in d.get("t_first", [0.0] * NUM_CLASSES)]
+        for k in ("t_first", "t_fill", "t_red", "t_item", "workers", "workers_seg", "t_level"):
             vals = list(d.get(k, [0.0] * NUM_CLASSES))
             if len(vals) != NUM_CLASSES:
                 raise ValueError("cost model field %s needs %d entries, got %d" % (k, NUM_CLASSES, len(vals)))
@@ -81,6 +95,9 @@ def lib():
         L.kkt_plan_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(Dims), i32]
         L.kkt_plan_create_tuned.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(Dims), i32,
                                             ctypes.POINTER(CostModel)]
+        L.kkt_plan_create_nested.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(Dims), ctypes.POINTER(Nest),
+                                             i32, ctypes.POINTER(CostModel)]
+        L.kkt_plan_reduced.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(i64)]
         L.kkt_plan_destroy.argtypes = [vp]
         L.kkt_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         L.kkt_plan_system.argtypes = [vp, i32, ctypes.POINTER(SystemLayout)]
@@ -107,7 +124,8 @@ def lib():
             getattr(L, name).restype = ctypes.c_int
         L.kkt_status_string.restype = ctypes.c_char_p
         L.kkt_status_string.argtypes = [ctypes.c_int]
-        for name in ("kkt_plan_create", "kkt_plan_create_tuned", "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
+        for name in ("kkt_plan_create", "kkt_plan_create_tuned", "kkt_plan_create_nested", "kkt_plan_reduced",
+                     "kkt_plan_destroy", "kkt_plan_get_info", "kkt_plan_system",
                      "kkt_workspace_init", "kkt_factor", "kkt_solve", "kkt_factor_solve", "kkt_solve_adjoint",
                      "kkt_factor_solve_noalloc", "kkt_plan_class_info", "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -119,7 +137,8 @@ EXPORTED = ("kkt_plan_create", "kkt_plan_create_tuned", "kkt_plan_destroy", "kkt
             "kkt_plan_factor_offset", "kkt_workspace_init", "kkt_factor", "kkt_solve",
             "kkt_factor_solve", "kkt_solve_adjoint", "kkt_status_string", "kkt_plan_class_info",
             "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error", "kkt_factor_solve_noalloc",
-            "kkt_ragged_create", "kkt_ragged_destroy", "kkt_ragged_lengths", "kkt_ragged_pad", "kkt_ragged_unpad")
+            "kkt_ragged_create", "kkt_ragged_destroy", "kkt_ragged_lengths", "kkt_ragged_pad", "kkt_ragged_unpad",
+            "kkt_plan_create_nested", "kkt_plan_reduced")
 
 # bytes of the no-allocation entry point's device array (plans above it are refused)
 NOALLOC_MAX_BYTES = 32 << 20
@@ -150,10 +169,17 @@ def _stream(stream):
 class Plan:
     """A plan for a batch of systems: ``dims`` is a list of (N, b, ng[, p[, N1]]).
 
-    p = 0 lets the plan choose the segment count from ``cost_model`` (a
-    ``CostModel`` or a dict of its fields; None = the default model)."""
+    p = 0 lets the plan choose the segment count (and the recursion of the reduced
+    chain) from ``cost_model`` (a ``CostModel`` or a dict of its fields; None = the
+    default model).  ``nest``: per system None or a sequence of segment counts of
+    its reduced chain, that chain's reduced chain, ... (recursive segmentation;
+    read for systems with a given p)."""
 
-    def __init__(self, dims, nrhs=1, cost_model=None):
+    def __init__(self, dims, nrhs=1, cost_model=None, nest=None, _borrow=None):
+        if _borrow is not None:
+            self._h, self._owned = _borrow, False
+            self._load(int(nrhs))
+            return
         dims = [tuple(d) for d in dims]
         arr = (Dims * len(dims))()
         for i, d in enumerate(dims):
@@ -162,18 +188,38 @@ class Plan:
             N1 = int(d[4]) if len(d) > 4 else 0
             arr[i] = Dims(N, b, ng, p, N1)
         h = ctypes.c_void_p()
-        if cost_model is None:
+        if nest is not None:
+            if len(nest) != len(dims):
+                raise ValueError("nest needs one entry per system")
+            narr = (Nest * len(dims))()
+            for i, ps in enumerate(nest):
+                ps = list(ps or [])
+                if len(ps) > MAX_LEVELS:
+                    raise ValueError("at most %d levels of recursion" % MAX_LEVELS)
+                for l, q in enumerate(ps):
+                    narr[i].p[l] = int(q)
+            cm = None
+            if cost_model is not None:
+                cm = cost_model if isinstance(cost_model, CostModel) else CostModel.from_dict(cost_model)
+            _check(lib().kkt_plan_create_nested(ctypes.byref(h), len(dims), arr, narr, int(nrhs),
+                                                ctypes.byref(cm) if cm is not None else None),
+                   "kkt_plan_create_nested")
+        elif cost_model is None:
             _check(lib().kkt_plan_create(ctypes.byref(h), len(dims), arr, int(nrhs)), "kkt_plan_create")
         else:
             cm = cost_model if isinstance(cost_model, CostModel) else CostModel.from_dict(cost_model)
             _check(lib().kkt_plan_create_tuned(ctypes.byref(h), len(dims), arr, int(nrhs), ctypes.byref(cm)),
                    "kkt_plan_create_tuned")
-        self._h = h
-        self.nrhs = int(nrhs)
-        self.S = len(dims)
+        self._h, self._owned = h, True
+        self._load(int(nrhs))
+
+    def _load(self, nrhs):
+        h = self._h
+        self.nrhs = nrhs
         info = PlanInfo()
         _check(lib().kkt_plan_get_info(h, ctypes.byref(info)), "kkt_plan_get_info")
         self.info = info
+        self.S = int(info.num_systems)
         self.factor_offset = int(lib().kkt_plan_factor_offset(h))
         self.layouts = []
         for s in range(self.S):
@@ -183,9 +229,27 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and _lib is not None:
+        if h is not None and getattr(self, "_owned", False) and _lib is not None:
             _lib.kkt_plan_destroy(h)
             self._h = None
+
+    def reduced(self, s):
+        """(child plan, child system, workspace byte offset) where the reduced chain
+        of system s is factored when it is segmented, else None.  The child plan is
+        owned by this one (kept alive by the returned view's reference)."""
+        ch, cs, off = ctypes.c_void_p(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().kkt_plan_reduced(self._h, int(s), ctypes.byref(ch), ctypes.byref(cs), ctypes.byref(off)),
+               "kkt_plan_reduced")
+        if not ch.value:
+            return None
+        view = Plan(None, self.nrhs, _borrow=ch)
+        view._parent = self
+        return view, int(cs.value), int(off.value)
+
+    def nest_depth(self, s):
+        """Levels of recursive segmentation below system s (0: its chain, if any, is swept sequentially)."""
+        r = self.reduced(s)
+        return 0 if r is None else 1 + r[0].nest_depth(r[1])
 
     # ---- memory
     def pool_lengths(self):
@@ -271,17 +335,29 @@ class Plan:
         for st in range(N - 1):
             blk = F[lay.off_Lc + st * b2: lay.off_Lc + (st + 1) * b2].reshape(b, b)
             out[(st, st + 1) if st in sepset else (st + 1, st)] = blk
+        red = self.reduced(s)
         for k in range(2, p + 1):
             sep = seps[k - 2]
             first = sep + 1
             for i in range(2, Nk + 1):
                 o = lay.off_fill + ((k - 2) * (Nk - 1) + (i - 2)) * b2
                 out[(sep, first + i - 1)] = F[o:o + b2].reshape(b, b)
-            if k < p:
+            if k < p and red is None:
                 o = lay.off_H + (k - 2) * b2
                 out[(seps[k - 1], sep)] = F[o:o + b2].reshape(b, b)
-        if ng:
+        if ng and red is None:
             out[("g", "g")] = F[lay.off_Lg: lay.off_Lg + ng * ng].reshape(ng, ng)
+        if red is not None:
+            # the reduced chain's factor (its stage j is separator seps[j]) replaces
+            # the blocks of the separators and the corner
+            child, cs, off = red
+            cb = child.factor_blocks(ws_host[off:off + int(child.info.workspace_bytes)], cs)
+            lab = lambda v: v if v == "g" else seps[v]
+            for st in seps:
+                out.pop((st, st), None)
+                out.pop(("g", st), None)
+            for (ri, cj), blk in cb.items():
+                out[(lab(ri), lab(cj))] = blk
         return out
 
     def classes(self, with_grid=False):

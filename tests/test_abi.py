@@ -91,10 +91,12 @@ def test_factor_words_count_fill():
 CLS = (8, 16, 24, 32, 48)
 
 
-def _model(W=512.0):
+def _model(W=512.0, t_level=1e30):
+    """Flop-ratio model; t_level prices recursive segmentation (1e30: never)."""
     b3 = [float(bp) ** 3 for bp in CLS]
     return {"t_first": [7 / 3 * x for x in b3], "t_fill": [19 / 3 * x for x in b3],
-            "t_red": [10 / 3 * x for x in b3], "t_item": [0.0] * 5, "workers": [W] * 5}
+            "t_red": [10 / 3 * x for x in b3], "t_item": [0.0] * 5, "workers": [W] * 5,
+            "t_level": [t_level] * 5}
 
 
 def _est(N, p, c, m):
@@ -311,3 +313,103 @@ def test_ragged_refuses_sizes_out_of_range_on_the_host():
     assert L.kkt_ragged_create(None, arr, ctypes.byref(h)) == kkt.KKT_EPOINTER
     assert L.kkt_ragged_create(plan._h, None, ctypes.byref(h)) == kkt.KKT_EPOINTER
     assert L.kkt_ragged_pad(None, *([None] * 10), None) == kkt.KKT_EPOINTER
+
+
+
+# ---------------------------------------------------------------- recursive segmentation (host side)
+def test_nested_plan_structure():
+    """The reduced chain of a nested system is a system of the child plan: p - 1
+    stages, the nest's segment count, couplings read in the parent's hat H region."""
+    kkt = _kkt()
+    plan = kkt.Plan([(64, 8, 3, 8), (40, 6, 0, 4), (200, 5, 2, 20)], nest=[[3], None, [5, 2]])
+    assert plan.reduced(1) is None and plan.nest_depth(1) == 0
+    ch, cs, off = plan.reduced(0)
+    lay = ch.layouts[cs]
+    assert (lay.N, lay.b, lay.ng, lay.p) == (7, 8, 3, 3)
+    assert lay.off_C == plan.layouts[0].off_H
+    assert off % 256 == 0 and off + ch.info.workspace_bytes <= plan.info.workspace_bytes
+    assert plan.nest_depth(0) == 1 and plan.nest_depth(2) == 2
+    ch2, cs2, _ = plan.reduced(2)
+    assert (ch2.layouts[cs2].N, ch2.layouts[cs2].p) == (19, 5)
+    gch, gcs, _ = ch2.reduced(cs2)
+    assert (gch.layouts[gcs].N, gch.layouts[gcs].p) == (4, 2)
+    # the chain of each level follows Eq. 13 with sigma = 19/7
+    from oracle import partition
+    assert ch2.segment_lengths(cs2) == partition.seg_lens(19, 5)
+
+
+def test_nested_plan_rejects_short_chains():
+    kkt = _kkt()
+    for dims, nest in [((40, 6, 0, 4), [3]),        # chain of 3 < 2*3 - 1
+                       ((40, 6, 0, 4), [2, 2]),     # level-1 chain of 1
+                       ((40, 6, 0, 4), [-1]),
+                       ((40, 6, 0, 1), [2])]:       # no chain at all
+        with pytest.raises(kkt.KKTError):
+            kkt.Plan([dims], nest=[nest])
+    # a count <= 1 ends the recursion: nothing is nested
+    assert kkt.Plan([(40, 6, 0, 4)], nest=[[1, 5]]).reduced(0) is None
+
+
+def _split(N, p, t1, tk):
+    """Eq. 13's balance with sigma = tk / t1, floor and ceil candidates (as _est)."""
+    nbar = (N - p + 1) / ((p - 1) + tk / t1)
+    best = None
+    for nk in sorted({int(np.floor(nbar)), int(np.ceil(nbar))}):
+        n1 = N - (p - 1) * (nk + 1)
+        if nk >= 1 and n1 >= 1:
+            cost = max(n1 * t1, nk * tk)
+            if best is None or cost < best[0]:
+                best = (cost, n1, nk)
+    return None if best is None else best[1:]
+
+
+def _chain_best(M, depth, c, m, memo):
+    """Shortest longest path through a reduced chain of M stages: sequential, or
+    segmented (then its own chain, recursively), t_level per extra level."""
+    key = (M, depth)
+    if key in memo:
+        return memo[key]
+    best = (M * m["t_red"][c], [])
+    if depth > 0 and M >= 3:
+        for q in range(2, (M + 1) // 2 + 1):
+            sp = _split(M, q, m["t_first"][c], m["t_fill"][c])
+            if sp is None:
+                continue
+            n1, nk = sp
+            seg = max(m["t_item"][c] + n1 * m["t_first"][c], m["t_item"][c] + nk * m["t_fill"][c])
+            sub, subp = _chain_best(q - 1, depth - 1, c, m, memo)
+            lg = seg + sub + m["t_level"][c]
+            if lg < best[0]:
+                best = (lg, [q] + subp)
+    memo[key] = best
+    return best
+
+
+def test_cost_model_nests_a_long_chain_at_its_optimum():
+    """One long system on an unbounded device: the plan's (p, recursion) reaches
+    the shortest longest path over every p and every recursion, computed here by
+    brute force; with recursion priced out the plan keeps the sequential chain."""
+    kkt = _kkt()
+    N, b, c = 1024, 6, 0
+    m = _model(W=1e12, t_level=40 * 7 / 3 * 8 ** 3)
+    plan = kkt.Plan([(N, b, 4, 0)], cost_model=m)
+    (p,) = plan.segments()
+    memo = {}
+
+    def longest(q):
+        n1, nk = (N, 0) if q == 1 else _split(N, q, m["t_first"][c], m["t_fill"][c])
+        seg = max(n1 * m["t_first"][c], nk * m["t_fill"][c])
+        return seg + (_chain_best(q - 1, 4, c, m, memo)[0] if q > 1 else 0.0)
+
+    opt = min(longest(q) for q in range(1, (N + 1) // 2 + 1))
+    assert longest(p) <= opt * (1 + 1e-12)
+    # the plan's recursion is the one the brute force picks for that chain
+    want = _chain_best(p - 1, 4, c, m, memo)[1]
+    got, pl, s = [], plan, 0
+    while pl.reduced(s) is not None:
+        ch, s, _ = pl.reduced(s)
+        got.append(ch.layouts[s].p)
+        pl = ch
+    assert got == want and len(got) >= 1
+    flat = kkt.Plan([(N, b, 4, 0)], cost_model=_model(W=1e12))
+    assert flat.reduced(0) is None
