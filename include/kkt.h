@@ -173,6 +173,8 @@ int kkt_plan_create_tuned(kkt_plan **plan, int32_t num_systems, const kkt_dims *
 #define KKT_MAX_LEVELS 4
 typedef struct {
     int32_t p[KKT_MAX_LEVELS];
+    int32_t N1[KKT_MAX_LEVELS];   /* first-segment length of each level's chain, as
+                                     kkt_dims.N1 (0: Eq. 13's balance)              */
 } kkt_nest;
 
 /* As kkt_plan_create_tuned (model may be NULL: the default model), with nest[s]

@@ -195,12 +195,55 @@ struct NestArgs {
     const SysDesc *csys;   // child systems
     const int *cstatus;    // child per-system status
     double *cD, *cB, *cCor, *cR;
+    // the child call's start (what its reset kernel would do): tag check, queue
+    // heads, failure indices
+    const long long *ctag;
+    long long cexpect;
+    int *cabort, *cctr, *cfail;
+    int cnctr, cS;
 };
+
+// In thread t < E of a 256-thread workgroup: sum_{k < p} src[k * stride + t]
+// (E <= 256).  Each element's k range is cut into 256 / E slices, each slice
+// keeps eight loads in flight, and the slices meet in LDS.  Every thread calls it.
+__device__ __forceinline__ double strided_sum(const double *src, long long stride, int p, int E, double *lds)
+{
+    if (E <= 0) return 0.0;
+    const int t = threadIdx.x, KS = 256 / E, e = t % E, ks = t / E;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (ks < KS) {
+        int k = ks;
+        for (; k + 7 * KS < p; k += 8 * KS) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += src[(long long)(k + u * KS) * stride + e];
+        }
+        for (; k < p; k += KS) acc[0] += src[(long long)k * stride + e];
+    }
+    __syncthreads();
+    lds[t] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    __syncthreads();
+    double w = 0.0;
+    if (t < E)
+        for (int q = 0; q < KS; ++q) w += lds[q * E + t];
+    __syncthreads();
+    return w;
+}
 
 template <int MODE>
 __global__ void __launch_bounds__(256) kkt_nest_gather(Args a, NestArgs na)
 {
     constexpr bool FACT = MODE == M_FACTOR || MODE == M_FACTOR_SOLVE, RHS = MODE != M_FACTOR;
+    __shared__ double red[256];
+    if (blockIdx.x == 0) {
+        // the start of the child's call (its reset kernel's work)
+        const bool ok = na.ctag[0] == na.cexpect && *a.abort == 0;
+        if (threadIdx.x == 0) *na.cabort = ok ? 0 : 1;
+        if (ok) {
+            for (int i = threadIdx.x; i < na.cnctr; i += 256) na.cctr[i] = 0;
+            if (FACT)
+                for (int i = threadIdx.x; i < na.cS; i += 256) na.cfail[i] = INT_MAX;
+        }
+    }
     if (*a.abort) return;
     const int2 u = na.units[blockIdx.x];
     const int2 pr = na.pairs[u.x];
@@ -227,21 +270,17 @@ __global__ void __launch_bounds__(256) kkt_nest_gather(Args a, NestArgs na)
         const double *sc0 = F + sd.oScr;
         if (FACT) {
             const double *cor = a.corner + sd.oCorner;
-            for (int e = t; e < ng * ng; e += 256) {
-                const int q = e / ng, c = e - q * ng;
-                double v = 0.5 * (cor[e] + cor[c * ng + q]);
-                for (int k = 0; k < sd.p; ++k) v += sc0[(long long)k * sd.scrStride + scr_Rk(b, ng, nr) + e];
-                na.cCor[cd.oCorner + e] = v;
+            const double v = strided_sum(sc0 + scr_Rk(b, ng, nr), sd.scrStride, sd.p, ng * ng, red);
+            if (t < ng * ng) {
+                const int q = t / ng, c = t - q * ng;
+                na.cCor[cd.oCorner + t] = 0.5 * (cor[t] + cor[c * ng + q]) + v;
             }
         }
         if (RHS) {
             const double *rg = a.rhs + sd.oRhs + (long long)sd.N * rb;
             double *Rc = na.cR + cd.oRhs + (long long)cd.N * rb;
-            for (int e = t; e < ng * nr; e += 256) {
-                double v = rg[e];
-                for (int k = 0; k < sd.p; ++k) v += sc0[(long long)k * sd.scrStride + scr_yg(b, ng, nr) + e];
-                Rc[e] = v;
-            }
+            const double v = strided_sum(sc0 + scr_yg(b, ng, nr), sd.scrStride, sd.p, ng * nr, red);
+            if (t < ng * nr) Rc[t] = rg[t] + v;
         }
     }
 }
@@ -280,35 +319,38 @@ __global__ void __launch_bounds__(256) kkt_nest_finish(Args a, NestArgs na)
     const double qnan = __longlong_as_double(0x7ff8000000000000LL);
     double *X = a.rhs + sd.oRhs;
     const double *Xc = na.cR + cd.oRhs;
-    for (int j = 0; j < M; ++j) {
-        const long long o = (long long)sep_of(sd, j + 2) * rb;
-        for (int e = t; e < rb; e += 256) X[o + e] = bad ? qnan : Xc[j * rb + e];
+    // every (separator, entry) pair at once: the loads are independent
+    for (long long e = t; e < (long long)M * rb; e += 256) {
+        const int j = (int)(e / rb);
+        const long long r = e - (long long)j * rb;
+        X[(long long)sep_of(sd, j + 2) * rb + r] = bad ? qnan : Xc[e];
     }
     const long long og = (long long)sd.N * rb, ocg = (long long)M * rb;
     for (int e = t; e < ng * nr; e += 256) X[og + e] = bad ? qnan : Xc[ocg + e];
     if (MODE != M_ADJOINT) return;
-    // lambda (just written, read back from the child) and the primal x
+    // lambda (read from the child's solution) and the primal x
     const double *XP = a.xp + sd.oRhs;
     auto lam = [&](long long o) { return bad ? qnan : Xc[o]; };
-    const long long b2 = (long long)b * b;
-    for (int j = 0; j < M; ++j) {
+    const long long b2 = (long long)b * b, gb = (long long)ng * b;
+    for (long long e = t; e < (long long)M * b2; e += 256) {
+        const int j = (int)(e / b2);
+        const int rc = (int)(e - (long long)j * b2), r = rc / b, c = rc - r * b;
         const int sep = sep_of(sd, j + 2);
         const long long os = (long long)sep * rb, oc = (long long)j * rb;
-        double *dD = a.dD + sd.oD + sep * b2, *dB = a.dB + sd.oB + (long long)sep * ng * b;
-        for (int e = t; e < b2; e += 256) {
-            const int r = e / b, c = e - r * b;
-            double v = 0.0;
-            for (int q = 0; q < nr; ++q)
-                v += lam(oc + r * nr + q) * XP[os + c * nr + q] + XP[os + r * nr + q] * lam(oc + c * nr + q);
-            dD[e] = -0.5 * v;
-        }
-        for (int e = t; e < ng * b; e += 256) {
-            const int g = e / b, c = e - g * b;
-            double v = 0.0;
-            for (int q = 0; q < nr; ++q)
-                v += lam(ocg + g * nr + q) * XP[os + c * nr + q] + XP[og + g * nr + q] * lam(oc + c * nr + q);
-            dB[e] = -v;
-        }
+        double v = 0.0;
+        for (int q = 0; q < nr; ++q)
+            v += lam(oc + r * nr + q) * XP[os + c * nr + q] + XP[os + r * nr + q] * lam(oc + c * nr + q);
+        a.dD[sd.oD + sep * b2 + rc] = -0.5 * v;
+    }
+    for (long long e = t; e < (long long)M * gb; e += 256) {
+        const int j = (int)(e / gb);
+        const int gc = (int)(e - (long long)j * gb), g = gc / b, c = gc - g * b;
+        const int sep = sep_of(sd, j + 2);
+        const long long os = (long long)sep * rb, oc = (long long)j * rb;
+        double v = 0.0;
+        for (int q = 0; q < nr; ++q)
+            v += lam(ocg + g * nr + q) * XP[os + c * nr + q] + XP[og + g * nr + q] * lam(oc + c * nr + q);
+        a.dB[sd.oB + sep * gb + gc] = -v;
     }
     double *dR = a.dcorner + sd.oCorner;
     for (int e = t; e < ng * ng; e += 256) {
@@ -594,6 +636,11 @@ void choose_segments(std::vector<kkt_dims> &dims, std::vector<kkt_nest> &nest, c
         const int c = cls_of[s], p = p_of[{c, dims[s].N}];
         dims[s].p = p;
         estimate(dims[s].N, p, c, m, &chains[c], &nest[s]);
+        // every level of the recursion is split with the balance the estimate assumed
+        for (int l = 0, M = p - 1; l < KKT_MAX_LEVELS && nest[s].p[l] >= 2; M = nest[s].p[l] - 1, ++l) {
+            int N1 = 0, Nk = 0;
+            nest[s].N1[l] = partition_sigma(M, nest[s].p[l], m.t_first[c], m.t_fill[c], &N1, &Nk) ? N1 : 0;
+        }
         int N1 = 0, Nk = 0;
         if (p > 1 && dims[s].N1 == 0 && partition_sigma(dims[s].N, p, m.t_first[c], m.t_fill[c], &N1, &Nk))
             dims[s].N1 = N1;
@@ -773,9 +820,13 @@ bool valid_nest(int p, const kkt_nest &n)
     int M = p - 1;
     for (int l = 0; l < KKT_MAX_LEVELS; ++l) {
         const int q = n.p[l];
-        if (q < 0) return false;
+        if (q < 0 || n.N1[l] < 0) return false;
         if (q <= 1) return true;
         if (M < 2 * q - 1) return false;
+        if (n.N1[l] > 0) {
+            const int rest = M - n.N1[l] - (q - 1);
+            if (rest < q - 1 || rest % (q - 1) != 0) return false;
+        }
         M = q - 1;
     }
     return true;
@@ -962,7 +1013,7 @@ Args base_args(const kkt_plan *plan, void *workspace)
 // forked streams when there are several).  On an error after the fork, the side
 // streams used so far are still joined back into the caller's stream.
 int launch_locked(const kkt_plan *plan, const kkt_plan::Dev *d, int mode, const Args &base, const void *ws,
-                  hipStream_t stream, int *info, bool allow_fork);
+                  hipStream_t stream, int *info, bool allow_fork, bool reset = true);
 
 int launch_mode(const kkt_plan *plan, int mode, const Args &base, const void *ws, hipStream_t stream, int *info,
                 bool need_factor)
@@ -1042,14 +1093,16 @@ int enqueue_classes(const kkt_plan *plan, const kkt_plan::Dev *d, int mode, cons
 // its own call (recursively) and the results are scattered back, and then every
 // class runs phase 3.
 int launch_locked(const kkt_plan *plan, const kkt_plan::Dev *d, int mode, const Args &base, const void *ws,
-                  hipStream_t stream, int *info, bool allow_fork)
+                  hipStream_t stream, int *info, bool allow_fork, bool reset)
 {
     const bool fact = mode == M_FACTOR || mode == M_FACTOR_SOLVE;
     const char *w = (const char *)ws;
-    hipLaunchKernelGGL(kkt_reset, dim3(std::max(1, std::min(1024, (plan->S + 255) / 256))), dim3(256), 0, stream,
-                       (const long long *)(w + plan->o_tag), plan->tag, (int *)(w + plan->o_tag + 16), base.ctr,
-                       4 * (int)plan->cls.size(), fact ? base.failidx : nullptr, plan->S, fact ? info : nullptr);
-    if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
+    if (reset) {
+        hipLaunchKernelGGL(kkt_reset, dim3(std::max(1, std::min(1024, (plan->S + 255) / 256))), dim3(256), 0, stream,
+                           (const long long *)(w + plan->o_tag), plan->tag, (int *)(w + plan->o_tag + 16), base.ctr,
+                           4 * (int)plan->cls.size(), fact ? base.failidx : nullptr, plan->S, fact ? info : nullptr);
+        if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
+    }
     if (!plan->child) return enqueue_classes(plan, d, mode, base, stream, allow_fork, 7, true, true);
     int rc = enqueue_classes(plan, d, mode, base, stream, allow_fork, 3, true, false);
     if (rc != KKT_OK) return rc;
@@ -1066,6 +1119,13 @@ int launch_locked(const kkt_plan *plan, const kkt_plan::Dev *d, int mode, const 
     na.cB = (double *)(w + plan->o_cB);
     na.cCor = (double *)(w + plan->o_cCor);
     na.cR = (double *)(w + plan->o_cR);
+    na.ctag = (const long long *)(cw + ch->o_tag);
+    na.cexpect = ch->tag;
+    na.cabort = (int *)(cw + ch->o_tag + 16);
+    na.cctr = (int *)(cw + ch->o_ctr);
+    na.cnctr = 4 * (int)ch->cls.size();
+    na.cfail = (int *)(cw + ch->o_fail);
+    na.cS = ch->S;
     hipLaunchKernelGGL(nest_kernel(mode, false), dim3((unsigned)plan->nunits.size()), dim3(256), 0, stream, base, na);
     if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
     Args ca = base_args(ch, cw);
@@ -1074,7 +1134,8 @@ int launch_locked(const kkt_plan *plan, const kkt_plan::Dev *d, int mode, const 
     ca.B = na.cB;
     ca.corner = na.cCor;
     ca.rhs = mode != M_FACTOR ? na.cR : nullptr;
-    rc = launch_locked(ch, cdv, mode == M_ADJOINT ? M_SOLVE : mode, ca, cw, stream, nullptr, allow_fork);
+    // the gather kernel has done the child's reset
+    rc = launch_locked(ch, cdv, mode == M_ADJOINT ? M_SOLVE : mode, ca, cw, stream, nullptr, allow_fork, false);
     if (rc != KKT_OK) return rc;
     hipLaunchKernelGGL(nest_kernel(mode, true), dim3((unsigned)plan->npairs.size()), dim3(256), 0, stream, base, na);
     if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
@@ -1226,15 +1287,13 @@ int kkt_plan_create_nested(kkt_plan **out, int32_t S, const kkt_dims *dims_in, c
             const SysDesc &sd = P->sys[s];
             if (sd.p < 2 || nest[s].p[0] < 2) continue;
             kkt_dims cd;
-            cd.N = sd.p - 1; cd.b = sd.b; cd.ng = sd.ng; cd.p = nest[s].p[0]; cd.N1 = 0;
-            if (dims_in[s].p == 0) {
-                // the cost model's balance, as its estimate assumed
-                int N1 = 0, Nk = 0;
-                if (partition_sigma(cd.N, cd.p, m.t_first[sd.cls], m.t_fill[sd.cls], &N1, &Nk)) cd.N1 = N1;
-            }
+            cd.N = sd.p - 1; cd.b = sd.b; cd.ng = sd.ng; cd.p = nest[s].p[0]; cd.N1 = nest[s].N1[0];
             kkt_nest cn;
             std::memset(&cn, 0, sizeof(cn));
-            for (int l = 1; l < KKT_MAX_LEVELS; ++l) cn.p[l - 1] = nest[s].p[l];
+            for (int l = 1; l < KKT_MAX_LEVELS; ++l) {
+                cn.p[l - 1] = nest[s].p[l];
+                cn.N1[l - 1] = nest[s].N1[l];
+            }
             P->child_of[s] = (int)cdims.size();
             P->npairs.push_back(make_int2(s, (int)cdims.size()));
             cdims.push_back(cd);

@@ -1187,6 +1187,20 @@ __device__ __forceinline__ void wave_backward(const Args &a, const SysDesc &sd, 
     gsync<NW>();
 }
 
+// sum_{k < p} src[k * stride], eight loads in flight (the partials of the p
+// segments sit a scratch stride apart)
+__device__ __forceinline__ double sum8(const double *src, long long stride, int p)
+{
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k + 8 <= p; k += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += src[(long long)(k + u) * stride];
+    }
+    for (; k < p; ++k) acc[0] += src[(long long)k * stride];
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
 // ---------------------------------------------------------------- corner
 // tilde R = sym(corner) + sum_k tilde R_k (+ the reduced chain's part) and
 // hat R = chol(tilde R) (Algorithm 1, last lines; Eq. 8d); with FWD also
@@ -1206,8 +1220,7 @@ __device__ __forceinline__ bool corner_factor_w(const Args &a, const SysDesc &sd
     const double *sc0 = a.F + sd.oScr;
     for (int e = tid; e < ng * ng; e += NT) {
         const int q = e / ng, c = e - q * ng;
-        double v = 0.5 * (cor[e] + cor[c * ng + q]);
-        for (int k = 0; k < sd.p; ++k) v += sc0[(long long)k * sd.scrStride + scr_Rk(b, ng, nr) + e];
+        double v = 0.5 * (cor[e] + cor[c * ng + q]) + sum8(sc0 + scr_Rk(b, ng, nr) + e, sd.scrStride, sd.p);
         if (Rred) v += Rred[q * PC + c];
         CR[q * PC + c] = v;
     }
@@ -1215,8 +1228,7 @@ __device__ __forceinline__ bool corner_factor_w(const Args &a, const SysDesc &sd
         const double *rg = a.rhs + sd.oRhs + (long long)N * b * nr;
         for (int e = tid; e < ng * nr; e += NT) {
             const int q = e / nr, j = e - q * nr;
-            double v = rg[e];
-            for (int k = 0; k < sd.p; ++k) v += sc0[(long long)k * sd.scrStride + scr_yg(b, ng, nr) + e];
+            double v = rg[e] + sum8(sc0 + scr_yg(b, ng, nr) + e, sd.scrStride, sd.p);
             if (Yred) v += Yred[q * RP + j];
             CW[q * RP + j] = v;
         }
@@ -1281,8 +1293,7 @@ __device__ __forceinline__ void corner_solve_w(const Args &a, const SysDesc &sd,
     const double *Lg = a.F + sd.oLg;
     for (int e = tid; e < ng * nr; e += NT) {
         const int q = e / nr, j = e - q * nr;
-        double v = rg[e];
-        for (int k = 0; k < sd.p; ++k) v += sc0[(long long)k * sd.scrStride + scr_yg(b, ng, nr) + e];
+        double v = rg[e] + sum8(sc0 + scr_yg(b, ng, nr) + e, sd.scrStride, sd.p);
         if (Yred) v += Yred[q * RP + j];
         CW[q * RP + j] = v;
     }

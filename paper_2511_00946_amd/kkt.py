@@ -29,8 +29,9 @@ MAX_LEVELS = 4
 
 
 class Nest(ctypes.Structure):
-    """Recursive segmentation of one system: p[l] segments of the level-l reduced chain (0 ends it)."""
-    _fields_ = [("p", ctypes.c_int32 * MAX_LEVELS)]
+    """Recursive segmentation of one system: p[l] segments of the level-l reduced
+    chain (0 ends it), N1[l] its first-segment length (0: Eq. 13's balance)."""
+    _fields_ = [("p", ctypes.c_int32 * MAX_LEVELS), ("N1", ctypes.c_int32 * MAX_LEVELS)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -173,7 +174,8 @@ class Plan:
     chain) from ``cost_model`` (a ``CostModel`` or a dict of its fields; None = the
     default model).  ``nest``: per system None or a sequence of segment counts of
     its reduced chain, that chain's reduced chain, ... (recursive segmentation;
-    read for systems with a given p)."""
+    read for systems with a given p); an entry may be a pair (p, N1) to fix that
+    level's first-segment length."""
 
     def __init__(self, dims, nrhs=1, cost_model=None, nest=None, _borrow=None):
         if _borrow is not None:
@@ -197,7 +199,9 @@ class Plan:
                 if len(ps) > MAX_LEVELS:
                     raise ValueError("at most %d levels of recursion" % MAX_LEVELS)
                 for l, q in enumerate(ps):
+                    q, n1 = (q if isinstance(q, (tuple, list)) else (q, 0))
                     narr[i].p[l] = int(q)
+                    narr[i].N1[l] = int(n1)
             cm = None
             if cost_model is not None:
                 cm = cost_model if isinstance(cost_model, CostModel) else CostModel.from_dict(cost_model)

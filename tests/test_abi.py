@@ -348,6 +348,18 @@ def test_nested_plan_rejects_short_chains():
             kkt.Plan([dims], nest=[nest])
     # a count <= 1 ends the recursion: nothing is nested
     assert kkt.Plan([(40, 6, 0, 4)], nest=[[1, 5]]).reduced(0) is None
+    # a level's first-segment length must tile its chain
+    with pytest.raises(kkt.KKTError):
+        kkt.Plan([(64, 8, 3, 8)], nest=[[(3, 2)]])     # chain of 7: 7 - 2 - 2 = 3 is not a multiple of 2
+
+
+def test_nested_plan_honours_first_segment_lengths():
+    kkt = _kkt()
+    plan = kkt.Plan([(130, 5, 2, 16)], nest=[[(4, 6), (2, 1)]])
+    ch, cs, _ = plan.reduced(0)
+    assert ch.segment_lengths(cs) == [6, 2, 2, 2]
+    gch, gcs, _ = ch.reduced(cs)
+    assert gch.segment_lengths(gcs) == [1, 1]
 
 
 def _split(N, p, t1, tk):
