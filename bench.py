@@ -213,6 +213,18 @@ def fd_check(torch, kkt, workloads, dsys, dplan, dev, grads, systems=(0, 511, 10
 SINGLE_P = {"small": (1, 2, 4, 8), "race": (1, 2, 4, 8, 16, 32, 64, 128), "chain": (1, 4, 8, 16, 32)}
 
 
+def nest_levels(plan, s=0):
+    """[(p, N1, Nk)] of system s and of every level of its recursive segmentation."""
+    out, pl = [], plan
+    while True:
+        lay = pl.layouts[s]
+        out.append([lay.p, lay.N1, lay.Nk])
+        r = pl.reduced(s)
+        if r is None:
+            return out
+        pl, s, _ = r
+
+
 def single_systems(torch, kkt, workloads, okkt, dev, cost_model=None, reps=50):
     """Latency of one factor + solve call on the single-system workloads, per
     segment count p and with the p the cost model picks; speedup vs p = 1."""
@@ -256,7 +268,8 @@ def single_systems(torch, kkt, workloads, okkt, dev, cost_model=None, reps=50):
                      "us_per_factor_solve": {str(p): round(v, 2) for p, v in res.items()},
                      "speedup_vs_p1": {str(p): round(base / v, 3) for p, v in res.items()},
                      "cost_model_p": auto,
-                     "cost_model_segments": [tuned.layouts[0].N1, tuned.layouts[0].Nk]}
+                     "cost_model_segments": [tuned.layouts[0].N1, tuned.layouts[0].Nk],
+                     "cost_model_levels": nest_levels(tuned)}
         log("single %s: %s" % (name, {p: round(v, 1) for p, v in res.items()}))
     return out
 

@@ -16,6 +16,10 @@ batches (the library's own kernels, one persistent launch per class):
             a first-segment stage) come from the latency of single systems:
             N = 97 with the first or the second segment one stage long, and
             N = 127 cut into 64 one-stage segments
+  t_level   the fixed cost of one more level of recursive segmentation: the
+            latency of the same N = 127 system with its chain of 63 separators
+            cut into 8 segments, less what its stages cost by the latencies
+            above, in units of t_first
 The result is cached as JSON per GPU architecture.  The chooser itself
 (makespan = max(total work / workers, longest item)) runs in the C library.
 """
@@ -38,7 +42,7 @@ def _cache_path(arch):
     return os.path.join(base, "cost_model_%s.json" % arch)
 
 
-def _time_batch(dims, reps=3):
+def _time_batch(dims, reps=3, nest=None, plan_out=None):
     import torch
     rng = np.random.default_rng(7)
     drawn = {}
@@ -46,7 +50,9 @@ def _time_batch(dims, reps=3):
         if d[:3] not in drawn:
             drawn[d[:3]] = workloads.draw_system(rng, d[0], d[1], d[2], alpha=d[1])
     systems = [drawn[d[:3]] for d in dims]
-    plan = kkt.Plan(dims, nrhs=1)
+    plan = kkt.Plan(dims, nrhs=1, nest=nest)
+    if plan_out is not None:
+        plan_out.append(plan)
     d = kkt.pack_to_device(workloads.pack(systems))
     ws = plan.new_workspace()
     info = torch.zeros(len(dims), dtype=torch.int32, device="cuda")
@@ -71,7 +77,8 @@ def _time_batch(dims, reps=3):
 def calibrate(verbose=False, classes=MEASURED):
     """Measure the classes in `classes`; any other class gets the stage costs of the
     widest measured class scaled by the cube of the block size (the flop ratio)."""
-    model = {k: [0.0] * len(CLASSES) for k in ("t_first", "t_fill", "t_red", "t_item", "workers", "workers_seg")}
+    keys = ("t_first", "t_fill", "t_red", "t_item", "workers", "workers_seg", "t_level")
+    model = {k: [0.0] * len(CLASSES) for k in keys}
     for c, bp in enumerate(CLASSES):
         if bp not in classes:
             continue
@@ -95,12 +102,20 @@ def calibrate(verbose=False, classes=MEASURED):
         lr, _ = _time_batch([(127, b, 2, 64, 1)], reps=5)           # 64 one-stage segments
         rho = max((lr - t0 - max(1.0, sigma) * a) / (63.0 * a), 0.1)
         t_fill, t_red = sigma * t_first, rho * t_first
+        # one more level: the chain of 63 separators cut into 8 segments (Eq. 13)
+        made = []
+        ln, _ = _time_batch([(127, b, 2, 64, 1)], reps=5, nest=[[8]], plan_out=made)
+        ch, cs, _ = made[0].reduced(0)
+        n1, nk = ch.layouts[cs].N1, ch.layouts[cs].Nk
+        stages = t0 + max(1.0, sigma) * a + max(n1 * a, nk * sigma * a) + 7 * rho * a
+        t_level = max(ln - stages, 0.0) * t_first / a
         model["t_first"][c], model["t_fill"][c], model["t_red"][c] = t_first, t_fill, t_red
         model["t_item"][c], model["workers"][c], model["workers_seg"][c] = t_item, float(W), float(Ws)
+        model["t_level"][c] = t_level
         if verbose:
-            print("class %2d: workers %d / %d t_first %.4f t_fill %.4f t_red %.4f t_item %.4f (ms); "
-                  "latency per stage %.4f, sigma %.2f, rho %.2f"
-                  % (bp, W, Ws, t_first, t_fill, t_red, t_item, a, sigma, rho), flush=True)
+            print("class %2d: workers %d / %d t_first %.4f t_fill %.4f t_red %.4f t_item %.4f t_level %.4f (ms); "
+                  "latency per stage %.4f, sigma %.2f, rho %.2f, extra level %.4f"
+                  % (bp, W, Ws, t_first, t_fill, t_red, t_item, t_level, a, sigma, rho, ln - stages), flush=True)
     ref = max(c for c, bp in enumerate(CLASSES) if bp in classes)
     for c, bp in enumerate(CLASSES):
         if bp in classes:
@@ -108,6 +123,7 @@ def calibrate(verbose=False, classes=MEASURED):
         scale = (bp / CLASSES[ref]) ** 3
         for k in ("t_first", "t_fill", "t_red", "t_item"):
             model[k][c] = model[k][ref] * scale
+        model["t_level"][c] = model["t_level"][ref]
         model["workers"][c] = model["workers"][ref]
         model["workers_seg"][c] = model["workers_seg"][ref]
     return model
