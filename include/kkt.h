@@ -142,13 +142,19 @@ int kkt_plan_create(kkt_plan **plan, int32_t num_systems, const kkt_dims *dims, 
  * smallest T that the resulting summed work also meets is kept (systems of one
  * class and length get equal p).  Fixed p are honoured and enter the estimate.
  * The default model follows the flop ratios of Table 1 (7/3, 19/3 and 10/3 b^3
- * per stage, t_level = 64 t_first); a measured one
- * (paper_2511_00946_amd/autotune.py) can be passed. */
+ * per stage, t_level = 64 t_first, family 0); a measured one
+ * (paper_2511_00946_amd/autotune.py, which also times both families of the 24
+ * and 32 classes and keeps the faster) can be passed. */
 typedef struct {
     double t_first[KKT_NUM_CLASSES], t_fill[KKT_NUM_CLASSES], t_red[KKT_NUM_CLASSES], t_item[KKT_NUM_CLASSES];
     double workers[KKT_NUM_CLASSES], workers_seg[KKT_NUM_CLASSES];
     double t_level[KKT_NUM_CLASSES];   /* fixed cost of one more level of recursive
                                           segmentation (its extra launches), below */
+    double family[KKT_NUM_CLASSES];    /* sweep family of the class (the tile shape):
+                                          0 the library's choice, 1 the dense single-wave
+                                          sweeps on 32-wide tiles (classes 24 and 32
+                                          only), 2 the row-lane sweeps on tiles of the
+                                          class's own width                             */
 } kkt_cost_model;
 
 int kkt_plan_create_tuned(kkt_plan **plan, int32_t num_systems, const kkt_dims *dims, int32_t nrhs,

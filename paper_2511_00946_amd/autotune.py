@@ -16,6 +16,10 @@ batches (the library's own kernels, one persistent launch per class):
             a first-segment stage) come from the latency of single systems:
             N = 97 with the first or the second segment one stage long, and
             N = 127 cut into 64 one-stage segments
+  family    (classes 24 and 32) the sweep family, i.e. the tile shape: the dense
+            single-wave sweeps on 32-wide tiles or the row-lane sweeps of the
+            class's width, whichever runs a full batch of 32-stage systems faster;
+            every other figure of the class is measured with it
   t_level   the fixed cost of one more level of recursive segmentation: the
             latency of the same N = 127 system with its chain of 63 separators
             cut into 8 segments, less what its stages cost by the latencies
@@ -42,7 +46,7 @@ def _cache_path(arch):
     return os.path.join(base, "cost_model_%s.json" % arch)
 
 
-def _time_batch(dims, reps=3, nest=None, plan_out=None):
+def _time_batch(dims, reps=3, nest=None, plan_out=None, family=None):
     import torch
     rng = np.random.default_rng(7)
     drawn = {}
@@ -50,7 +54,8 @@ def _time_batch(dims, reps=3, nest=None, plan_out=None):
         if d[:3] not in drawn:
             drawn[d[:3]] = workloads.draw_system(rng, d[0], d[1], d[2], alpha=d[1])
     systems = [drawn[d[:3]] for d in dims]
-    plan = kkt.Plan(dims, nrhs=1, nest=nest)
+    cm = None if family is None else {"family": list(family)}
+    plan = kkt.Plan(dims, nrhs=1, nest=nest, cost_model=cm)
     if plan_out is not None:
         plan_out.append(plan)
     d = kkt.pack_to_device(workloads.pack(systems))
@@ -77,34 +82,51 @@ def _time_batch(dims, reps=3, nest=None, plan_out=None):
 def calibrate(verbose=False, classes=MEASURED):
     """Measure the classes in `classes`; any other class gets the stage costs of the
     widest measured class scaled by the cube of the block size (the flop ratio)."""
-    keys = ("t_first", "t_fill", "t_red", "t_item", "workers", "workers_seg", "t_level")
+    keys = ("t_first", "t_fill", "t_red", "t_item", "workers", "workers_seg", "t_level", "family")
     model = {k: [0.0] * len(CLASSES) for k in keys}
     for c, bp in enumerate(CLASSES):
         if bp not in classes:
             continue
         b = bp
-        _, W = _time_batch([(1, b, 2, 1)] * 8192, reps=1)          # more items than slots: the full grid
+        fam = None
+        if bp in (24, 32):
+            # the tile shape: dense single-wave sweeps on 32-wide tiles or row-lane
+            # sweeps of the class's width, each timed on a full batch of whole systems
+            ft = {}
+            for f in (1, 2):
+                fl = [0.0] * len(CLASSES)
+                fl[c] = float(f)
+                _, Wf = _time_batch([(1, b, 2, 1)] * 8192, reps=1, family=fl)
+                ft[f], _ = _time_batch([(32, b, 2, 1)] * max(1, Wf), family=fl)
+            best = min(ft, key=ft.get)
+            fam = [0.0] * len(CLASSES)
+            fam[c] = float(best)
+            model["family"][c] = float(best)
+            if verbose:
+                print("class %2d: dense sweeps %.3f ms, row-lane sweeps %.3f ms per full batch -> family %d"
+                      % (bp, ft[1], ft[2], best), flush=True)
+        _, W = _time_batch([(1, b, 2, 1)] * 8192, reps=1, family=fam)   # more items than slots: the full grid
         W = max(1, W)
-        _, Ws = _time_batch([(3, b, 2, 2, 1)] * 8192, reps=1)      # two items per system
+        _, Ws = _time_batch([(3, b, 2, 2, 1)] * 8192, reps=1, family=fam)   # two items per system
         Ws = max(2, Ws)
-        t1, _ = _time_batch([(8, b, 2, 1)] * W)
-        t2, _ = _time_batch([(24, b, 2, 1)] * W)
+        t1, _ = _time_batch([(8, b, 2, 1)] * W, family=fam)
+        t2, _ = _time_batch([(24, b, 2, 1)] * W, family=fam)
         t_first = max((t2 - t1) / 16.0, 1e-6)
         t_item = max(t1 - 8 * t_first, 0.0)
         # stage-cost ratios from single-system latencies
-        l33, _ = _time_batch([(33, b, 2, 1)], reps=5)
-        l97, _ = _time_batch([(97, b, 2, 1)], reps=5)
+        l33, _ = _time_batch([(33, b, 2, 1)], reps=5, family=fam)
+        l97, _ = _time_batch([(97, b, 2, 1)], reps=5, family=fam)
         a = max((l97 - l33) / 64.0, 1e-6)                           # latency of a first-segment stage
         t0 = max(l33 - 33 * a, 0.0)
-        lf, _ = _time_batch([(97, b, 2, 2, 1)], reps=5)             # N1 = 1, Nk = 95 (fill rows)
-        lh, _ = _time_batch([(97, b, 2, 2, 95)], reps=5)            # N1 = 95, Nk = 1
+        lf, _ = _time_batch([(97, b, 2, 2, 1)], reps=5, family=fam)   # N1 = 1, Nk = 95 (fill rows)
+        lh, _ = _time_batch([(97, b, 2, 2, 95)], reps=5, family=fam)  # N1 = 95, Nk = 1
         sigma = min(max(1.0 + (lf - lh) / (94.0 * a), 1.0), 8.0)
-        lr, _ = _time_batch([(127, b, 2, 64, 1)], reps=5)           # 64 one-stage segments
+        lr, _ = _time_batch([(127, b, 2, 64, 1)], reps=5, family=fam)  # 64 one-stage segments
         rho = max((lr - t0 - max(1.0, sigma) * a) / (63.0 * a), 0.1)
         t_fill, t_red = sigma * t_first, rho * t_first
         # one more level: the chain of 63 separators cut into 8 segments (Eq. 13)
         made = []
-        ln, _ = _time_batch([(127, b, 2, 64, 1)], reps=5, nest=[[8]], plan_out=made)
+        ln, _ = _time_batch([(127, b, 2, 64, 1)], reps=5, nest=[[8]], plan_out=made, family=fam)
         ch, cs, _ = made[0].reduced(0)
         n1, nk = ch.layouts[cs].N1, ch.layouts[cs].Nk
         stages = t0 + max(1.0, sigma) * a + max(n1 * a, nk * sigma * a) + 7 * rho * a

@@ -659,6 +659,7 @@ kkt_cost_model default_cost_model()
         m.workers[c] = 512.0;
         m.workers_seg[c] = 512.0;
         m.t_level[c] = 64.0 * m.t_first[c];
+        m.family[c] = 0.0;
     }
     return m;
 }
@@ -1243,16 +1244,20 @@ int kkt_plan_create_nested(kkt_plan **out, int32_t S, const kkt_dims *dims_in, c
     // classes: per block-size class the whole systems of the 16/24/32 groups (dense
     // sweeps), then everything else (segmented dense-group systems; all systems of
     // the 8 and 48 groups); items longest first (LPT) inside a class
+    // the sweep family of each class: the dense sweeps where they exist, unless the
+    // cost model chose the row-lane sweeps (family 2)
+    bool dense_ok[NCLS];
+    for (int c = 0; c < NCLS; ++c) dense_ok[c] = dense_capable(CLS_BP[c]) && m.family[c] != 2.0;
     for (int cc = 0; cc < 2 * NCLS; ++cc) {
         const int c = cc >> 1, bp = CLS_BP[c];
         const bool dense = (cc & 1) == 0;
-        if (dense && !dense_capable(bp)) continue;
+        if (dense && !dense_ok[c]) continue;
         std::vector<std::pair<double, int2>> its;
         std::vector<int> reds;
         for (int s = 0; s < S; ++s) {
             if (cls_of[s] != c) continue;
             const SysDesc &sd = P->sys[s];
-            if (dense_capable(bp) && (sd.p == 1) != dense) continue;
+            if (dense_ok[c] && (sd.p == 1) != dense) continue;
             for (int k = 1; k <= sd.p; ++k) its.push_back({item_cost(sd, k), make_int2(s, k)});
             if (sd.p > 1 && nest[s].p[0] < 2) reds.push_back(s);
         }
@@ -1263,7 +1268,7 @@ int kkt_plan_create_nested(kkt_plan **out, int32_t S, const kkt_dims *dims_in, c
         kkt_plan::Cls C;
         C.cls = c;
         C.bp = bp;
-        C.kind = dense ? kkt_plan::K_DENSE : (dense_capable(bp) ? kkt_plan::K_DSEG : kkt_plan::K_WAVE);
+        C.kind = dense ? kkt_plan::K_DENSE : (dense_ok[c] ? kkt_plan::K_DSEG : kkt_plan::K_WAVE);
         C.item_off = (int)P->items.size();
         C.item_cnt = (int)its.size();
         C.red_off = (int)P->red.size();

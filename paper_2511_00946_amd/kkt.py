@@ -56,12 +56,13 @@ class CostModel(ctypes.Structure):
     """Per padded block-size class (8, 16, 24, 32, 48): stage times of first segments,
     fill-carrying segments and reduced stages, item overhead, concurrent items of
     unsegmented systems (workers) and of segmented ones (workers_seg, 0 = workers),
-    and the fixed cost of one more level of recursive segmentation (t_level;
-    64 t_first when a dict leaves it out)."""
+    the fixed cost of one more level of recursive segmentation (t_level;
+    64 t_first when a dict leaves it out), and the sweep family per class (family:
+    0 library choice, 1 dense 32-wide tiles, 2 row-lane; 0 when left out)."""
     _fields_ = [("t_first", ctypes.c_double * NUM_CLASSES), ("t_fill", ctypes.c_double * NUM_CLASSES),
                 ("t_red", ctypes.c_double * NUM_CLASSES), ("t_item", ctypes.c_double * NUM_CLASSES),
                 ("workers", ctypes.c_double * NUM_CLASSES), ("workers_seg", ctypes.c_double * NUM_CLASSES),
-                ("t_level", ctypes.c_double * NUM_CLASSES)]
+                ("t_level", ctypes.c_double * NUM_CLASSES), ("family", ctypes.c_double * NUM_CLASSES)]
 
     @classmethod
     def from_dict(cls, d):
@@ -69,7 +70,7 @@ class CostModel(ctypes.Structure):
         d = dict(d)
         if "t_level" not in d:
             d["t_level"] = [64.0 * float(v) for v in d.get("t_first", [0.0] * NUM_CLASSES)]
-        for k in ("t_first", "t_fill", "t_red", "t_item", "workers", "workers_seg", "t_level"):
+        for k in ("t_first", "t_fill", "t_red", "t_item", "workers", "workers_seg", "t_level", "family"):
             vals = list(d.get(k, [0.0] * NUM_CLASSES))
             if len(vals) != NUM_CLASSES:
                 raise ValueError("cost model field %s needs %d entries, got %d" % (k, NUM_CLASSES, len(vals)))

@@ -425,3 +425,16 @@ def test_cost_model_nests_a_long_chain_at_its_optimum():
     assert got == want and len(got) >= 1
     flat = kkt.Plan([(N, b, 4, 0)], cost_model=_model(W=1e12))
     assert flat.reduced(0) is None
+
+
+def test_cost_model_family_selects_the_sweeps_of_a_class():
+    """family 2 puts the 24 and 32 classes on the row-lane sweeps; 0 and 1 keep the
+    dense sweeps (whole systems) and dense segment sweeps (segmented)."""
+    kkt = _kkt()
+    dims = [(20, 28, 2, 1), (20, 20, 2, 3), (20, 8, 2, 1)]
+    for fam, want in ((0, {1, 2}), (1, {1, 2}), (2, {0})):
+        m = dict(_model(), family=[0.0, 0.0, float(fam), float(fam), 0.0])
+        plan = kkt.Plan(dims, cost_model=m)
+        kinds = dict(zip([c[0] for c in plan.classes()], plan.class_kinds()))
+        got = {k for bp, k in zip([c[0] for c in plan.classes()], plan.class_kinds()) if bp in (24, 32)}
+        assert got == want, (fam, kinds)

@@ -343,3 +343,26 @@ def test_workspaces_keep_their_own_factors():
     plan.init_workspace(wa)
     with pytest.raises(kkt.KKTError):
         plan.solve(wa, pa["r"].clone())
+
+
+def test_row_lane_family_for_the_dense_classes():
+    """The cost model's family 2 runs the 24- and 32-wide classes on the row-lane
+    sweeps (whole and segmented systems, factor then solve): same results."""
+    kkt = _kkt()
+    dims = [(14, 20, 3), (11, 28, 2), (9, 32, 16), (16, 24, 0)]
+    ps = [1, 1, 3, 2]
+    systems = gen(83, dims, nrhs=2)
+    m = {"family": [0.0, 0.0, 2.0, 2.0, 0.0]}
+    _say("gpu case: row-lane family for the 24/32 classes dims=%s" % dims)
+    plan = kkt.Plan([(s.N, s.b, s.ng, p) for s, p in zip(systems, ps)], nrhs=2, cost_model=m)
+    assert set(plan.class_kinds()) == {0}
+    pools = kkt.pack_to_device(workloads.pack(systems))
+    ws = plan.new_workspace()
+    info = torch.zeros(len(systems), dtype=torch.int32, device="cuda")
+    x = pools["r"].clone()
+    plan.factor(pools["D"], pools["C"], pools["B"], pools["corner"], ws, info)
+    plan.solve(ws, x)
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all()
+    check_factor(plan, ws, systems)
+    check_solution(plan, x, systems)
