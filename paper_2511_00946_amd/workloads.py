@@ -168,3 +168,36 @@ def pack_ragged(systems):
     return dict(D=cat([d for s in systems for d in s.D]), C=cat([c for s in systems for c in s.C]),
                 B=cat([b for s in systems for b in s.B]), corner=cat([s.corner for s in systems]),
                 r=cat([s.r for s in systems]))
+
+
+# ---------------------------------------------------------------- multistage QP data
+@dataclass
+class QPData:
+    """A multistage QP (Sec. 2, Eq. 1) with N stages of size b, ng global
+    variables, pe equality and me inequality rows per constraint group, and the
+    positive inequality weights w of one interior-point iteration."""
+    N: int
+    b: int
+    ng: int
+    pe: int
+    me: int
+    arrays: dict
+
+
+def draw_qp(rng, N, b, ng, pe, me, s=0.3):
+    """Q_i = M M^T / b + I (SPD), S_i, T_i, constraint rows ~ N(0, s^2), Qg SPD,
+    weights w ~ U(0.1, 10) (log-uniform), in this order."""
+    M = rng.standard_normal((N, b, b))
+    Q = np.matmul(M, np.swapaxes(M, 1, 2)) / b + np.eye(b)[None]
+    S = s * rng.standard_normal((max(N - 1, 0), b, b))
+    T = s * rng.standard_normal((N, ng, b))
+    R = rng.standard_normal((ng, ng))
+    Qg = R @ R.T / max(ng, 1) + np.eye(ng)
+    EL = s * rng.standard_normal((N, pe, b))
+    ER = s * rng.standard_normal((max(N - 1, 0), pe, b))
+    EG = s * rng.standard_normal((N, pe, ng))
+    IL = s * rng.standard_normal((N, me, b))
+    IR = s * rng.standard_normal((max(N - 1, 0), me, b))
+    IG = s * rng.standard_normal((N, me, ng))
+    w = np.exp(rng.uniform(np.log(0.1), np.log(10.0), size=(N, me)))
+    return QPData(N, b, ng, pe, me, dict(Q=Q, S=S, T=T, Qg=Qg, EL=EL, ER=ER, EG=EG, IL=IL, IR=IR, IG=IG, w=w))

@@ -595,3 +595,92 @@ def test_nested_failure_is_first_in_the_nested_order():
     D[11] = -np.eye(b)   # level-1 segment stage: eliminated before it
     assert kkt.KKTFactor(D, s.C, s.B, s.corner, [3, 3, 3, 3]).info == 8
     assert kkt.KKTFactor(D, s.C, s.B, s.corner, [3, 3, 3, 3], nest=[[1, 1]]).info == 12
+
+
+# ---------------------------------------------------------------- multistage QP -> KKT (scope row f3)
+from oracle import qp as oqp
+
+
+def _qp(seed, N, b, ng, pe, me):
+    return workloads.draw_qp(np.random.default_rng(seed), N, b, ng, pe, me).arrays
+
+
+@pytest.mark.parametrize("N,b,ng,pe,me", [(4, 3, 2, 2, 3), (1, 2, 1, 1, 2), (5, 2, 0, 3, 1)])
+def test_qp_dense_parts_follow_eq1(N, b, ng, pe, me):
+    """The Hessian and the stacked constraint rows reproduce Eq. 1 evaluated term by
+    term at a random point: the coupled stage costs and the terminal cost, and each
+    group's equality and inequality rows."""
+    d = _qp(7 + N, N, b, ng, pe, me)
+    P, A, G = oqp.dense_parts(d)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((N, b))
+    g = rng.standard_normal(ng)
+    z = np.concatenate([x.reshape(-1), g])
+    cost = 0.0
+    for i in range(N - 1):
+        v = np.concatenate([x[i], x[i + 1], g])
+        H = np.zeros((2 * b + ng, 2 * b + ng))
+        H[:b, :b] = d["Q"][i]
+        H[b:2 * b, :b] = d["S"][i]
+        H[:b, b:2 * b] = d["S"][i].T
+        if ng:
+            H[2 * b:, :b] = d["T"][i]
+            H[:b, 2 * b:] = d["T"][i].T
+        cost += 0.5 * v @ H @ v
+    v = np.concatenate([x[N - 1], g])
+    H = np.zeros((b + ng, b + ng))
+    H[:b, :b] = d["Q"][N - 1]
+    if ng:
+        H[b:, :b] = d["T"][N - 1]
+        H[:b, b:] = d["T"][N - 1].T
+        H[b:, b:] = d["Qg"]
+    cost += 0.5 * v @ H @ v
+    assert 0.5 * z @ P @ z == pytest.approx(cost, rel=1e-13)
+    for k in range(N):
+        eq = d["EL"][k] @ x[k] + (d["ER"][k] @ x[k + 1] if k < N - 1 else 0) + (d["EG"][k] @ g if ng else 0)
+        iq = d["IL"][k] @ x[k] + (d["IR"][k] @ x[k + 1] if k < N - 1 else 0) + (d["IG"][k] @ g if ng else 0)
+        np.testing.assert_allclose((A @ z)[k * pe:(k + 1) * pe], eq, rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose((G @ z)[k * me:(k + 1) * me], iq, rtol=1e-13, atol=1e-14)
+
+
+def test_qp_assembly_scalar_closed_form():
+    """One stage of size 1, one equality and one inequality row: Psi is the scalar
+    Q + rho + EL^2 / delta + w IL^2."""
+    d = dict(Q=np.array([[[2.0]]]), S=np.zeros((0, 1, 1)), T=np.zeros((1, 0, 1)), Qg=np.zeros((0, 0)),
+             EL=np.array([[[3.0]]]), ER=np.zeros((0, 1, 1)), EG=np.zeros((1, 1, 0)),
+             IL=np.array([[[-5.0]]]), IR=np.zeros((0, 1, 1)), IG=np.zeros((1, 1, 0)), w=np.array([[0.25]]))
+    D, C, B, corner, _ = oqp.assemble(d, 0.5, 0.1)
+    assert D[0, 0, 0] == pytest.approx(2.0 + 0.5 + 9.0 / 0.1 + 0.25 * 25.0, rel=1e-15)
+
+
+@pytest.mark.parametrize("N,b,ng,pe,me", [(6, 3, 2, 2, 4), (5, 4, 0, 4, 2), (3, 2, 3, 1, 1)])
+def test_qp_psi_is_a_block_tridiagonal_arrow_spd_matrix(N, b, ng, pe, me):
+    d = _qp(20 + N, N, b, ng, pe, me)
+    D, C, B, corner, Psi = oqp.assemble(d, 1e-2, 1e-3)
+    for i in range(N):
+        for j in range(i + 2, N):
+            assert np.max(np.abs(Psi[j * b:(j + 1) * b, i * b:(i + 1) * b])) == 0.0
+    np.testing.assert_allclose(Psi, Psi.T, rtol=0, atol=1e-12 * np.max(np.abs(Psi)))
+    np.linalg.cholesky(Psi)
+    # the block arrays rebuild the same matrix through the KKT oracle's assembly
+    x = np.random.default_rng(3).standard_normal((N * b + ng, 2))
+    np.testing.assert_allclose(kkt.matvec(D, C, B if ng else None, corner, x), Psi @ x, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("N,b,ng,pe,me", [(6, 3, 2, 2, 4), (7, 2, 1, 3, 3), (4, 4, 0, 2, 5)])
+def test_qp_reduced_newton_step_equals_the_full_saddle_point_solve(N, b, ng, pe, me):
+    """Reduce the rhs, solve with Psi (block Cholesky oracle), recover dy and dz: the
+    same step as LAPACK on the unreduced saddle-point matrix, for several rhs."""
+    d = _qp(40 + N, N, b, ng, pe, me)
+    rho, delta = 1e-3, 1e-2
+    rng = np.random.default_rng(5)
+    rx = rng.standard_normal((N * b + ng, 2))
+    ry = rng.standard_normal((N * pe, 2))
+    rz = rng.standard_normal((N * me, 2))
+    D, C, B, corner, _ = oqp.assemble(d, rho, delta)
+    r = oqp.reduce_rhs(d, delta, rx, ry, rz)
+    dx = kkt.solve(D, C, B if ng else None, corner, r, [N])
+    dy, dz = oqp.recover(d, delta, dx, ry, rz)
+    fx, fy, fz = oqp.newton_step_full(d, rho, delta, rx, ry, rz)
+    for got, ref in ((dx, fx), (dy, fy), (dz, fz)):
+        np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-10 * np.max(np.abs(ref)))
