@@ -326,6 +326,62 @@ int kkt_ragged_pad(const kkt_ragged *ragged, const double *D, const double *C, c
  * non-uniform rhs layout (device); enqueued on stream. */
 int kkt_ragged_unpad(const kkt_ragged *ragged, const double *xp, double *x, hipStream_t stream);
 
+/* ---- KKT systems of a multistage QP (Sec. 2, Eq. 1).  The paper takes Psi from
+ * the interior-point solver without deriving it; the reading used here is the
+ * proximal interior-point Newton system
+ *     [ H   A^T   G^T  ] [dx]   [rx]
+ *     [ A  -d I    0   ] [dy] = [ry]      H = P + rho I, d = delta > 0, W = diag(w) > 0,
+ *     [ G    0   -W^-1 ] [dz]   [rz]
+ * (P the Hessian of Eq. 1's cost, A and G its stacked equality and inequality
+ * rows), reduced by eliminating dy = (A dx - ry)/d and dz = W (G dx - rz) to
+ *     Psi dx = rx + A^T ry / d + G^T W rz,   Psi = P + rho I + A^T A / d + G^T W G,
+ * which is SPD with the pattern of Eq. 3.  One interior-point iteration then
+ * assembles Psi, factors it once and solves several right-hand sides
+ * (kkt_qp_reduce_rhs, kkt_solve, kkt_qp_recover).
+ * A system of the plan (N stages of size b, ng globals) gets pe equality and me
+ * inequality rows per constraint group (0 <= pe, me <= KKT_QP_MAX_ROWS); group
+ * k < N-1 couples x_k, x_{k+1} and g, group N-1 (terminal) x_{N-1} and g.  QP pools,
+ * per system, system after system, row-major FP64 (the paper's symbols):
+ *   Q  [N, b, b]    Hessian block of x_i (Q_i; Q_N for the last stage)  - the plan's D layout
+ *   S  [N-1, b, b]  Hessian block (x_{i+1}, x_i) (S_i)                   - the C layout
+ *   T  [N, ng, b]   Hessian block (g, x_i) (T_i; T_N)                   - the B layout
+ *   Qg [ng, ng]     Hessian block of g (Q_g)                            - the corner layout
+ *   EL [N, pe, b], ER [N-1, pe, b], EG [N, pe, ng]   equality rows of group k on
+ *                   x_k (A_k; A_N), on x_{k+1} (B_k), on g (E_k)
+ *   IL [N, me, b], IR [N-1, me, b], IG [N, me, ng]   inequality rows (C_k; D_N),
+ *                   (D_k), (F_k)
+ *   w  [N, me]      positive weights of the inequality rows
+ *   ry [N pe, nrhs], rz [N me, nrhs] (and dy, dz)     vectors of the constraint rows
+ * rx, dx and the reduced rhs use the plan's rhs layout. */
+#define KKT_QP_MAX_ROWS 32
+typedef struct kkt_qp kkt_qp;   /* opaque: layouts and device tables */
+typedef struct {
+    const double *Q, *S, *T, *Qg, *EL, *ER, *EG, *IL, *IR, *IG, *w;   /* device pools */
+} kkt_qp_data;
+
+/* n_eq, n_in: host arrays of the plan's S systems (pe, me).  Allocates the device
+ * tables and a scratch array on the current device (hipMalloc) and synchronises.
+ * KKT_EDIMS for counts out of range (checked before any device call).  Calls on
+ * one kkt_qp share its scratch: they must not overlap in time. */
+int kkt_qp_create(const kkt_plan *plan, const int32_t *n_eq, const int32_t *n_in, kkt_qp **out);
+int kkt_qp_destroy(kkt_qp *qp);
+/* Pool lengths (doubles) of the constraint data and vectors (the cost pools have
+ * the plan's D, C, B and corner lengths). */
+int kkt_qp_lengths(const kkt_qp *qp, int64_t *EL_len, int64_t *ER_len, int64_t *EG_len, int64_t *IL_len,
+                   int64_t *IR_len, int64_t *IG_len, int64_t *w_len, int64_t *ry_len, int64_t *rz_len);
+/* Offsets (doubles) of system s in those pools, in the order of kkt_qp_lengths. */
+int kkt_qp_offsets(const kkt_qp *qp, int32_t s, int64_t offsets[9]);
+/* Psi -> the plan's D, C, B, corner pools (device, written entirely); rho >= 0,
+ * delta > 0.  D may alias Q (and C S, B T, corner Qg).  Enqueued on stream. */
+int kkt_qp_assemble(const kkt_qp *qp, const kkt_qp_data *data, double rho, double delta, double *D, double *C,
+                    double *B, double *corner, hipStream_t stream);
+/* rhs = rx + A^T ry / delta + G^T W rz (the plan's rhs layout; rhs may alias rx). */
+int kkt_qp_reduce_rhs(const kkt_qp *qp, const kkt_qp_data *data, double delta, const double *rx, const double *ry,
+                      const double *rz, double *rhs, hipStream_t stream);
+/* dy = (A dx - ry) / delta, dz = W (G dx - rz). */
+int kkt_qp_recover(const kkt_qp *qp, const kkt_qp_data *data, double delta, const double *dx, const double *ry,
+                   const double *rz, double *dy, double *dz, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,8 @@ HIPCC_FLAGS = [
 
 
 def _units():
-    units = [("kkt", os.path.join(CSRC, "kkt.hip"), []), ("kkt_ragged", os.path.join(CSRC, "kkt_ragged.hip"), [])]
+    units = [("kkt", os.path.join(CSRC, "kkt.hip"), []), ("kkt_ragged", os.path.join(CSRC, "kkt_ragged.hip"), []),
+             ("kkt_qp", os.path.join(CSRC, "kkt_qp.hip"), [])]
     for bp in WAVE_CLASSES:
         # single-wave classes: one instance per right-hand-side count
         for nr in ((1, 4, 8) if bp <= 16 else (8,)):

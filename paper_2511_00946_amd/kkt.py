@@ -79,6 +79,10 @@ class CostModel(ctypes.Structure):
         return m
 
 
+class QPData(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("Q", "S", "T", "Qg", "EL", "ER", "EG", "IL", "IR", "IG", "w")]
+
+
 class KKTError(RuntimeError):
     pass
 
@@ -121,8 +125,17 @@ def lib():
         L.kkt_ragged_lengths.argtypes = [vp] + [ctypes.POINTER(i64)] * 5
         L.kkt_ragged_pad.argtypes = [vp] * 11 + [vp]
         L.kkt_ragged_unpad.argtypes = [vp, vp, vp, vp]
+        L.kkt_qp_create.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(vp)]
+        L.kkt_qp_destroy.argtypes = [vp]
+        L.kkt_qp_lengths.argtypes = [vp] + [ctypes.POINTER(i64)] * 9
+        L.kkt_qp_offsets.argtypes = [vp, i32, ctypes.POINTER(i64)]
+        dbl = ctypes.c_double
+        L.kkt_qp_assemble.argtypes = [vp, ctypes.POINTER(QPData), dbl, dbl, vp, vp, vp, vp, vp]
+        L.kkt_qp_reduce_rhs.argtypes = [vp, ctypes.POINTER(QPData), dbl, vp, vp, vp, vp, vp]
+        L.kkt_qp_recover.argtypes = [vp, ctypes.POINTER(QPData), dbl, vp, vp, vp, vp, vp, vp]
         for name in ("kkt_ragged_create", "kkt_ragged_destroy", "kkt_ragged_lengths", "kkt_ragged_pad",
-                     "kkt_ragged_unpad"):
+                     "kkt_ragged_unpad", "kkt_qp_create", "kkt_qp_destroy", "kkt_qp_lengths", "kkt_qp_offsets",
+                     "kkt_qp_assemble", "kkt_qp_reduce_rhs", "kkt_qp_recover"):
             getattr(L, name).restype = ctypes.c_int
         L.kkt_status_string.restype = ctypes.c_char_p
         L.kkt_status_string.argtypes = [ctypes.c_int]
@@ -140,7 +153,8 @@ EXPORTED = ("kkt_plan_create", "kkt_plan_create_tuned", "kkt_plan_destroy", "kkt
             "kkt_factor_solve", "kkt_solve_adjoint", "kkt_status_string", "kkt_plan_class_info",
             "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error", "kkt_factor_solve_noalloc",
             "kkt_ragged_create", "kkt_ragged_destroy", "kkt_ragged_lengths", "kkt_ragged_pad", "kkt_ragged_unpad",
-            "kkt_plan_create_nested", "kkt_plan_reduced")
+            "kkt_plan_create_nested", "kkt_plan_reduced", "kkt_qp_create", "kkt_qp_destroy", "kkt_qp_lengths",
+            "kkt_qp_offsets", "kkt_qp_assemble", "kkt_qp_reduce_rhs", "kkt_qp_recover")
 
 # bytes of the no-allocation entry point's device array (plans above it are refused)
 NOALLOC_MAX_BYTES = 32 << 20
@@ -438,6 +452,62 @@ class Ragged:
 
     def unpad(self, xp, x, stream=None):
         _check(lib().kkt_ragged_unpad(self._h, _ptr(xp), _ptr(x), _stream(stream)), "kkt_ragged_unpad")
+
+
+class QP:
+    """KKT systems of multistage QPs (Sec. 2, Eq. 1) on a plan: assembly of Psi into
+    the plan's pools, the reduced rhs and the recovery of dy, dz (kkt_qp_*).
+    ``n_eq`` / ``n_in``: equality / inequality rows per constraint group, per system.
+    Pools are device float64 tensors in a dict with keys Q, S, T, Qg (the plan's D,
+    C, B, corner layouts), EL, ER, EG, IL, IR, IG, w."""
+
+    NAMES = ("EL", "ER", "EG", "IL", "IR", "IG", "w", "ry", "rz")
+    MAX_ROWS = 32
+
+    def __init__(self, plan, n_eq, n_in):
+        self.plan = plan
+        ne = (ctypes.c_int32 * plan.S)(*[int(v) for v in n_eq])
+        ni = (ctypes.c_int32 * plan.S)(*[int(v) for v in n_in])
+        h = ctypes.c_void_p()
+        _check(lib().kkt_qp_create(plan._h, ne, ni, ctypes.byref(h)), "kkt_qp_create")
+        self._h = h
+        vals = [ctypes.c_int64() for _ in range(9)]
+        _check(lib().kkt_qp_lengths(h, *[ctypes.byref(v) for v in vals]), "kkt_qp_lengths")
+        self.lengths = {k: int(v.value) for k, v in zip(self.NAMES, vals)}
+        self.offsets = []
+        for s in range(plan.S):
+            arr = (ctypes.c_int64 * 9)()
+            _check(lib().kkt_qp_offsets(h, s, arr), "kkt_qp_offsets")
+            self.offsets.append({k: int(arr[j]) for j, k in enumerate(self.NAMES)})
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.kkt_qp_destroy(h)
+            self._h = None
+
+    @staticmethod
+    def _data(pools):
+        d = QPData()
+        for k, _ in QPData._fields_:
+            p = _ptr(pools.get(k))
+            setattr(d, k, None if p is None else p.value)
+        return d
+
+    def assemble(self, pools, rho, delta, D, C, B, corner, stream=None):
+        d = self._data(pools)
+        _check(lib().kkt_qp_assemble(self._h, ctypes.byref(d), float(rho), float(delta), _ptr(D), _ptr(C), _ptr(B),
+                                     _ptr(corner), _stream(stream)), "kkt_qp_assemble")
+
+    def reduce_rhs(self, pools, delta, rx, ry, rz, rhs, stream=None):
+        d = self._data(pools)
+        _check(lib().kkt_qp_reduce_rhs(self._h, ctypes.byref(d), float(delta), _ptr(rx), _ptr(ry), _ptr(rz),
+                                       _ptr(rhs), _stream(stream)), "kkt_qp_reduce_rhs")
+
+    def recover(self, pools, delta, dx, ry, rz, dy, dz, stream=None):
+        d = self._data(pools)
+        _check(lib().kkt_qp_recover(self._h, ctypes.byref(d), float(delta), _ptr(dx), _ptr(ry), _ptr(rz), _ptr(dy),
+                                    _ptr(dz), _stream(stream)), "kkt_qp_recover")
 
 
 def pack_to_device(pools, device="cuda"):

@@ -201,3 +201,12 @@ def draw_qp(rng, N, b, ng, pe, me, s=0.3):
     IG = s * rng.standard_normal((N, me, ng))
     w = np.exp(rng.uniform(np.log(0.1), np.log(10.0), size=(N, me)))
     return QPData(N, b, ng, pe, me, dict(Q=Q, S=S, T=T, Qg=Qg, EL=EL, ER=ER, EG=EG, IL=IL, IR=IR, IG=IG, w=w))
+
+
+def pack_qp(qps):
+    """QP pools of a batch (system after system, the layouts of the plan and of
+    kkt_qp): Q, S, T, Qg, EL, ER, EG, IL, IR, IG, w as flat float64 arrays."""
+    out = {}
+    for k in ("Q", "S", "T", "Qg", "EL", "ER", "EG", "IL", "IR", "IG", "w"):
+        out[k] = np.concatenate([np.asarray(q.arrays[k], dtype=np.float64).reshape(-1) for q in qps])
+    return out

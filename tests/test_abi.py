@@ -438,3 +438,15 @@ def test_cost_model_family_selects_the_sweeps_of_a_class():
         kinds = dict(zip([c[0] for c in plan.classes()], plan.class_kinds()))
         got = {k for bp, k in zip([c[0] for c in plan.classes()], plan.class_kinds()) if bp in (24, 32)}
         assert got == want, (fam, kinds)
+
+
+def test_qp_refuses_row_counts_out_of_range_on_the_host():
+    import ctypes
+    kkt = _kkt()
+    plan = kkt.Plan([(5, 4, 2, 1), (6, 8, 0, 1)])
+    L = kkt.lib()
+    for ne, ni in (((33, 1), (1, 1)), ((1, 1), (1, -1))):
+        h = ctypes.c_void_p()
+        a = (ctypes.c_int32 * 2)(*ne)
+        b = (ctypes.c_int32 * 2)(*ni)
+        assert L.kkt_qp_create(plan._h, a, b, ctypes.byref(h)) == kkt.KKT_EDIMS
