@@ -274,6 +274,63 @@ def single_systems(torch, kkt, workloads, okkt, dev, cost_model=None, reps=50):
     return out
 
 
+def qp_iteration(torch, kkt, workloads, dev, cost_model=None, reps=30):
+    """One interior-point linear-algebra step of a multistage QP with the race-line
+    system's shape (N 2048, b 6, ng 8, 4 rhs; 6 equality rows per group, the
+    dynamics, and 12 inequality rows, two-sided bounds): assemble Psi, factor it
+    once, then two right-hand-side sets (predictor, corrector), each reduced,
+    solved and its dy, dz recovered.  The plan is the cost model's (recursive
+    segmentation included).  Also the assembly kernel's HBM rate."""
+    N, b, ng, pe, me, nrhs = 2048, 6, 8, 6, 12, 4
+    rng = np.random.default_rng(6)
+    q = workloads.draw_qp(rng, N, b, ng, pe, me)
+    plan = kkt.Plan([(N, b, ng, 0)], nrhs=nrhs, cost_model=cost_model)
+    qp = kkt.QP(plan, [pe], [me])
+    pools = {k: torch.from_numpy(v).to(dev) for k, v in workloads.pack_qp([q]).items()}
+    lens = plan.pool_lengths()
+    z = lambda n: torch.zeros(n, dtype=torch.float64, device=dev)
+    D, C, B, R = z(lens["D"]), z(lens["C"]), z(lens["B"]), z(lens["corner"])
+    ws = plan.new_workspace(dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    vec = [(torch.from_numpy(rng.standard_normal(lens["rhs"])).to(dev),
+            torch.from_numpy(rng.standard_normal(qp.lengths["ry"])).to(dev),
+            torch.from_numpy(rng.standard_normal(qp.lengths["rz"])).to(dev)) for _ in range(2)]
+    x, dy, dz = z(lens["rhs"]), z(qp.lengths["ry"]), z(qp.lengths["rz"])
+    rho, delta = 1e-6, 1e-6
+
+    def step():
+        qp.assemble(pools, rho, delta, D, C, B, R)
+        plan.factor(D, C, B, R, ws, info)
+        for rx, ry, rz in vec:
+            qp.reduce_rhs(pools, delta, rx, ry, rz, x)
+            plan.solve(ws, x)
+            qp.recover(pools, delta, x, ry, rz, dy, dz)
+
+    def assemble_only():
+        qp.assemble(pools, rho, delta, D, C, B, R)
+
+    out = {"shape": "N=%d b=%d ng=%d pe=%d me=%d nrhs=%d" % (N, b, ng, pe, me, nrhs),
+           "levels": nest_levels(plan)}
+    for name, fn in (("us_per_iteration", step), ("us_assembly", assemble_only)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b2.record()
+        torch.cuda.synchronize()
+        out[name] = round(a.elapsed_time(b2) * 1e3 / reps, 2)
+    assert int(info.item()) == 0
+    # assembly bytes: read the cost and constraint pools, write Psi (and the corner partials)
+    rd = sum(int(v.numel()) for v in pools.values()) * 8
+    wr = (lens["D"] + lens["C"] + lens["B"] + lens["corner"] + N * ng * ng) * 8
+    out["assembly_gbps"] = round((rd + wr) / (out["us_assembly"] * 1e-6) / 1e9, 1)
+    log("qp iteration: %s" % out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -500,6 +557,7 @@ def main():
     torch.cuda.empty_cache()
 
     single = None if args.skip_single else single_systems(torch, kkt, workloads, okkt, dev, cost_model)
+    qp_iter = None if args.skip_single else qp_iteration(torch, kkt, workloads, dev, cost_model)
 
     # differentiation workload: forward factor + solve, adjoint backward
     diff = None
@@ -587,6 +645,7 @@ def main():
                                 for c in range(len(classes))},
         "differentiation": diff,
         "single_system": single,
+        "qp_iteration": qp_iter,
         "roofline": roofline,
         "cpu_baseline": {"value": None if cpu_sps is None else round(cpu_sps, 2), "unit": "systems/s", "cores": 1,
                          "kind": "oracle",

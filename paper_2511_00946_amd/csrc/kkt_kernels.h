@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(WC<BP>::NT) kkt_wave_p2(Args a)
         if (FACT) {
             const int rf = any_factor<BP, NR, FWD, true>(a, sd, 0, L);
             __syncthreads();
-            const bool cf = corner_factor_w<NT, FWD>(a, sd, L.nxt, L.nxt + NGM * (NGM + 1), L.racc, L.yg);
+            const bool cf = corner_factor_w<NT, FWD, true>(a, sd, L.nxt, L.nxt + NGM * (NGM + 1), L.racc, L.yg);
             if (threadIdx.x == 0) {
                 const int segf = load_status(&a.failidx[s]);
                 const int v = segf != INT_MAX ? segf : (rf ? rf : (cf ? sd.N + 1 : 0));
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(WC<BP>::NT) kkt_wave_p2(Args a)
             any_forward<BP, NR, true>(a, sd, 0, L);
             __syncthreads();
             info = L.misc[1];
-            corner_solve_w<NT>(a, sd, L.nxt, L.nxt + NGM * (NGM + 1), L.yg);
+            corner_solve_w<NT, true>(a, sd, L.nxt, L.nxt + NGM * (NGM + 1), L.yg);
             if (MODE == M_ADJOINT) corner_grad_w<NT>(a, sd);
             __syncthreads();
             any_backward<BP, NR, MODE == M_ADJOINT, true>(a, sd, 0, L);

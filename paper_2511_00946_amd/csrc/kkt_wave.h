@@ -1208,7 +1208,8 @@ __device__ __forceinline__ double sum8(const double *src, long long stride, int 
 // CR (>= 16 x 17 doubles) and CW (>= 16 x 8) are LDS work areas; Rred (pitch 17)
 // and Yred (pitch 8) hold the reduced chain's arrow partials, or are null.
 // Every thread of the workgroup (NT) calls it; returns true if a pivot failed.
-template <int NT, bool FWD>
+// SEGS: a segmented system (many partials; their sums keep eight loads in flight).
+template <int NT, bool FWD, bool SEGS = false>
 __device__ __forceinline__ bool corner_factor_w(const Args &a, const SysDesc &sd, double *CR, double *CW,
                                                 const double *Rred, const double *Yred)
 {
@@ -1220,7 +1221,12 @@ __device__ __forceinline__ bool corner_factor_w(const Args &a, const SysDesc &sd
     const double *sc0 = a.F + sd.oScr;
     for (int e = tid; e < ng * ng; e += NT) {
         const int q = e / ng, c = e - q * ng;
-        double v = 0.5 * (cor[e] + cor[c * ng + q]) + sum8(sc0 + scr_Rk(b, ng, nr) + e, sd.scrStride, sd.p);
+        double v = 0.5 * (cor[e] + cor[c * ng + q]);
+        if (SEGS) {
+            v += sum8(sc0 + scr_Rk(b, ng, nr) + e, sd.scrStride, sd.p);
+        } else {
+            for (int k = 0; k < sd.p; ++k) v += sc0[(long long)k * sd.scrStride + scr_Rk(b, ng, nr) + e];
+        }
         if (Rred) v += Rred[q * PC + c];
         CR[q * PC + c] = v;
     }
@@ -1228,7 +1234,12 @@ __device__ __forceinline__ bool corner_factor_w(const Args &a, const SysDesc &sd
         const double *rg = a.rhs + sd.oRhs + (long long)N * b * nr;
         for (int e = tid; e < ng * nr; e += NT) {
             const int q = e / nr, j = e - q * nr;
-            double v = rg[e] + sum8(sc0 + scr_yg(b, ng, nr) + e, sd.scrStride, sd.p);
+            double v = rg[e];
+            if (SEGS) {
+                v += sum8(sc0 + scr_yg(b, ng, nr) + e, sd.scrStride, sd.p);
+            } else {
+                for (int k = 0; k < sd.p; ++k) v += sc0[(long long)k * sd.scrStride + scr_yg(b, ng, nr) + e];
+            }
             if (Yred) v += Yred[q * RP + j];
             CW[q * RP + j] = v;
         }
@@ -1280,7 +1291,7 @@ __device__ __forceinline__ bool corner_factor_w(const Args &a, const SysDesc &sd
 }
 
 // Corner solve with the factor in place: tilde y_g, hat y_g, x_g.
-template <int NT>
+template <int NT, bool SEGS = false>
 __device__ __forceinline__ void corner_solve_w(const Args &a, const SysDesc &sd, double *CR, double *CW,
                                                const double *Yred)
 {
@@ -1293,7 +1304,12 @@ __device__ __forceinline__ void corner_solve_w(const Args &a, const SysDesc &sd,
     const double *Lg = a.F + sd.oLg;
     for (int e = tid; e < ng * nr; e += NT) {
         const int q = e / nr, j = e - q * nr;
-        double v = rg[e] + sum8(sc0 + scr_yg(b, ng, nr) + e, sd.scrStride, sd.p);
+        double v = rg[e];
+        if (SEGS) {
+            v += sum8(sc0 + scr_yg(b, ng, nr) + e, sd.scrStride, sd.p);
+        } else {
+            for (int k = 0; k < sd.p; ++k) v += sc0[(long long)k * sd.scrStride + scr_yg(b, ng, nr) + e];
+        }
         if (Yred) v += Yred[q * RP + j];
         CW[q * RP + j] = v;
     }
