@@ -30,8 +30,8 @@ def _gen(seed, dims, nrhs):
     return [workloads.draw_system(rng, N, b, ng, nrhs=nrhs, alpha=b, s_C=0.05, s_B=0.05) for (N, b, ng) in dims]
 
 
-def _run_pair(kkt, L, systems, ps, nrhs):
-    plan = kkt.Plan([(s.N, s.b, s.ng, p) for s, p in zip(systems, ps)], nrhs=nrhs)
+def _run_pair(kkt, L, systems, ps, nrhs, nest=None):
+    plan = kkt.Plan([(s.N, s.b, s.ng, p) for s, p in zip(systems, ps)], nrhs=nrhs, nest=nest)
     pools = kkt.pack_to_device(workloads.pack(systems))
     info1 = torch.full((len(systems),), -7, dtype=torch.int32, device="cuda")
     info2 = torch.full((len(systems),), -7, dtype=torch.int32, device="cuda")
@@ -64,6 +64,18 @@ def test_noalloc_matches_workspace_entry_point_twice():
     _run_pair(kkt, L, small, [2, 1], 2)
     # the first plan again: its tables are copied back in
     _run_pair(kkt, L, big, [4, 1, 2, 3, 1], 2)
+
+
+def test_noalloc_runs_a_nested_plan():
+    """Recursive segmentation through the no-allocation entry point: the child plans'
+    tables and workspaces live in the same device array."""
+    kkt, L = _lib()
+    print("gpu case: no-allocation entry point, nested plan", file=sys.stderr, flush=True)
+    systems = _gen(63, [(130, 5, 2), (61, 16, 4), (20, 8, 0)], 2)
+    plan = _run_pair(kkt, L, systems, [16, 10, 1], 2, nest=[[4, 2], [4], None])
+    assert plan.nest_depth(0) == 2 and plan.nest_depth(1) == 1
+    # and a plain plan after it
+    _run_pair(kkt, L, _gen(64, [(12, 8, 2), (9, 24, 3)], 2), [2, 1], 2)
 
 
 def test_noalloc_refuses_a_plan_larger_than_its_array():
