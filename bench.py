@@ -346,6 +346,8 @@ def main():
                          "-1 = chosen by the default flop-ratio model)")
     ap.add_argument("--skip-diff", action="store_true")
     ap.add_argument("--skip-single", action="store_true", help="skip the single-system latency section")
+    ap.add_argument("--single-only", action="store_true",
+                    help="run only the single-system latencies and the QP iteration (no batch, no headline value)")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration) and exit")
@@ -370,6 +372,13 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "launches": 3}))
+        return
+
+    if args.single_only:
+        from paper_2511_00946_amd import autotune
+        cm = autotune.cost_model()
+        single = single_systems(torch, kkt, workloads, okkt, dev, cm)
+        print(json.dumps({"single_system": single, "qp_iteration": qp_iteration(torch, kkt, workloads, dev, cm)}))
         return
 
     # ------------------------------------------------------------ ragged batch workload
