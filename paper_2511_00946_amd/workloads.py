@@ -210,3 +210,24 @@ def pack_qp(qps):
     for k in ("Q", "S", "T", "Qg", "EL", "ER", "EG", "IL", "IR", "IG", "w"):
         out[k] = np.concatenate([np.asarray(q.arrays[k], dtype=np.float64).reshape(-1) for q in qps])
     return out
+
+
+def draw_qp_problem(rng, N, b, ng, pe, me, s=0.3):
+    """A feasible multistage QP: the data of draw_qp, then c ~ N(0, 1), a point
+    x_f ~ N(0, 1) and slacks u ~ U(0.5, 1.5) with beq = A x_f and h = G x_f + u
+    (stage by stage, g last; the rows of each constraint group in turn)."""
+    q = draw_qp(rng, N, b, ng, pe, me, s)
+    a = q.arrays
+    n = N * b + ng
+    c = rng.standard_normal(n)
+    xf = rng.standard_normal(n)
+    u = rng.uniform(0.5, 1.5, size=N * me)
+    xs, xg = xf[:N * b].reshape(N, b), xf[N * b:]
+    beq = np.zeros(N * pe)
+    h = np.zeros(N * me)
+    for k in range(N):
+        e = a["EL"][k] @ xs[k] + (a["ER"][k] @ xs[k + 1] if k < N - 1 else 0.0) + (a["EG"][k] @ xg if ng else 0.0)
+        g = a["IL"][k] @ xs[k] + (a["IR"][k] @ xs[k + 1] if k < N - 1 else 0.0) + (a["IG"][k] @ xg if ng else 0.0)
+        beq[k * pe:(k + 1) * pe] = e
+        h[k * me:(k + 1) * me] = g + u[k * me:(k + 1) * me]
+    return q, c, beq, h

@@ -684,3 +684,42 @@ def test_qp_reduced_newton_step_equals_the_full_saddle_point_solve(N, b, ng, pe,
     fx, fy, fz = oqp.newton_step_full(d, rho, delta, rx, ry, rz)
     for got, ref in ((dx, fx), (dy, fy), (dz, fz)):
         np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-10 * np.max(np.abs(ref)))
+
+
+# ---------------------------------------------------------------- the interior-point loop (scope row f3)
+from oracle import ipm as oipm
+
+
+def _kkt_residuals(q, c, beq, h, sol):
+    P, A, G = oqp.dense_parts(q.arrays)
+    x, y, z, s = sol["x"], sol["y"], sol["z"], sol["s"]
+    return (np.max(np.abs(P @ x + c + A.T @ y + G.T @ z), initial=0.0), np.max(np.abs(A @ x - beq), initial=0.0),
+            np.max(np.abs(G @ x + s - h), initial=0.0), float(s @ z) / max(1, s.size))
+
+
+@pytest.mark.parametrize("N,b,ng,pe,me", [(5, 3, 2, 1, 4), (8, 2, 1, 1, 3), (4, 4, 0, 2, 6), (6, 3, 2, 2, 0)])
+def test_ipm_reaches_a_kkt_point(N, b, ng, pe, me):
+    """Stationarity, primal feasibility and complementarity at the loop's result
+    (the optimality conditions of the convex QP), with s, z > 0."""
+    q, c, beq, h = workloads.draw_qp_problem(np.random.default_rng(80 + N), N, b, ng, pe, me)
+    sol = oipm.solve(q.arrays, c, beq, h)
+    assert sol["converged"] and sol["iterations"] < 40
+    rd, rp, rs, gap = _kkt_residuals(q, c, beq, h, sol)
+    assert max(rd, rp, rs, gap) < 1e-8
+    if me:
+        assert np.all(sol["s"] > 0) and np.all(sol["z"] > 0)
+
+
+def test_ipm_matches_an_independent_solver():
+    """A tiny strictly convex QP: the same minimiser as scipy's SLSQP on the
+    dense problem."""
+    from scipy.optimize import minimize
+    q, c, beq, h = workloads.draw_qp_problem(np.random.default_rng(91), 3, 2, 1, 1, 2)
+    P, A, G = oqp.dense_parts(q.arrays)
+    sol = oipm.solve(q.arrays, c, beq, h)
+    res = minimize(lambda v: 0.5 * v @ P @ v + c @ v, np.zeros(P.shape[0]), jac=lambda v: P @ v + c, method="SLSQP",
+                   constraints=[{"type": "eq", "fun": lambda v: A @ v - beq, "jac": lambda v: A},
+                                {"type": "ineq", "fun": lambda v: h - G @ v, "jac": lambda v: -G}],
+                   options={"ftol": 1e-14, "maxiter": 500})
+    assert res.success
+    np.testing.assert_allclose(sol["x"], res.x, rtol=0, atol=1e-6)
