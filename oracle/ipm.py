@@ -11,7 +11,12 @@ last), whose Newton systems are the regularised ones of ``oracle.qp`` with the
 proximal centres at the current iterate (the regularisation terms vanish in the
 residuals, so the fixed point is the exact KKT point):
 
-  iterate from x = 0, y = 0, s = 1, z = 1; per iteration
+  start: from x = 0, y = 0, s = z = 1 take the full predictor step (below) and
+  move s and z into the interior by Mehrotra's heuristic (the starting point of
+  primal-dual methods in Nocedal & Wright, Numerical Optimization, Sec. 14.2):
+    s += max(-1.5 min s, 0), z += max(-1.5 min z, 0), then with t = s^T z
+    s += t / (2 sum z), z += t / (2 sum s)   (both shifts from the same s, z);
+  skipped without inequality rows.  Then per iteration
     r_d = P x + c + A^T y + G^T z,   r_p = A x - beq,   r_s = G x + s - h,
     mu = s^T z / m (m inequality rows; 0 without any);
     stop when max(|r_d|, |r_p|, |r_s|)_inf <= tol and mu <= tol;
@@ -53,6 +58,20 @@ def solve(qp, c, beq, h, rho=1e-6, delta=1e-6, tol=1e-9, max_iter=60):
     c, beq, h = (np.asarray(v, dtype=np.float64).reshape(-1) for v in (c, beq, h))
     x, y = np.zeros(n), np.zeros(ma)
     s, z = np.ones(mg), np.ones(mg)
+    if mg:
+        rd = P @ x + c + A.T @ y + G.T @ z
+        rp = A @ x - beq
+        rs = G @ x + s - h
+        w = z / (s + delta * z)
+        rz = -rs + s
+        dx, dy, dz = newton(qp, rho, delta, w, -rd[:, None], -rp[:, None], rz[:, None])
+        x, y = x + dx[:, 0], y + dy[:, 0]
+        s = s + (-rs - rz - dz[:, 0] / w)
+        z = z + dz[:, 0]
+        s = s + max(-1.5 * float(np.min(s)), 0.0)
+        z = z + max(-1.5 * float(np.min(z)), 0.0)
+        t = float(s @ z)
+        s, z = s + 0.5 * t / float(np.sum(z)), z + 0.5 * t / float(np.sum(s))
     hist = []
     converged = False
     it = 0

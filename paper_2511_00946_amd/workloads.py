@@ -185,14 +185,19 @@ class QPData:
 
 
 def draw_qp(rng, N, b, ng, pe, me, s=0.3):
-    """Q_i = M M^T / b + I (SPD), S_i, T_i, constraint rows ~ N(0, s^2), Qg SPD,
-    weights w ~ U(0.1, 10) (log-uniform), in this order."""
+    """S_i, T_i ~ N(0, s^2 / b); Q_i = M M^T / b + (1 + |S_{i-1}| + |S_i| + |T_i|) I and
+    Qg = R R^T / ng + (1 + sum_i |T_i|) I (spectral norms: P is SPD by block
+    Gershgorin, so the QP is strictly convex); constraint rows ~ N(0, s^2);
+    weights w log-uniform in [0.1, 10]; drawn in this order (M, S, T, R, rows, w)."""
     M = rng.standard_normal((N, b, b))
-    Q = np.matmul(M, np.swapaxes(M, 1, 2)) / b + np.eye(b)[None]
-    S = s * rng.standard_normal((max(N - 1, 0), b, b))
-    T = s * rng.standard_normal((N, ng, b))
+    S = s / np.sqrt(b) * rng.standard_normal((max(N - 1, 0), b, b))
+    T = s / np.sqrt(b) * rng.standard_normal((N, ng, b))
     R = rng.standard_normal((ng, ng))
-    Qg = R @ R.T / max(ng, 1) + np.eye(ng)
+    nS = np.array([np.linalg.norm(v, 2) for v in S]) if N > 1 else np.zeros(0)
+    nT = np.array([np.linalg.norm(v, 2) if ng else 0.0 for v in T])
+    margin = 1.0 + nT + np.concatenate([[0.0], nS]) + np.concatenate([nS, [0.0]])
+    Q = np.matmul(M, np.swapaxes(M, 1, 2)) / b + margin[:, None, None] * np.eye(b)[None]
+    Qg = R @ R.T / max(ng, 1) + (1.0 + float(np.sum(nT))) * np.eye(ng)
     EL = s * rng.standard_normal((N, pe, b))
     ER = s * rng.standard_normal((max(N - 1, 0), pe, b))
     EG = s * rng.standard_normal((N, pe, ng))
