@@ -382,6 +382,42 @@ int kkt_qp_reduce_rhs(const kkt_qp *qp, const kkt_qp_data *data, double delta, c
 int kkt_qp_recover(const kkt_qp *qp, const kkt_qp_data *data, double delta, const double *dx, const double *ry,
                    const double *rz, double *dy, double *dz, hipStream_t stream);
 
+/* ---- The interior-point loop around these solves (the paper runs its solver
+ * inside PIQP and does not describe the iteration; the reading used here): a
+ * primal-dual method with Mehrotra's predictor-corrector for
+ *     min 1/2 x^T P x + c^T x   s.t.   A x = beq,   G x + s = h,   s >= 0,
+ * each of whose Newton systems is the regularised one above with the proximal
+ * centres at the current iterate (the regularisation vanishes in the residuals,
+ * so the fixed point is the exact KKT point).  Per iteration, per system: the
+ * residuals r_d = P x + c + A^T y + G^T z, r_p = A x - beq, r_s = G x + s - h and
+ * mu = s^T z / m; a system stops when max |r| <= tol and mu <= tol; otherwise
+ * w = z / (s + delta z), Psi is assembled and factored once, and two right-hand
+ * sides are solved: the predictor (rx, ry, rz) = (-r_d, -r_p, -r_s + s) and the
+ * corrector with rz = -r_s - (-s z + sigma mu - ds_aff dz_aff) / z, sigma =
+ * (mu_aff / mu)^3; ds = -r_s - rz - dz / w; the step is min(1, 0.99 times the
+ * largest step keeping s, z >= 0).  Start: from x = 0, y = 0, s = z = 1 the full
+ * predictor step, then s and z moved into the interior by Mehrotra's heuristic
+ * (s += max(-1.5 min s, 0), likewise z, then s += s^T z / (2 sum z), z += s^T z /
+ * (2 sum s)); systems without inequality rows start at x = 0.
+ * Vectors: c and x in the plan's rhs layout, beq and y in the ry layout, h, z and
+ * s in the rz layout (one column: the plan must have nrhs = 1). */
+typedef struct kkt_ipm kkt_ipm;   /* opaque: work vectors and per-system state */
+
+/* Allocates the work vectors on the current device (hipMalloc, pinned host word).
+ * KKT_EDIMS if the plan has nrhs != 1 or is not qp's plan size.  plan and qp must
+ * outlive it. */
+int kkt_ipm_create(const kkt_plan *plan, const kkt_qp *qp, kkt_ipm **out);
+int kkt_ipm_destroy(kkt_ipm *ipm);
+/* Runs the loop on stream (it synchronises once per iteration to test whether
+ * any system still runs; not capturable).  workspace: initialised for the plan.
+ * data: the QP pools (data->w is not read: the loop keeps its own weights).
+ * x, y, z, s (device) receive the iterates; status (device int32[S]) the
+ * iterations each system took to converge, -1 if a factorization failed, -2 if it
+ * did not converge within max_iter. */
+int kkt_ipm_solve(kkt_ipm *ipm, void *workspace, const kkt_qp_data *data, const double *c, const double *beq,
+                  const double *h, double rho, double delta, double tol, int32_t max_iter, double *x, double *y,
+                  double *z, double *s, int32_t *status, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,14 +41,14 @@ struct QpMax {
 // parts of dx (x_i, x_{i+1}, g).
 struct StageLds {
     double *EL, *ER, *EG, *IL, *IR, *IG, *w, *ERp, *EGp, *IRp, *IGp, *wp;
-    double *ry, *ryp, *rz, *rzp, *xi, *xn, *xg;
+    double *ry, *ryp, *rz, *rzp, *xi, *xn, *xg, *xp;
 };
 
 __host__ __device__ inline size_t stage_lds_doubles(const QpMax &m)
 {
     const size_t PB = (size_t)m.P * m.B, PG = (size_t)m.P * m.G, MB = (size_t)m.M * m.B, MG = (size_t)m.M * m.G;
     return 3 * PB + 2 * PG + 3 * MB + 2 * MG + 2 * (size_t)m.M + 2 * (size_t)m.P * m.R + 2 * (size_t)m.M * m.R +
-           2 * (size_t)m.B * m.R + (size_t)m.G * m.R;
+           3 * (size_t)m.B * m.R + (size_t)m.G * m.R;
 }
 
 __device__ inline StageLds carve(double *p, const QpMax &m)
@@ -73,6 +73,7 @@ __device__ inline StageLds carve(double *p, const QpMax &m)
     L.rzp = p; p += m.M * m.R;
     L.xi = p; p += m.B * m.R;
     L.xn = p; p += m.B * m.R;
+    L.xp = p; p += m.B * m.R;
     L.xg = p;
     return L;
 }
@@ -280,6 +281,275 @@ __global__ void __launch_bounds__(256) qp_recover_k(const QpSys *sys, const int2
     }
 }
 
+// ------------------------------------------------------------------ interior-point loop
+// Residuals of the KKT conditions at (x, y, z, s), one rhs column:
+//   r_d = P x + c + A^T y + G^T z,  r_p = A x - beq,  r_s = G x + s - h.
+// Stage i's rows of r_d (and group i's part of its g rows), and group i's rows of
+// r_p and r_s.  P's blocks are read from the Q, S, T pools where they are used.
+__global__ void __launch_bounds__(256) ipm_resid_k(const QpSys *sys, const int2 *units, QpPtr d, QpMax mx,
+                                                   const double *x, const double *y, const double *z,
+                                                   const double *s, const double *c, const double *beq,
+                                                   const double *h, double *rd, double *rp, double *rs, double *part)
+{
+    extern __shared__ double lds[];
+    const StageLds L = carve(lds, mx);
+    const int2 u = units[blockIdx.x];
+    const QpSys q = sys[u.x];
+    const int i = u.y, b = q.b, ng = q.ng, pe = q.pe, me = q.me, N = q.N, t = threadIdx.x;
+    const bool nx = i + 1 < N, pv = i > 0;
+    stage_rows(L, d, q, i, true, true);
+    stage(L.xi, x + q.oR + (long long)i * b, b, true);
+    stage(L.xn, x + q.oR + (long long)(i + 1) * b, b, nx);
+    stage(L.xp, x + q.oR + (long long)(i - 1) * b, b, pv);
+    stage(L.xg, x + q.oR + (long long)N * b, ng, true);
+    stage(L.ry, y + q.oy + (long long)i * pe, pe, true);
+    stage(L.ryp, y + q.oy + (long long)(i - 1) * pe, pe, pv);
+    stage(L.rz, z + q.oz + (long long)i * me, me, true);
+    stage(L.rzp, z + q.oz + (long long)(i - 1) * me, me, pv);
+    __syncthreads();
+    const long long b2 = (long long)b * b;
+    const double *Qi = d.Q + q.oD + i * b2, *Si = d.S + q.oC + i * b2, *Sp = d.S + q.oC + (i - 1) * b2;
+    const double *Ti = d.T + q.oB + (long long)i * ng * b;
+    for (int r = t; r < b; r += 256) {
+        double v = c[q.oR + (long long)i * b + r];
+        for (int cc = 0; cc < b; ++cc) v += Qi[r * b + cc] * L.xi[cc];
+        if (nx)
+            for (int cc = 0; cc < b; ++cc) v += Si[cc * b + r] * L.xn[cc];
+        if (pv)
+            for (int cc = 0; cc < b; ++cc) v += Sp[r * b + cc] * L.xp[cc];
+        for (int g = 0; g < ng; ++g) v += Ti[g * b + r] * L.xg[g];
+        for (int k = 0; k < pe; ++k) v += L.EL[k * b + r] * L.ry[k] + L.ERp[k * b + r] * L.ryp[k];
+        for (int k = 0; k < me; ++k) v += L.IL[k * b + r] * L.rz[k] + L.IRp[k * b + r] * L.rzp[k];
+        rd[q.oR + (long long)i * b + r] = v;
+    }
+    for (int g = t; g < ng; g += 256) {
+        double v = 0.0;
+        for (int cc = 0; cc < b; ++cc) v += Ti[g * b + cc] * L.xi[cc];
+        for (int k = 0; k < pe; ++k) v += L.EG[k * ng + g] * L.ry[k];
+        for (int k = 0; k < me; ++k) v += L.IG[k * ng + g] * L.rz[k];
+        part[q.oPart + (long long)i * ng + g] = v;
+    }
+    for (int k = t; k < pe; k += 256) {
+        double v = -beq[q.oy + (long long)i * pe + k];
+        for (int cc = 0; cc < b; ++cc) v += L.EL[k * b + cc] * L.xi[cc] + L.ER[k * b + cc] * L.xn[cc];
+        for (int g = 0; g < ng; ++g) v += L.EG[k * ng + g] * L.xg[g];
+        rp[q.oy + (long long)i * pe + k] = v;
+    }
+    for (int k = t; k < me; k += 256) {
+        const long long o = q.oz + (long long)i * me + k;
+        double v = s[o] - h[o];
+        for (int cc = 0; cc < b; ++cc) v += L.IL[k * b + cc] * L.xi[cc] + L.IR[k * b + cc] * L.xn[cc];
+        for (int g = 0; g < ng; ++g) v += L.IG[k * ng + g] * L.xg[g];
+        rs[o] = v;
+    }
+}
+
+// The g rows of r_d: c_g + Qg x_g + the stages' parts (one workgroup per system).
+__global__ void __launch_bounds__(256) ipm_resid_g_k(const QpSys *sys, QpPtr d, const double *x, const double *c,
+                                                     double *rd, const double *part)
+{
+    __shared__ double red[256];
+    const QpSys q = sys[blockIdx.x];
+    const int ng = q.ng, t = threadIdx.x;
+    if (ng == 0) return;
+    const double sum = slice_sum(part + q.oPart, ng, q.N, ng, red);
+    if (t < ng) {
+        const long long og = q.oR + (long long)q.N * q.b;
+        double v = c[og + t] + sum;
+        for (int g = 0; g < ng; ++g) v += d.Qg[q.oCor + t * ng + g] * x[og + g];
+        rd[og + t] = v;
+    }
+}
+
+struct IpmState {
+    double mu;
+    int status;   // 0 running, 1 converged, -1 a factorization failed
+    int iters;
+};
+
+struct IpmVec {
+    double *x, *y, *z, *s, *w;
+    const double *rd, *rp, *rs;
+    double *RX, *RY, *RZ, *X, *DY, *DZ, *DS;
+    const int *info;
+};
+
+// Block-wide reductions over the 256 threads (every thread calls them).
+__device__ inline double block_reduce(double v, double *red, int op)   // 0 sum, 1 max, 2 min
+{
+    const int t = threadIdx.x;
+    __syncthreads();
+    red[t] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            const double a = red[t], bb = red[t + h];
+            red[t] = op == 0 ? a + bb : (op == 1 ? fmax(a, bb) : fmin(a, bb));
+        }
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Largest step in (0, 1] keeping v + a dv >= 0 over one thread's share (min-reduced afterwards).
+__device__ inline double ratio(double v, double dv) { return dv < 0.0 ? -v / dv : 1.0; }
+
+// The vector work of one iteration for one system (one workgroup per system):
+//   PH 0 (after the residuals; PH 4 the same without counting an iteration): mu,
+//        the residual norm, the convergence test; for a
+//        running system the weights w = z / (s + delta z) and the predictor rhs
+//        (rx, ry, rz) = (-r_d, -r_p, -r_s + s); a finished one gets w = 1 and a zero rhs.
+//   PH 1 (after the predictor's solve): ds, the affine step, sigma = (mu_aff / mu)^3
+//        and the corrector's rz = -r_s - (-s z + sigma mu - ds dz) / z.
+//   PH 2 (after the corrector's solve): ds, the step 0.99 * (largest step keeping s,
+//        z >= 0) capped at 1, and the update of x, y, z, s.
+//   PH 3 (the starting point, after a predictor solve from x = 0, s = z = 1): the
+//        full step, then s and z moved into the interior by Mehrotra's heuristic:
+//        s += max(-1.5 min s, 0), z += max(-1.5 min z, 0), and with t = s^T z,
+//        s += t / (2 sum z), z += t / (2 sum s).  Systems without inequality rows
+//        start the loop at x = 0.
+template <int PH>
+__global__ void __launch_bounds__(256) ipm_vec_k(const QpSys *sys, IpmState *state, int *active, IpmVec v,
+                                                 double delta, double tol)
+{
+    __shared__ double red[256];
+    const QpSys q = sys[blockIdx.x];
+    const int t = threadIdx.x;
+    IpmState st = state[blockIdx.x];
+    const long long nx = (long long)q.N * q.b + q.ng, ny = (long long)q.N * q.pe, nz = (long long)q.N * q.me;
+    double *x = v.x + q.oR, *X = v.X + q.oR, *RX = v.RX + q.oR;
+    const double *rd = v.rd + q.oR;
+    double *y = v.y + q.oy, *DY = v.DY + q.oy, *RY = v.RY + q.oy;
+    const double *rp = v.rp + q.oy;
+    double *z = v.z + q.oz, *s = v.s + q.oz, *w = v.w + q.ow, *RZ = v.RZ + q.oz, *DZ = v.DZ + q.oz,
+           *DS = v.DS + q.oz;
+    const double *rs = v.rs + q.oz;
+    if (PH == 0 || PH == 4) {
+        double res = 0.0, sz = 0.0;
+        for (long long e = t; e < nx; e += 256) res = fmax(res, fabs(rd[e]));
+        for (long long e = t; e < ny; e += 256) res = fmax(res, fabs(rp[e]));
+        for (long long e = t; e < nz; e += 256) {
+            res = fmax(res, fabs(rs[e]));
+            sz += s[e] * z[e];
+        }
+        res = block_reduce(res, red, 1);
+        sz = block_reduce(sz, red, 0);
+        const double mu = nz > 0 ? sz / (double)nz : 0.0;
+        bool run = st.status == 0;
+        if (run && res <= tol && mu <= tol) {
+            run = false;
+            if (t == 0) state[blockIdx.x].status = 1;
+        }
+        for (long long e = t; e < nx; e += 256) RX[e] = run ? -rd[e] : 0.0;
+        for (long long e = t; e < ny; e += 256) RY[e] = run ? -rp[e] : 0.0;
+        for (long long e = t; e < nz; e += 256) {
+            w[e] = run ? z[e] / (s[e] + delta * z[e]) : 1.0;
+            RZ[e] = run ? -rs[e] + s[e] : 0.0;
+        }
+        if (t == 0 && run) {
+            state[blockIdx.x].mu = mu;
+            if (PH == 0) state[blockIdx.x].iters = st.iters + 1;
+            atomicAdd(active, 1);
+        }
+        return;
+    }
+    if (st.status != 0) return;
+    if (v.info[blockIdx.x] != 0) {
+        if (PH == 2 && t == 0) state[blockIdx.x].status = -1;
+        return;
+    }
+    if (PH == 3) {
+        if (nz == 0) return;
+        double smin = 1e300, zmin = 1e300;
+        for (long long e = t; e < nx; e += 256) x[e] += X[e];
+        for (long long e = t; e < ny; e += 256) y[e] += DY[e];
+        for (long long e = t; e < nz; e += 256) {
+            s[e] += -rs[e] - RZ[e] - DZ[e] / w[e];
+            z[e] += DZ[e];
+            smin = fmin(smin, s[e]);
+            zmin = fmin(zmin, z[e]);
+        }
+        smin = block_reduce(smin, red, 2);
+        zmin = block_reduce(zmin, red, 2);
+        const double ps = fmax(-1.5 * smin, 0.0), pz = fmax(-1.5 * zmin, 0.0);
+        double tsz = 0.0, ss = 0.0, sumz = 0.0;
+        for (long long e = t; e < nz; e += 256) {
+            s[e] += ps;
+            z[e] += pz;
+            tsz += s[e] * z[e];
+            ss += s[e];
+            sumz += z[e];
+        }
+        tsz = block_reduce(tsz, red, 0);
+        ss = block_reduce(ss, red, 0);
+        sumz = block_reduce(sumz, red, 0);
+        const double hs = 0.5 * tsz / sumz, hz = 0.5 * tsz / ss;
+        for (long long e = t; e < nz; e += 256) {
+            s[e] += hs;
+            z[e] += hz;
+        }
+        return;
+    }
+    double amax = 1.0;
+    for (long long e = t; e < nz; e += 256) {
+        const double ds = -rs[e] - RZ[e] - DZ[e] / w[e];
+        DS[e] = ds;
+        amax = fmin(amax, fmin(ratio(s[e], ds), ratio(z[e], DZ[e])));
+    }
+    amax = block_reduce(amax, red, 2);
+    if (PH == 1) {
+        if (nz == 0) return;
+        double sz = 0.0;
+        for (long long e = t; e < nz; e += 256) sz += (s[e] + amax * DS[e]) * (z[e] + amax * DZ[e]);
+        sz = block_reduce(sz, red, 0);
+        const double mu_aff = sz / (double)nz;
+        const double sg = mu_aff / st.mu, sigma = sg * sg * sg;
+        for (long long e = t; e < nz; e += 256) {
+            const double rc = -s[e] * z[e] + sigma * st.mu - DS[e] * DZ[e];
+            RZ[e] = -rs[e] - rc / z[e];
+        }
+        return;
+    }
+    const double alpha = nz > 0 ? fmin(1.0, 0.99 * amax) : 1.0;
+    for (long long e = t; e < nx; e += 256) x[e] += alpha * X[e];
+    for (long long e = t; e < ny; e += 256) y[e] += alpha * DY[e];
+    for (long long e = t; e < nz; e += 256) {
+        z[e] += alpha * DZ[e];
+        s[e] += alpha * DS[e];
+    }
+}
+
+// The starting point x = 0, y = 0, s = z = 1 and a fresh state.
+__global__ void __launch_bounds__(256) ipm_init_k(const QpSys *sys, IpmState *state, double *x, double *y,
+                                                  double *z, double *s)
+{
+    const QpSys q = sys[blockIdx.x];
+    const int t = threadIdx.x;
+    const long long nx = (long long)q.N * q.b + q.ng, ny = (long long)q.N * q.pe, nz = (long long)q.N * q.me;
+    for (long long e = t; e < nx; e += 256) x[q.oR + e] = 0.0;
+    for (long long e = t; e < ny; e += 256) y[q.oy + e] = 0.0;
+    for (long long e = t; e < nz; e += 256) {
+        z[q.oz + e] = 1.0;
+        s[q.oz + e] = 1.0;
+    }
+    if (t == 0) state[blockIdx.x] = IpmState{0.0, 0, 0};
+}
+
+__global__ void ipm_clear_k(int *active)
+{
+    if (threadIdx.x == 0) *active = 0;
+}
+
+// Per system: iterations to convergence, -1 (a factorization failed) or -2 (not
+// converged within the iteration limit).
+__global__ void __launch_bounds__(256) ipm_status_k(const IpmState *state, int S, int32_t *out)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < S) out[i] = state[i].status == 1 ? state[i].iters : (state[i].status == -1 ? -1 : -2);
+}
+
 bool aligned8(const void *p) { return ((uintptr_t)p & 7) == 0; }
 
 }  // namespace
@@ -482,6 +752,160 @@ int kkt_qp_recover(const kkt_qp *qp, const kkt_qp_data *data, double delta, cons
     if (qp->nunits == 0) return KKT_OK;
     hipLaunchKernelGGL(qp_recover_k, dim3(qp->nunits), dim3(256), qp->lds, stream, qp->dsys, qp->dunits, ptrs(data),
                        qp->mx, 1.0 / delta, dx, ry, rz, dy, dz);
+    return hipGetLastError() == hipSuccess ? KKT_OK : KKT_ELAUNCH;
+}
+
+}  // extern "C"
+
+struct kkt_ipm {
+    const kkt_plan *plan = nullptr;
+    const kkt_qp *qp = nullptr;
+    long long nx = 0, ny = 0, nz = 0, nD = 0, nC = 0, nB = 0, nCor = 0;
+    double *buf = nullptr;
+    IpmState *state = nullptr;
+    int *active = nullptr, *info = nullptr, *h_active = nullptr;
+    ~kkt_ipm()
+    {
+        // teardown: nothing to recover from a failure
+        if (buf) (void)hipFree(buf);
+        if (state) (void)hipFree(state);
+        if (active) (void)hipFree(active);
+        if (info) (void)hipFree(info);
+        if (h_active) (void)hipHostFree(h_active);
+    }
+};
+
+extern "C" {
+
+int kkt_ipm_create(const kkt_plan *plan, const kkt_qp *qp, kkt_ipm **out)
+{
+    if (!plan || !qp || !out) return KKT_EPOINTER;
+    *out = nullptr;
+    kkt_plan_info info;
+    int rc = kkt_plan_get_info(plan, &info);
+    if (rc != KKT_OK) return rc;
+    if (info.nrhs != 1 || info.num_systems != qp->S) return KKT_EDIMS;
+    kkt_ipm *m = new (std::nothrow) kkt_ipm;
+    if (!m) return KKT_EINTERNAL;
+    m->plan = plan;
+    m->qp = qp;
+    m->nx = info.rhs_len; m->ny = qp->len[7]; m->nz = qp->len[8];
+    m->nD = info.D_len; m->nC = info.C_len; m->nB = info.B_len; m->nCor = info.corner_len;
+    const long long total = 3 * m->nx + 3 * m->ny + 5 * m->nz + m->nD + m->nC + m->nB + m->nCor;
+    const bool ok = hipMalloc((void **)&m->buf, sizeof(double) * std::max(1LL, total)) == hipSuccess &&
+                    hipMalloc((void **)&m->state, sizeof(IpmState) * std::max(1, qp->S)) == hipSuccess &&
+                    hipMalloc((void **)&m->active, sizeof(int)) == hipSuccess &&
+                    hipMalloc((void **)&m->info, sizeof(int) * std::max(1, qp->S)) == hipSuccess &&
+                    hipHostMalloc((void **)&m->h_active, sizeof(int), hipHostMallocDefault) == hipSuccess &&
+                    set_lds((const void *)ipm_resid_k, qp->lds) == KKT_OK;
+    if (!ok) {
+        delete m;
+        return KKT_ELAUNCH;
+    }
+    *out = m;
+    return KKT_OK;
+}
+
+int kkt_ipm_destroy(kkt_ipm *ipm)
+{
+    delete ipm;
+    return KKT_OK;
+}
+
+int kkt_ipm_solve(kkt_ipm *ipm, void *workspace, const kkt_qp_data *data, const double *c, const double *beq,
+                  const double *h, double rho, double delta, double tol, int32_t max_iter, double *x, double *y,
+                  double *z, double *s, int32_t *status, hipStream_t stream)
+{
+    if (!ipm || !workspace || !data || !c || !x || !status) return KKT_EPOINTER;
+    const kkt_qp *qp = ipm->qp;
+    if ((ipm->ny && (!beq || !y)) || (ipm->nz && (!h || !z || !s))) return KKT_EPOINTER;
+    if (!(delta > 0.0) || !(rho >= 0.0) || !(tol > 0.0) || max_iter < 0) return KKT_EDIMS;
+    const void *ps[] = {c, beq, h, x, y, z, s};
+    for (const void *p : ps)
+        if (!aligned8(p)) return KKT_EPOINTER;
+    if (qp->nunits == 0) return KKT_OK;
+    // work vectors: r_d, rx, dx (rhs layout); r_p, ry, dy; r_s, rz, dz, ds, w; Psi's pools
+    double *p = ipm->buf;
+    double *rd = p; p += ipm->nx;
+    double *RX = p; p += ipm->nx;
+    double *X = p; p += ipm->nx;
+    double *rp = p; p += ipm->ny;
+    double *RY = p; p += ipm->ny;
+    double *DY = p; p += ipm->ny;
+    double *rs = p; p += ipm->nz;
+    double *RZ = p; p += ipm->nz;
+    double *DZ = p; p += ipm->nz;
+    double *DS = p; p += ipm->nz;
+    double *w = p; p += ipm->nz;
+    double *D = p; p += ipm->nD;
+    double *C = p; p += ipm->nC;
+    double *B = p; p += ipm->nB;
+    double *Cor = p;
+    kkt_qp_data dw = *data;
+    dw.w = w;   // the iteration's own weights
+    const QpPtr d = ptrs(&dw);
+    if (!data_ok(qp, &dw, true, ipm->nD, ipm->nC, ipm->nB, ipm->nCor)) return KKT_EPOINTER;
+    const int S = qp->S;
+    IpmVec v{x, y, z, s, w, rd, rp, rs, RX, RY, RZ, X, DY, DZ, DS, ipm->info};
+    hipLaunchKernelGGL(ipm_init_k, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, x, y, z, s);
+    if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
+    int rc = KKT_OK;
+    // the starting point: a predictor solve from x = 0, s = z = 1, then the shift
+    if (ipm->nz > 0) {
+        hipLaunchKernelGGL(ipm_resid_k, dim3(qp->nunits), dim3(256), qp->lds, stream, qp->dsys, qp->dunits, d, qp->mx,
+                           (const double *)x, (const double *)y, (const double *)z, (const double *)s, c, beq, h, rd,
+                           rp, rs, qp->dpart);
+        hipLaunchKernelGGL(ipm_resid_g_k, dim3(S), dim3(256), 0, stream, qp->dsys, d, (const double *)x, c, rd,
+                           (const double *)qp->dpart);
+        hipLaunchKernelGGL(ipm_vec_k<4>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active, v, delta,
+                           tol);
+        if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
+        rc = kkt_qp_assemble(qp, &dw, rho, delta, D, C, B, Cor, stream);
+        if (rc == KKT_OK) rc = kkt_factor(ipm->plan, D, C, B, Cor, workspace, ipm->info, stream);
+        if (rc == KKT_OK) rc = kkt_qp_reduce_rhs(qp, &dw, delta, RX, RY, RZ, X, stream);
+        if (rc == KKT_OK) rc = kkt_solve(ipm->plan, workspace, X, stream);
+        if (rc == KKT_OK) rc = kkt_qp_recover(qp, &dw, delta, X, RY, RZ, DY, DZ, stream);
+        if (rc != KKT_OK) return rc;
+        hipLaunchKernelGGL(ipm_vec_k<3>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active, v, delta,
+                           tol);
+        if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
+    }
+    for (int it = 0; it <= max_iter && rc == KKT_OK; ++it) {
+        hipLaunchKernelGGL(ipm_clear_k, dim3(1), dim3(64), 0, stream, ipm->active);
+        hipLaunchKernelGGL(ipm_resid_k, dim3(qp->nunits), dim3(256), qp->lds, stream, qp->dsys, qp->dunits, d, qp->mx,
+                           (const double *)x, (const double *)y, (const double *)z, (const double *)s, c, beq, h, rd,
+                           rp, rs, qp->dpart);
+        hipLaunchKernelGGL(ipm_resid_g_k, dim3(S), dim3(256), 0, stream, qp->dsys, d, (const double *)x, c, rd,
+                           (const double *)qp->dpart);
+        hipLaunchKernelGGL(ipm_vec_k<0>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active, v, delta,
+                           tol);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(ipm->h_active, ipm->active, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess) {
+            rc = KKT_ELAUNCH;
+            break;
+        }
+        if (*ipm->h_active == 0 || it == max_iter) break;
+        // one factorization, two solves (predictor, corrector)
+        rc = kkt_qp_assemble(qp, &dw, rho, delta, D, C, B, Cor, stream);
+        if (rc == KKT_OK) rc = kkt_factor(ipm->plan, D, C, B, Cor, workspace, ipm->info, stream);
+        for (int ph = 1; ph <= 2 && rc == KKT_OK; ++ph) {
+            rc = kkt_qp_reduce_rhs(qp, &dw, delta, RX, RY, RZ, X, stream);
+            if (rc == KKT_OK) rc = kkt_solve(ipm->plan, workspace, X, stream);
+            if (rc == KKT_OK) rc = kkt_qp_recover(qp, &dw, delta, X, RY, RZ, DY, DZ, stream);
+            if (rc == KKT_OK) {
+                if (ph == 1)
+                    hipLaunchKernelGGL(ipm_vec_k<1>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active,
+                                       v, delta, tol);
+                else
+                    hipLaunchKernelGGL(ipm_vec_k<2>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active,
+                                       v, delta, tol);
+                if (hipGetLastError() != hipSuccess) rc = KKT_ELAUNCH;
+            }
+        }
+    }
+    if (rc != KKT_OK) return rc;
+    hipLaunchKernelGGL(ipm_status_k, dim3((S + 255) / 256), dim3(256), 0, stream, ipm->state, S, status);
     return hipGetLastError() == hipSuccess ? KKT_OK : KKT_ELAUNCH;
 }
 

@@ -133,9 +133,14 @@ def lib():
         L.kkt_qp_assemble.argtypes = [vp, ctypes.POINTER(QPData), dbl, dbl, vp, vp, vp, vp, vp]
         L.kkt_qp_reduce_rhs.argtypes = [vp, ctypes.POINTER(QPData), dbl, vp, vp, vp, vp, vp]
         L.kkt_qp_recover.argtypes = [vp, ctypes.POINTER(QPData), dbl, vp, vp, vp, vp, vp, vp]
+        L.kkt_ipm_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
+        L.kkt_ipm_destroy.argtypes = [vp]
+        L.kkt_ipm_solve.argtypes = [vp, vp, ctypes.POINTER(QPData), vp, vp, vp, dbl, dbl, dbl, i32, vp, vp, vp, vp,
+                                    vp, vp]
         for name in ("kkt_ragged_create", "kkt_ragged_destroy", "kkt_ragged_lengths", "kkt_ragged_pad",
                      "kkt_ragged_unpad", "kkt_qp_create", "kkt_qp_destroy", "kkt_qp_lengths", "kkt_qp_offsets",
-                     "kkt_qp_assemble", "kkt_qp_reduce_rhs", "kkt_qp_recover"):
+                     "kkt_qp_assemble", "kkt_qp_reduce_rhs", "kkt_qp_recover", "kkt_ipm_create", "kkt_ipm_destroy",
+                     "kkt_ipm_solve"):
             getattr(L, name).restype = ctypes.c_int
         L.kkt_status_string.restype = ctypes.c_char_p
         L.kkt_status_string.argtypes = [ctypes.c_int]
@@ -154,7 +159,8 @@ EXPORTED = ("kkt_plan_create", "kkt_plan_create_tuned", "kkt_plan_destroy", "kkt
             "kkt_plan_class_kind", "kkt_plan_set_class_events", "kkt_workspace_error", "kkt_factor_solve_noalloc",
             "kkt_ragged_create", "kkt_ragged_destroy", "kkt_ragged_lengths", "kkt_ragged_pad", "kkt_ragged_unpad",
             "kkt_plan_create_nested", "kkt_plan_reduced", "kkt_qp_create", "kkt_qp_destroy", "kkt_qp_lengths",
-            "kkt_qp_offsets", "kkt_qp_assemble", "kkt_qp_reduce_rhs", "kkt_qp_recover")
+            "kkt_qp_offsets", "kkt_qp_assemble", "kkt_qp_reduce_rhs", "kkt_qp_recover", "kkt_ipm_create",
+            "kkt_ipm_destroy", "kkt_ipm_solve")
 
 # bytes of the no-allocation entry point's device array (plans above it are refused)
 NOALLOC_MAX_BYTES = 32 << 20
@@ -508,6 +514,38 @@ class QP:
         d = self._data(pools)
         _check(lib().kkt_qp_recover(self._h, ctypes.byref(d), float(delta), _ptr(dx), _ptr(ry), _ptr(rz), _ptr(dy),
                                     _ptr(dz), _stream(stream)), "kkt_qp_recover")
+
+
+class IPM:
+    """The interior-point loop of kkt_ipm_* on a plan (nrhs = 1) and its QP object:
+    solve() runs it and returns the iterates (device tensors) and, per system, the
+    iterations to convergence (-1 factorization failure, -2 not converged)."""
+
+    def __init__(self, plan, qp):
+        self.plan, self.qp = plan, qp
+        h = ctypes.c_void_p()
+        _check(lib().kkt_ipm_create(plan._h, qp._h, ctypes.byref(h)), "kkt_ipm_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.kkt_ipm_destroy(h)
+            self._h = None
+
+    def solve(self, ws, pools, c, beq, h, rho=1e-6, delta=1e-6, tol=1e-9, max_iter=60, stream=None):
+        import torch
+        dev = c.device
+        x = torch.empty(self.plan.info.rhs_len, dtype=torch.float64, device=dev)
+        y = torch.empty(self.qp.lengths["ry"], dtype=torch.float64, device=dev)
+        z = torch.empty(self.qp.lengths["rz"], dtype=torch.float64, device=dev)
+        s = torch.empty_like(z)
+        status = torch.empty(self.plan.S, dtype=torch.int32, device=dev)
+        d = QP._data(pools)
+        _check(lib().kkt_ipm_solve(self._h, _ptr(ws), ctypes.byref(d), _ptr(c), _ptr(beq), _ptr(h), float(rho),
+                                   float(delta), float(tol), int(max_iter), _ptr(x), _ptr(y), _ptr(z), _ptr(s),
+                                   _ptr(status), _stream(stream)), "kkt_ipm_solve")
+        return dict(x=x, y=y, z=z, s=s, status=status)
 
 
 def pack_to_device(pools, device="cuda"):
