@@ -9,7 +9,11 @@ method with Mehrotra's predictor-corrector on
 (P, A, G from ``oracle.qp.dense_parts``; c, beq, h stacked stage by stage, g
 last), whose Newton systems are the regularised ones of ``oracle.qp`` with the
 proximal centres at the current iterate (the regularisation terms vanish in the
-residuals, so the fixed point is the exact KKT point):
+residuals, so the fixed point is the exact KKT point).  The regularisation falls
+as the iterate converges, as proximal methods do: the start step uses rho_0 and
+delta_0, iteration k uses rho_0 f, delta_0 f with f = max(1e-4, 10^-(k+1)) (a
+fixed delta leaves an equality residual of about delta |dy| per step, which
+contracts ever more slowly as the horizon grows).
 
   start: from x = 0, y = 0, s = z = 1 take the full predictor step (below) and
   move s and z into the interior by Mehrotra's heuristic (the starting point of
@@ -87,10 +91,12 @@ def solve(qp, c, beq, h, rho=1e-6, delta=1e-6, tol=1e-9, max_iter=60):
             break
         if it == max_iter:
             break
-        w = z / (s + delta * z)
+        f = max(1e-4, 10.0 ** -(it + 1))
+        rk, dk = rho * f, delta * f
+        w = z / (s + dk * z)
         rx, ry = -rd, -rp
         rz = -rs + s
-        dx, dy, dz = newton(qp, rho, delta, w, rx[:, None], ry[:, None], rz[:, None])
+        dx, dy, dz = newton(qp, rk, dk, w, rx[:, None], ry[:, None], rz[:, None])
         dx, dy, dz = dx[:, 0], dy[:, 0], dz[:, 0]
         ds = -rs - rz - dz / w
         if mg:
@@ -99,7 +105,7 @@ def solve(qp, c, beq, h, rho=1e-6, delta=1e-6, tol=1e-9, max_iter=60):
             sigma = (mu_aff / mu) ** 3
             rc = -s * z + sigma * mu - ds * dz
             rz = -rs - rc / z
-            dx, dy, dz = newton(qp, rho, delta, w, rx[:, None], ry[:, None], rz[:, None])
+            dx, dy, dz = newton(qp, rk, dk, w, rx[:, None], ry[:, None], rz[:, None])
             dx, dy, dz = dx[:, 0], dy[:, 0], dz[:, 0]
             ds = -rs - rz - dz / w
             alpha = min(1.0, 0.99 * min(_step_to_boundary(s, ds), _step_to_boundary(z, dz)))
