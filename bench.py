@@ -331,6 +331,49 @@ def qp_iteration(torch, kkt, workloads, dev, cost_model=None, reps=30):
     return out
 
 
+def qp_solves(torch, kkt, workloads, dev, cost_model=None, reps=3):
+    """Whole interior-point solves (kkt_ipm_solve, every step on the device) of
+    feasible strictly convex multistage QPs: one with the race-line system's shape
+    (N 2048, b 6, ng 8, 6 equality and 12 inequality rows per group) on the cost
+    model's plan, and a batch of 512 small ones (N 64, b 8, ng 2, 4 and 8 rows)."""
+    out = {}
+    for name, shape, count in (("race", (2048, 6, 8, 6, 12), 1), ("batch512", (64, 8, 2, 4, 8), 512)):
+        rng = np.random.default_rng(7)
+        probs = [workloads.draw_qp_problem(rng, *shape) for _ in range(count)]
+        qps = [p[0] for p in probs]
+        N, b, ng, pe, me = shape
+        plan = kkt.Plan([(N, b, ng, 0)] * count, nrhs=1, cost_model=cost_model)
+        qp = kkt.QP(plan, [pe] * count, [me] * count)
+        pools = {k: torch.from_numpy(v).to(dev) for k, v in workloads.pack_qp(qps).items()}
+        c = np.zeros(plan.info.rhs_len)
+        beq = np.zeros(qp.lengths["ry"])
+        h = np.zeros(qp.lengths["rz"])
+        for i, (q, cv, bv, hv) in enumerate(probs):
+            lay, off = plan.layouts[i], qp.offsets[i]
+            c[lay.off_rhs:lay.off_rhs + cv.size] = cv
+            beq[off["ry"]:off["ry"] + bv.size] = bv
+            h[off["rz"]:off["rz"] + hv.size] = hv
+        cd, bd, hd = (torch.from_numpy(v).to(dev) for v in (c, beq, h))
+        ipm = kkt.IPM(plan, qp)
+        ws = plan.new_workspace(dev)
+        res = ipm.solve(ws, pools, cd, bd, hd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res = ipm.solve(ws, pools, cd, bd, hd)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        st = res["status"].cpu().numpy()
+        assert (st >= 0).all(), "interior-point solve did not converge: %s" % st[:8]
+        its = float(np.mean(st))
+        out[name] = {"shape": "%d x (N=%d b=%d ng=%d pe=%d me=%d)" % (count, N, b, ng, pe, me),
+                     "ms_per_solve": round(ms, 3), "iterations_mean": round(its, 2),
+                     "ms_per_iteration": round(ms / max(its, 1.0), 3),
+                     "qps_per_s": round(count / (ms * 1e-3), 1), "levels": nest_levels(plan)}
+    log("qp solves: %s" % out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -378,7 +421,8 @@ def main():
         from paper_2511_00946_amd import autotune
         cm = autotune.cost_model()
         single = single_systems(torch, kkt, workloads, okkt, dev, cm)
-        print(json.dumps({"single_system": single, "qp_iteration": qp_iteration(torch, kkt, workloads, dev, cm)}))
+        print(json.dumps({"single_system": single, "qp_iteration": qp_iteration(torch, kkt, workloads, dev, cm),
+                          "qp_solve": qp_solves(torch, kkt, workloads, dev, cm)}))
         return
 
     # ------------------------------------------------------------ ragged batch workload
@@ -567,6 +611,7 @@ def main():
 
     single = None if args.skip_single else single_systems(torch, kkt, workloads, okkt, dev, cost_model)
     qp_iter = None if args.skip_single else qp_iteration(torch, kkt, workloads, dev, cost_model)
+    qp_solve = None if args.skip_single else qp_solves(torch, kkt, workloads, dev, cost_model)
 
     # differentiation workload: forward factor + solve, adjoint backward
     diff = None
@@ -655,6 +700,7 @@ def main():
         "differentiation": diff,
         "single_system": single,
         "qp_iteration": qp_iter,
+        "qp_solve": qp_solve,
         "roofline": roofline,
         "cpu_baseline": {"value": None if cpu_sps is None else round(cpu_sps, 2), "unit": "systems/s", "cores": 1,
                          "kind": "oracle",

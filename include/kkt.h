@@ -398,7 +398,9 @@ int kkt_qp_recover(const kkt_qp *qp, const kkt_qp_data *data, double delta, cons
  * largest step keeping s, z >= 0).  Start: from x = 0, y = 0, s = z = 1 the full
  * predictor step, then s and z moved into the interior by Mehrotra's heuristic
  * (s += max(-1.5 min s, 0), likewise z, then s += s^T z / (2 sum z), z += s^T z /
- * (2 sum s)); systems without inequality rows start at x = 0.
+ * (2 sum s)); systems without inequality rows start at x = 0.  rho and delta are
+ * the regularisation of the start step; iteration k uses them times
+ * max(1e-4, 10^-(k+1)) (proximal methods shrink it as they converge).
  * Vectors: c and x in the plan's rhs layout, beq and y in the ry layout, h, z and
  * s in the rz layout (one column: the plan must have nrhs = 1). */
 typedef struct kkt_ipm kkt_ipm;   /* opaque: work vectors and per-system state */

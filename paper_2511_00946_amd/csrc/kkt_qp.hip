@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 #include <vector>
 
@@ -871,13 +872,16 @@ int kkt_ipm_solve(kkt_ipm *ipm, void *workspace, const kkt_qp_data *data, const 
         if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
     }
     for (int it = 0; it <= max_iter && rc == KKT_OK; ++it) {
+        // the regularisation falls tenfold per iteration, to 1e-4 of its start
+        const double f = std::max(1e-4, std::pow(10.0, -(double)(it + 1)));
+        const double rk = rho * f, dk = delta * f;
         hipLaunchKernelGGL(ipm_clear_k, dim3(1), dim3(64), 0, stream, ipm->active);
         hipLaunchKernelGGL(ipm_resid_k, dim3(qp->nunits), dim3(256), qp->lds, stream, qp->dsys, qp->dunits, d, qp->mx,
                            (const double *)x, (const double *)y, (const double *)z, (const double *)s, c, beq, h, rd,
                            rp, rs, qp->dpart);
         hipLaunchKernelGGL(ipm_resid_g_k, dim3(S), dim3(256), 0, stream, qp->dsys, d, (const double *)x, c, rd,
                            (const double *)qp->dpart);
-        hipLaunchKernelGGL(ipm_vec_k<0>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active, v, delta,
+        hipLaunchKernelGGL(ipm_vec_k<0>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active, v, dk,
                            tol);
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(ipm->h_active, ipm->active, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
@@ -887,19 +891,19 @@ int kkt_ipm_solve(kkt_ipm *ipm, void *workspace, const kkt_qp_data *data, const 
         }
         if (*ipm->h_active == 0 || it == max_iter) break;
         // one factorization, two solves (predictor, corrector)
-        rc = kkt_qp_assemble(qp, &dw, rho, delta, D, C, B, Cor, stream);
+        rc = kkt_qp_assemble(qp, &dw, rk, dk, D, C, B, Cor, stream);
         if (rc == KKT_OK) rc = kkt_factor(ipm->plan, D, C, B, Cor, workspace, ipm->info, stream);
         for (int ph = 1; ph <= 2 && rc == KKT_OK; ++ph) {
-            rc = kkt_qp_reduce_rhs(qp, &dw, delta, RX, RY, RZ, X, stream);
+            rc = kkt_qp_reduce_rhs(qp, &dw, dk, RX, RY, RZ, X, stream);
             if (rc == KKT_OK) rc = kkt_solve(ipm->plan, workspace, X, stream);
-            if (rc == KKT_OK) rc = kkt_qp_recover(qp, &dw, delta, X, RY, RZ, DY, DZ, stream);
+            if (rc == KKT_OK) rc = kkt_qp_recover(qp, &dw, dk, X, RY, RZ, DY, DZ, stream);
             if (rc == KKT_OK) {
                 if (ph == 1)
                     hipLaunchKernelGGL(ipm_vec_k<1>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active,
-                                       v, delta, tol);
+                                       v, dk, tol);
                 else
                     hipLaunchKernelGGL(ipm_vec_k<2>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active,
-                                       v, delta, tol);
+                                       v, dk, tol);
                 if (hipGetLastError() != hipSuccess) rc = KKT_ELAUNCH;
             }
         }
