@@ -75,3 +75,25 @@ def test_ipm_batch_matches_the_oracle_loop():
         assert max(np.max(np.abs(rd)), np.max(np.abs(rp), initial=0.0), np.max(np.abs(rs), initial=0.0), gap) < 1e-8, s
         if hv.size:
             assert np.all(got["s"] > 0) and np.all(got["z"] > 0)
+
+
+def test_ipm_on_a_nested_plan():
+    """The loop on a recursively segmented plan (the race-line shape at N 130, its
+    chain segmented twice): the same minimiser as the oracle loop."""
+    from paper_2511_00946_amd import kkt
+    q, cv, bv, hv = workloads.draw_qp_problem(np.random.default_rng(77), 130, 6, 8, 6, 12)
+    plan = kkt.Plan([(130, 6, 8, 16)], nrhs=1, nest=[[4, 2]])
+    assert plan.nest_depth(0) == 2
+    qp = kkt.QP(plan, [6], [12])
+    pools = {k: torch.from_numpy(v).cuda() for k, v in workloads.pack_qp([q]).items()}
+    ipm = kkt.IPM(plan, qp)
+    ws = plan.new_workspace()
+    print("gpu case: interior-point loop on a nested plan", file=sys.stderr, flush=True)
+    out = ipm.solve(ws, pools, *(torch.from_numpy(v).cuda() for v in (cv, bv, hv)))
+    torch.cuda.synchronize()
+    ref = oipm.solve(q.arrays, cv, bv, hv)
+    assert ref["converged"]
+    st = int(out["status"].cpu().numpy()[0])
+    assert st >= 0 and abs(st - ref["iterations"]) <= 1, (st, ref["iterations"])
+    x = out["x"].cpu().numpy()[:cv.size]
+    assert float(np.max(np.abs(x - ref["x"]))) / max(1.0, float(np.max(np.abs(ref["x"])))) < 1e-6
