@@ -203,7 +203,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
     const long long b2 = (long long)b * b;
     double *F = a.F;
     double *RA = L.P;                 // Dw -> L (store staging) -> hat E -> next Dw
-    double *RB = L.P + DB * PD;       // L^{-1}
+    double *RB = L.P + DB * PD;       // L^{-T}: row j holds column j of L^{-1}
     double *RG = L.P + 2 * DB * PD;   // Gw -> hat G -> next Gw (16 rows)
     double *RF = RG + NGM * PD;       // SEG, k >= 2: fill rows Fw -> hat B^T -> next Fw
     double *RAA = RF + DB * PD;       //              hat A_k accumulator
@@ -320,46 +320,65 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                 vec[c] = isP ? 0.5 * (lo[c] + up[c]) : ((isI && c == ri) ? 1.0 : 0.0);
         }
         bool bad = false;
-        // Every lane writes its column entry each step, the lanes that hold no
-        // entry of the column into a slot of their own: the step stays one basic
+        // Every lane applies every step unmasked.  A row lane at or above the pivot
+        // then only changes entries right of its diagonal, which no later step reads
+        // and the staging of L clears; an inverse lane right of the pivot holds an
+        // exact zero in row c, so its multiplier and update are exact zeros.  Every
+        // row lane writes its column entry each step (the slots above the pivot are
+        // not read), the other lanes a slot of their own: the step stays one basic
         // block, so all its LDS reads are issued together ahead of their use.
         double *const dummy = L.col + 2 * DB + lane_s;
         *(isP ? buf0 + ri : dummy) = vec[0];
+        double *const wr0 = isP ? buf0 + ri : dummy, *const wr1 = isP ? buf1 + ri : dummy;
+        const int dkey = isP ? ri : -1;
         wave_sync();
         double col[DB];
 #pragma unroll
         for (int l = 0; l < DB; ++l) col[l] = buf0[l];
-#pragma unroll
-        for (int c = 0; c < DB; ++c) {
+        // the pivot's square root and its inverse, one step ahead
+        double d, inv;
+        bad |= !(col[0] > 0.0) || !isfinite(col[0]);
+        sqrt_rsqrt(col[0], d, inv);
+        static_for<0, DB>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
             double *nxt = (c & 1) ? buf0 : buf1;
-            const double dcc = col[c];
-            bad |= !(dcc > 0.0) || !isfinite(dcc);
-            double d, inv;
-            sqrt_rsqrt(dcc, d, inv);
             // row lanes below the pivot scale their entry of column c to L[ri][c];
             // inverse lanes at or left of the pivot form X[c][ri] = acc[c] / L[c][c]
             const double v = vec[c] * inv;
-            const bool act = isP ? (ri > c) : (isI && ri <= c);
-            const double f = act ? v * inv : 0.0;
-            vec[c] = (isP && ri == c) ? d : (act ? v : vec[c]);
-            if (c + 1 < DB) {
+            const double f = v * inv;
+            vec[c] = (dkey == c) ? d : v;
+            if constexpr (c + 1 < DB) {
                 // the next pivot column first: it is written and read back (a wave's
-                // LDS accesses complete in order) before the remaining updates of this
-                // step, which then overlap the round trip
+                // LDS accesses complete in order) while the remaining updates of this
+                // step run; the next pivot itself comes straight from its row lane,
+                // so its square root does not wait for the LDS round trip
                 vec[c + 1] = fma(-f, col[c + 1], vec[c + 1]);
-                *((isP && ri >= c + 1) ? nxt + ri : dummy) = vec[c + 1];
+                const double pn = readlane_d(vec[c + 1], c + 1);
+                *((c & 1) ? wr0 : wr1) = vec[c + 1];
                 wave_sync();
                 double coln[DB];
 #pragma unroll
                 for (int l = c + 1; l < DB; ++l) coln[l] = nxt[l];
                 __builtin_amdgcn_sched_barrier(0);
+                bad |= !(pn > 0.0) || !isfinite(pn);
+                // the stages of that square root depend on each other: the remaining
+                // updates of this step fill the gaps between them
+                RsqChain q{pn, 0.0, 0.0, 0.0};
+                static_for<0, RSQ_STAGES>([&](auto ss) {
+                    constexpr int st = decltype(ss)::value;
+                    rsq_stage(st, q);
+                    constexpr int l0 = c + 2 + 2 * st, l1 = (st + 1 == RSQ_STAGES) ? DB : c + 4 + 2 * st;
 #pragma unroll
-                for (int l = c + 2; l < DB; ++l) vec[l] = fma(-f, col[l], vec[l]);
+                    for (int l = l0; l < (l1 < DB ? l1 : DB); ++l) vec[l] = fma(-f, col[l], vec[l]);
+                    __builtin_amdgcn_sched_barrier(0);
+                });
+                d = q.g;
+                inv = q.h;
 #pragma unroll
                 for (int l = c + 1; l < DB; ++l) col[l] = coln[l];
             }
             pin_row<DB>(vec);
-        }
+        });
         wave_sync();
         if (bad && !failed) failed = gs + 1;
         // C_i and r_{i+1} have long arrived: retire them here, before this stage's
@@ -367,13 +386,15 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         vm_drain();
 
         phase_fence();
-        // ---- (2) L rows and L^{-1} columns into LDS; store L
-        if (isP) {
+        // ---- (2) L rows and L^{-1} columns into LDS (both as rows: L^{-1} is staged
+        // transposed, so the two halves of the wave write in the same instructions);
+        // store L.  The row lanes clear what is right of their diagonal; the inverse
+        // lanes hold exact zeros above theirs.
+        if (isP || isI) {
+            double *const dst = (isP ? RA : RB) + ri * PD;
+            const int keep = isP ? ri : DB;
 #pragma unroll
-            for (int c = 0; c < DB; ++c) RA[ri * PD + c] = (c <= ri) ? vec[c] : 0.0;
-        } else if (isI) {
-#pragma unroll
-            for (int r = 0; r < DB; ++r) RB[r * PD + ri] = (r >= ri) ? vec[r] : 0.0;
+            for (int c = 0; c < DB; ++c) dst[c] = (c <= keep) ? vec[c] : 0.0;
         }
         wave_sync();
         store_tile<DB, DB>(F + sd.oLd + (long long)gs * b2, RA, b, b, lane_s);
@@ -388,7 +409,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
 #pragma unroll
             for (int rt = 0; rt < TB; ++rt) accE[rt][ct] = dx4{0.0, 0.0, 0.0, 0.0};
         }
-        // B operand: L^{-T}[k][j] = L^{-1}[j][k], upper triangular: k-chunks past
+        // B operand: L^{-T}[k][j] as staged, upper triangular: k-chunks past
         // a tile's last column are zero and skipped.  All operands are read before
         // the first product.
         double bo[KS][TB], ga[KS];
@@ -396,7 +417,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         for (int kk = 0; kk < KS; ++kk) {
             ga[kk] = RG[li * PD + 4 * kk + lk];
 #pragma unroll
-            for (int ct = 0; ct < TB; ++ct) bo[kk][ct] = RB[(16 * ct + li) * PD + 4 * kk + lk];
+            for (int ct = 0; ct < TB; ++ct) bo[kk][ct] = RB[(4 * kk + lk) * PD + 16 * ct + li];
         }
         if (hasN) {
 #pragma unroll
@@ -414,12 +435,13 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         for (int t = 0; t < T4; ++t) accG4[t] = 0.0;
         if (g4) {
             // hat G[y4][4 (4 t + k4) + x4] per lane: A = Gw[x4][4 kc + y4], B = L^{-1} rows
+            // (columns of the staged L^{-T})
             double av[KS], bv[KS][T4];
 #pragma unroll
             for (int kc = 0; kc < KS; ++kc) {
                 av[kc] = RG[x4 * PD + 4 * kc + y4];
 #pragma unroll
-                for (int t = 0; t < T4; ++t) bv[kc][t] = RB[(4 * (4 * t + k4) + x4) * PD + 4 * kc + y4];
+                for (int t = 0; t < T4; ++t) bv[kc][t] = RB[(4 * kc + y4) * PD + 4 * (4 * t + k4) + x4];
             }
 #pragma unroll
             for (int kc = 0; kc < KS; ++kc)
@@ -558,7 +580,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             const int r = lane_s;
             const bool rowL = r < DB, gl = r >= DB && r < DB + NGM;
             const int q = r - DB;
-            const double yv = row_dot1<DB, false>(RB, PD, rowL ? r : 0, L.W);
+            const double yv = row_dot1<DB, true>(RB, PD, rowL ? r : 0, L.W);
             if (rowL) L.Y[r] = yv;
             wave_sync();
             const double ev = row_dot1<DB, false>(rowL ? RA : RG, PD, rowL ? r : (gl ? q : 0), L.Y);
@@ -579,7 +601,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             dx4 accY[TB];
 #pragma unroll
             for (int rt = 0; rt < TB; ++rt) accY[rt] = dx4{0.0, 0.0, 0.0, 0.0};
-            mm_rhs<TB, DB, false, true>(RB, PD, L.W, nr, accY, li, lk);
+            mm_rhs<TB, DB, true, true>(RB, PD, L.W, nr, accY, li, lk);
             if (li < nr) {
 #pragma unroll
                 for (int rt = 0; rt < TB; ++rt)

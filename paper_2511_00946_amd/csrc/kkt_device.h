@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <climits>
+#include <type_traits>
 
 namespace kkt_dev {
 
@@ -129,21 +130,46 @@ __device__ __forceinline__ double readlane_d(double v, int lane)
     return __hiloint2double(hi, lo);
 }
 
+// f(std::integral_constant<int, I>) for I = I0 .. I1 - 1 in order: the index is a
+// constant expression inside f, so arrays indexed by it stay in registers whatever
+// the size of the body.
+template <int I0, int I1, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I0 < I1) {
+        f(std::integral_constant<int, I0>{});
+        static_for<I0 + 1, I1>(f);
+    }
+}
+
 // sqrt(x) and 1/sqrt(x) from the hardware reciprocal square root refined by two
 // Goldschmidt iterations (g -> sqrt(x), h -> 1/(2 sqrt(x))); for x > 0 finite the
-// result is within a few ulp of the correctly rounded values.
+// result is within a few ulp of the correctly rounded values.  The iteration is
+// split into its dependent stages so that a caller can place independent work
+// between them; sqrt_rsqrt runs them back to back.
+struct RsqChain {
+    double x, g, h, r;
+};
+constexpr int RSQ_STAGES = 7;
+__device__ __forceinline__ void rsq_stage(int s, RsqChain &q)
+{
+    switch (s) {
+    case 0: q.h = __builtin_amdgcn_rsq(q.x); break;
+    case 1: q.g = q.x * q.h; q.h = 0.5 * q.h; break;
+    case 2: q.r = fma(-q.g, q.h, 0.5); break;
+    case 3: q.g = fma(q.g, q.r, q.g); q.h = fma(q.h, q.r, q.h); break;
+    case 4: q.r = fma(-q.g, q.h, 0.5); break;
+    case 5: q.g = fma(q.g, q.r, q.g); q.h = fma(q.h, q.r, q.h); break;
+    default: q.h = q.h + q.h; break;
+    }
+}
 __device__ __forceinline__ void sqrt_rsqrt(double x, double &d, double &inv)
 {
-    const double y0 = __builtin_amdgcn_rsq(x);
-    double g = x * y0, h = 0.5 * y0;
-    double r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    d = g;
-    inv = h + h;
+    RsqChain q{x, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < RSQ_STAGES; ++s) rsq_stage(s, q);
+    d = q.g;
+    inv = q.h;
 }
 
 // Keeps the compiler from moving LDS accesses across this point; LDS operations of
