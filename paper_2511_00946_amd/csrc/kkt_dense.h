@@ -49,9 +49,10 @@ struct TileMap {
 };
 
 // Rows [0, rows) x columns [0, cols) of an LDS tile of ROWS rows (pitch DB + 1) to
-// a row-major global block: every read first, then the predicated stores.
+// the row-major block g of rows x cols: every read first, then the stores (rows
+// at or past the end fall outside the block, columns past cols are sent there).
 template <int DB, int ROWS>
-__device__ __forceinline__ void store_tile(double *dst, const double *lds, int rows, int cols, int lane)
+__device__ __forceinline__ void store_tile(const GBlock &g, const double *lds, int cols, int lane)
 {
     constexpr int PD = DB + 1, M = ROWS / TileMap<DB>::RS;
     const TileMap<DB> t(lane);
@@ -59,12 +60,9 @@ __device__ __forceinline__ void store_tile(double *dst, const double *lds, int r
 #pragma unroll
     for (int m = 0; m < M; ++m) v[m] = lds[t.row(m) * PD + t.c];
     pin_row<M>(v);
-    const bool cin = t.c < cols;
+    const int base = t.c < cols ? (t.r0 * cols + t.c) * 8 : GB_OUT;
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        const int r = t.row(m);
-        if (cin && r < rows) dst[r * cols + t.c] = v[m];
-    }
+    for (int m = 0; m < M; ++m) g.st(base + TileMap<DB>::RS * m * cols * 8, v[m]);
 }
 
 // acc[rt] += A B on the FP64 matrix cores for the 16-row tiles rt < RT of A
@@ -291,13 +289,13 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         // the same for a single rhs, row lane_s
         const double rn1 = FWD ? ld_or_zero(a.rhs + sd.oRhs + (long long)(gs + 1) * b, lane_s, nextD && lane_s < b) : 0.0;
         double cA[TB][KS];
-        const double *Ci = a.C + sd.oC + (long long)gs * b2;
+        const GBlock gC(a.C + sd.oC + (long long)gs * b2, hasN ? b2 : 0);
 #pragma unroll
         for (int rt = 0; rt < TB; ++rt)
 #pragma unroll
             for (int kk = 0; kk < KS; ++kk) {
                 const int r = 16 * rt + li, c = 4 * kk + lk;
-                cA[rt][kk] = ld_or_zero(Ci, r * b + c, hasN && r < b && c < b);
+                cA[rt][kk] = gC.ld(c < b ? (r * b + c) * 8 : GB_OUT);   // rows past b: past the end
             }
         phase_fence();
         // ---- (1) L = chol(Dw) on the row lanes, L^{-1} on the column lanes
@@ -397,8 +395,6 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             for (int c = 0; c < DB; ++c) dst[c] = (c <= keep) ? vec[c] : 0.0;
         }
         wave_sync();
-        store_tile<DB, DB>(F + sd.oLd + (long long)gs * b2, RA, b, b, lane_s);
-        wave_sync();
 
         phase_fence();
         // ---- (3) hat E = C L^{-T}, hat G = Gw L^{-T} (and hat B^T = Fw L^{-T})
@@ -459,10 +455,18 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                     accG[ct] = mfma4(ga[kk], bo[kk][ct], accG[ct]);
                 }
         }
+        // while the products run on the matrix cores: L goes out, and with one rhs
+        // y = L^{-1} w is formed on the row lanes
+        store_tile<DB, DB>(GBlock(F + sd.oLd + (long long)gs * b2, b2), RA, b, lane_s);
+        if (FWD && nr == 1) {
+            const double yv = row_dot1<DB, true>(RB, PD, lane_s < DB ? lane_s : 0, L.W);
+            if (lane_s < DB) L.Y[lane_s] = yv;
+        }
+        wave_sync();
         // hat E and hat G go to the factor straight from the accumulators (each
         // element v of a tile is 4 rows of 16 consecutive entries)
         if (hasN) {
-            double *dE = F + sd.oLc + (long long)gs * b2;
+            const GBlock gE(F + sd.oLc + (long long)gs * b2, b2);
 #pragma unroll
             for (int rt = 0; rt < TB; ++rt)
 #pragma unroll
@@ -470,24 +474,24 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int r = 16 * rt + 4 * v + lk, c = 16 * ct + li;
-                        if (r < b && c < b) dE[r * b + c] = accE[rt][ct][v];
+                        gE.st(c < b ? (r * b + c) * 8 : GB_OUT, accE[rt][ct][v]);
                     }
         }
         if (g4) {
-            double *dG = F + sd.oLb + (long long)gs * ng * b;
+            const GBlock gG(F + sd.oLb + (long long)gs * ng * b, (long long)ng * b);
 #pragma unroll
             for (int t = 0; t < T4; ++t) {
                 const int c = 4 * (4 * t + k4) + x4;
-                if (y4 < ng && c < b) dG[y4 * b + c] = accG4[t];
+                gG.st(c < b ? (y4 * b + c) * 8 : GB_OUT, accG4[t]);
             }
         } else if (ng) {
-            double *dG = F + sd.oLb + (long long)gs * ng * b;
+            const GBlock gG(F + sd.oLb + (long long)gs * ng * b, (long long)ng * b);
 #pragma unroll
             for (int ct = 0; ct < TB; ++ct)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int q = 4 * v + lk, c = 16 * ct + li;
-                    if (q < ng && c < b) dG[q * b + c] = accG[ct][v];
+                    gG.st(c < b ? (q * b + c) * 8 : GB_OUT, accG[ct][v]);
                 }
         }
         wave_sync();
@@ -536,7 +540,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
             // the first fill block sits in the coupling slot of the separator
             double *dst = (i == 0) ? F + sd.oLc + (long long)sep * b2
                                    : F + sd.oFill + ((long long)(k - 2) * (sd.Nk - 1) + (i - 1)) * b2;
-            store_tile<DB, DB>(dst, RF, b, b, lane_s);
+            store_tile<DB, DB>(GBlock(dst, b2), RF, b, lane_s);
         }
 
         phase_fence();
@@ -544,7 +548,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         // D_{i+1} as stored (all tiles, in accumulator layout: coalesced rows); the
         // next factorization symmetrizes it when it reads the block
         double dn[TB][TB][4];
-        const double *Dn = a.D + sd.oD + (long long)(gs + 1) * b2;
+        const GBlock gD(a.D + sd.oD + (long long)(gs + 1) * b2, nextD ? b2 : 0);
 #pragma unroll
         for (int rt = 0; rt < TB; ++rt)
 #pragma unroll
@@ -552,22 +556,22 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * rt + 4 * v + lk, c = 16 * ct + li;
-                    dn[rt][ct][v] = ld_or_zero(Dn, r * b + c, nextD && r < b && c < b);
+                    dn[rt][ct][v] = gD.ld(c < b ? (r * b + c) * 8 : GB_OUT);
                 }
         double bn[TB][4];
-        const double *Bn = a.B + sd.oB + (long long)(gs + 1) * ng * b;
+        const GBlock gB(a.B + sd.oB + (long long)(gs + 1) * ng * b, nextD ? (long long)ng * b : 0);
 #pragma unroll
         for (int ct = 0; ct < TB; ++ct)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int q = 4 * v + lk, c = 16 * ct + li;
-                bn[ct][v] = ld_or_zero(Bn, q * b + c, nextD && q < ng && c < b);
+                bn[ct][v] = gB.ld(c < b ? (q * b + c) * 8 : GB_OUT);
             }
         double bn4[T4];
 #pragma unroll
         for (int t = 0; t < T4; ++t) {
             const int c = 4 * (4 * t + k4) + x4;
-            bn4[t] = ld_or_zero(Bn, y4 * b + c, g4 && nextD && y4 < ng && c < b);
+            bn4[t] = gB.ld(g4 && c < b ? (y4 * b + c) * 8 : GB_OUT);
         }
 
         phase_fence();
@@ -575,14 +579,11 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         // (at a segment end the scratch gets -hat F_k y instead of w'; with fill rows
         // the separator rhs -= hat B^T y)
         if (FWD && nr == 1) {
-            // one rhs: y = L^{-1} w on the row lanes, then hat E y (or hat F_k y) and,
+            // one rhs (y = L^{-1} w is in LDS already): hat E y (or hat F_k y) and,
             // with fill rows, hat B^T y on the row lanes and hat G y on the next 16 lanes
             const int r = lane_s;
             const bool rowL = r < DB, gl = r >= DB && r < DB + NGM;
             const int q = r - DB;
-            const double yv = row_dot1<DB, true>(RB, PD, rowL ? r : 0, L.W);
-            if (rowL) L.Y[r] = yv;
-            wave_sync();
             const double ev = row_dot1<DB, false>(rowL ? RA : RG, PD, rowL ? r : (gl ? q : 0), L.Y);
             const double sv = (SEG && hasF) ? row_dot1<DB, false>(RF, PD, rowL ? r : 0, L.Y) : 0.0;
             wave_sync();

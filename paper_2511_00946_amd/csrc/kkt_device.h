@@ -317,6 +317,39 @@ __device__ __forceinline__ double ld_or_zero(const double *src, int i, bool ok)
     return *(ok ? src + i : zero_word);
 }
 
+// A block of n doubles in global memory addressed through a buffer resource with
+// 32-bit byte offsets: a load past the end of the block returns zero and a store
+// past it is dropped, so an edge predicate costs one offset select (or nothing,
+// when the offset runs past the end by itself) instead of a branch or a 64-bit
+// address select.  n = 0 makes every access fall outside.  p and n must be the
+// same in every lane (the resource is a scalar operand; they are read from the
+// first active lane).
+constexpr int GB_OUT = 0x40000000;   // an offset past the end of every block
+typedef unsigned int gb_u32x2 __attribute__((ext_vector_type(2)));
+struct GBlock {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ static double *uniform_ptr(const double *p)
+    {
+        const unsigned long long u = (unsigned long long)p;
+        const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+        const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+        return (double *)(((unsigned long long)hi << 32) | lo);
+    }
+    __device__ __forceinline__ GBlock(const double *p, long long n)
+        : r(__builtin_amdgcn_make_buffer_rsrc(uniform_ptr(p), (short)0,
+                                              __builtin_amdgcn_readfirstlane((int)(n * 8)), 0x00020000))
+    {
+    }
+    __device__ __forceinline__ double ld(int off) const
+    {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    }
+    __device__ __forceinline__ void st(int off, double v) const
+    {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(gb_u32x2, v), r, off, 0, 0);
+    }
+};
+
 // Lane c of wave 0 holds acc = (rhs)[c] and dcol[l] = T[l][c] of a lower
 // triangular T with dinv = 1 / T[c][c]; returns x[c] of T^T x = rhs.
 template <int BP>
