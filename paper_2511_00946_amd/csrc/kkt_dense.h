@@ -883,11 +883,10 @@ struct BwdStage {
         const double *src = (il == 0) ? a.F + sd.oLc + (long long)sep_of(sd, k) * b2
                                       : a.F + sd.oFill + ((long long)(k - 2) * (sd.Nk - 1) + (il - 1)) * b2;
         const TileMap<DB> t(lane);
+        const GBlock gF(src, b2);
+        const int base = t.c < b ? (t.r0 * b + t.c) * 8 : GB_OUT;   // rows past b: past the end
 #pragma unroll
-        for (int m = 0; m < MD; ++m) {
-            const int r = t.row(m);
-            f[m] = ld_or_zero(src, r * b + t.c, r < b && t.c < b);
-        }
+        for (int m = 0; m < MD; ++m) f[m] = gF.ld(base + TileMap<DB>::RS * m * b * 8);
     }
 
     __device__ __forceinline__ void stage_fill(const SysDesc &sd, double *stF, int lane) const
@@ -905,33 +904,26 @@ struct BwdStage {
         const int b = sd.b, ng = sd.ng, nr = a.nr;
         const long long b2 = (long long)b * b;
         const bool hasE = i + 1 < sd.N;
-        const double *Ld = a.F + sd.oLd + (long long)i * b2, *Lc = a.F + sd.oLc + (long long)i * b2;
-        const double *Lb = a.F + sd.oLb + (long long)i * ng * b, *Y = a.rhs + sd.oRhs + (long long)i * b * nr;
+        const GBlock gLd(a.F + sd.oLd + (long long)i * b2, b2), gLc(a.F + sd.oLc + (long long)i * b2, hasE ? b2 : 0);
+        const GBlock gLb(a.F + sd.oLb + (long long)i * ng * b, (long long)ng * b);
+        const GBlock gY(a.rhs + sd.oRhs + (long long)i * b * nr, (long long)b * nr);
         const TileMap<DB> t(lane);
+        // one lane offset for all three blocks (b columns each): rows past the
+        // block's last fall past its end
+        const int base = t.c < b ? (t.r0 * b + t.c) * 8 : GB_OUT;
 #pragma unroll
         for (int m = 0; m < MD; ++m) {
-            const int r = t.row(m);
-            const bool in = r < b && t.c < b;
-            d[m] = ld_or_zero(Ld, r * b + t.c, in);
-            e[m] = ld_or_zero(Lc, r * b + t.c, hasE && in);
+            d[m] = gLd.ld(base + TileMap<DB>::RS * m * b * 8);
+            e[m] = gLc.ld(base + TileMap<DB>::RS * m * b * 8);
         }
 #pragma unroll
-        for (int m = 0; m < MG; ++m) {
-            const int q = t.row(m);
-            g[m] = ld_or_zero(Lb, q * b + t.c, q < ng && t.c < b);
-        }
+        for (int m = 0; m < MG; ++m) g[m] = gLb.ld(base + TileMap<DB>::RS * m * b * 8);
 #pragma unroll
-        for (int m = 0; m < MY; ++m) {
-            const int x = lane + m * NTL;
-            y[m] = ld_or_zero(Y, x, x < b * nr);
-        }
+        for (int m = 0; m < MY; ++m) y[m] = gY.ld((lane + m * NTL) * 8);
         if (PRIMAL) {
-            const double *XP = a.xp + sd.oRhs + (long long)i * b * nr;
+            const GBlock gP(a.xp + sd.oRhs + (long long)i * b * nr, (long long)b * nr);
 #pragma unroll
-            for (int m = 0; m < MY; ++m) {
-                const int x = lane + m * NTL;
-                px[m] = ld_or_zero(XP, x, x < b * nr);
-            }
+            for (int m = 0; m < MY; ++m) px[m] = gP.ld((lane + m * NTL) * 8);
         }
     }
 
