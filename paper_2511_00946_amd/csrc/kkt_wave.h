@@ -173,11 +173,9 @@ __device__ __forceinline__ void wstore(double *dst, const double *lds, int P, in
         v[m] = scale * (TR ? lds[c * P + r] : lds[r * P + c]);
     }
     pin_row<M>(v);
+    const GBlock g(dst, n);   // stores past the block's end are dropped
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        const int e = t + m * NT;
-        if (e < n) dst[e] = v[m];
-    }
+    for (int m = 0; m < M; ++m) g.st((t + m * NT) * 8, v[m]);
 }
 
 // rhs rows (rows x nr, global pitch nr) from LDS (pitch RP).
@@ -196,11 +194,9 @@ __device__ __forceinline__ void wstore_rhs(double *dst, const double *lds, int r
         v[m] = lds[r * MAX_NRHS_DEV + j];
     }
     pin_row<M>(v);
+    const GBlock g(dst, n);   // stores past the block's end are dropped
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        const int e = threadIdx.x + m * NT;
-        if (e < n) dst[e] = v[m];
-    }
+    for (int m = 0; m < M; ++m) g.st((int)(threadIdx.x + m * NT) * 8, v[m]);
 }
 
 // The thread index behind an opaque copy: values derived from it inside a loop
@@ -433,7 +429,7 @@ __device__ __forceinline__ void dot4_lds(const double *own, const double *B, int
 // ---------------------------------------------------------------- stage loads
 // The blocks of one stage of a factor chain, fetched into registers with
 // lane-contiguous, branch-free loads (element e = thread + NT m; entries past a
-// block read a zero word), then written to the next-row area of LDS.
+// block read as zero), then written to the next-row area of LDS.
 template <int BP, bool RED>
 struct FacLoad {
     using C = WC<BP>;
@@ -452,29 +448,63 @@ struct FacLoad {
         const int b = sd.b, ng = sd.ng, nr = a.nr, s = ch.stage(j);
         const int b2 = b * b, gb = ng * b, rb = b * nr;
         const bool hasE = ch.has_next(j);
-        const double *Dp = RED ? a.F + sd.oLd + (long long)s * b2 : a.D + sd.oD + (long long)s * b2;
-        const double *Cp = RED ? a.F + ch.coup_off(j) : a.C + sd.oC + (long long)s * b2;
-        const double *Bp = RED ? a.F + sd.oLb + (long long)s * gb : a.B + sd.oB + (long long)s * gb;
-        const double *Rp = a.rhs + sd.oRhs + (long long)s * rb;
-        const double *sc = RED ? ch.scr(j + 1) : nullptr;
+        if constexpr (BP <= 32) {
+            // the blocks are read through buffer resources: entries past a block's end
+            // (and every entry of an absent block) read as zero
+            const GBlock gD(RED ? a.F + sd.oLd + (long long)s * b2 : a.D + sd.oD + (long long)s * b2, b2);
+            const GBlock gC(RED ? a.F + ch.coup_off(j) : a.C + sd.oC + (long long)s * b2, hasE ? b2 : 0);
+            const GBlock gB(RED ? a.F + sd.oLb + (long long)s * gb : a.B + sd.oB + (long long)s * gb, gb);
+            const GBlock gR(a.rhs + sd.oRhs + (long long)s * rb, fwd ? rb : 0);
+            const double *sc = RED ? ch.scr(j + 1) : a.rhs;
+            const GBlock gsD(sc + (RED ? scr_dA(b, ng, nr) : 0), RED ? b2 : 0);
+            const GBlock gsQ(sc + (RED ? scr_dQ(b, ng, nr) : 0), RED ? gb : 0);
+            const GBlock gsY(sc + (RED ? scr_dy(b, ng, nr) : 0), RED && fwd ? rb : 0);
 #pragma unroll
-        for (int m = 0; m < MB; ++m) {
-            const int e = t + m * NT;
-            d[m] = ld_or_zero(Dp, e, e < b2);
-            c[m] = ld_or_zero(Cp, e, hasE && e < b2);
-            if (RED) d2[m] = ld_or_zero(sc + scr_dA(b, ng, nr), e, e < b2);
-        }
+            for (int m = 0; m < MB; ++m) {
+                const int e = (t + m * NT) * 8;
+                d[m] = gD.ld(e);
+                c[m] = gC.ld(e);
+                if (RED) d2[m] = gsD.ld(e);
+            }
 #pragma unroll
-        for (int m = 0; m < MG; ++m) {
-            const int e = t + m * NT;
-            g[m] = ld_or_zero(Bp, e, e < gb);
-            if (RED) g2[m] = ld_or_zero(sc + scr_dQ(b, ng, nr), e, e < gb);
-        }
+            for (int m = 0; m < MG; ++m) {
+                const int e = (t + m * NT) * 8;
+                g[m] = gB.ld(e);
+                if (RED) g2[m] = gsQ.ld(e);
+            }
 #pragma unroll
-        for (int m = 0; m < MR; ++m) {
-            const int e = t + m * NT;
-            r[m] = ld_or_zero(Rp, e, fwd && e < rb);
-            if (RED) r2[m] = ld_or_zero(sc + scr_dy(b, ng, nr), e, fwd && e < rb);
+            for (int m = 0; m < MR; ++m) {
+                const int e = (t + m * NT) * 8;
+                r[m] = gR.ld(e);
+                if (RED) r2[m] = gsY.ld(e);
+            }
+        } else {
+            // (the 48-wide tiles keep 64-bit addresses: their per-load offsets would
+            // add to registers that already spill)
+            const double *Dp = RED ? a.F + sd.oLd + (long long)s * b2 : a.D + sd.oD + (long long)s * b2;
+            const double *Cp = RED ? a.F + ch.coup_off(j) : a.C + sd.oC + (long long)s * b2;
+            const double *Bp = RED ? a.F + sd.oLb + (long long)s * gb : a.B + sd.oB + (long long)s * gb;
+            const double *Rp = a.rhs + sd.oRhs + (long long)s * rb;
+            const double *sc = RED ? ch.scr(j + 1) : nullptr;
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+                const int e = t + m * NT;
+                d[m] = ld_or_zero(Dp, e, e < b2);
+                c[m] = ld_or_zero(Cp, e, hasE && e < b2);
+                if (RED) d2[m] = ld_or_zero(sc + scr_dA(b, ng, nr), e, e < b2);
+            }
+#pragma unroll
+            for (int m = 0; m < MG; ++m) {
+                const int e = t + m * NT;
+                g[m] = ld_or_zero(Bp, e, e < gb);
+                if (RED) g2[m] = ld_or_zero(sc + scr_dQ(b, ng, nr), e, e < gb);
+            }
+#pragma unroll
+            for (int m = 0; m < MR; ++m) {
+                const int e = t + m * NT;
+                r[m] = ld_or_zero(Rp, e, fwd && e < rb);
+                if (RED) r2[m] = ld_or_zero(sc + scr_dy(b, ng, nr), e, fwd && e < rb);
+            }
         }
     }
 
@@ -821,28 +851,52 @@ struct SolveLoad {
         const int b = sd.b, ng = sd.ng, nr = a.nr, s = ch.stage(i);
         const int b2 = b * b, gb = ng * b, rb = b * nr;
         const bool hasE = ch.has_next(i);
-        const double *Ld = a.F + sd.oLd + (long long)s * b2, *Le = a.F + ch.coup_off(i);
-        const double *Lb = a.F + sd.oLb + (long long)s * gb;
-        const double *Lf = a.F + (hasF ? ch.fill_off(i) : 0);
-        const double *Y = a.rhs + sd.oRhs + (long long)s * rb;
-        const double *XP = PRIMAL ? a.xp + sd.oRhs + (long long)s * rb : Y;
+        if constexpr (BP <= 32) {
+            // buffer resources: entries past a block's end (and absent blocks) read as zero
+            const GBlock gLd(a.F + sd.oLd + (long long)s * b2, b2), gLe(a.F + ch.coup_off(i), hasE ? b2 : 0);
+            const GBlock gLb(a.F + sd.oLb + (long long)s * gb, gb);
+            const GBlock gLf(a.F + (hasF ? ch.fill_off(i) : 0), hasF ? b2 : 0);
+            const GBlock gY(a.rhs + sd.oRhs + (long long)s * rb, rb);
+            const GBlock gXP(PRIMAL ? a.xp + sd.oRhs + (long long)s * rb : a.rhs, PRIMAL ? rb : 0);
 #pragma unroll
-        for (int m = 0; m < MB; ++m) {
-            const int x = t + m * NT;
-            d[m] = ld_or_zero(Ld, x, x < b2);
-            e[m] = ld_or_zero(Le, x, hasE && x < b2);
-            f[m] = ld_or_zero(Lf, x, hasF && x < b2);
-        }
+            for (int m = 0; m < MB; ++m) {
+                const int x = (t + m * NT) * 8;
+                d[m] = gLd.ld(x);
+                e[m] = gLe.ld(x);
+                f[m] = gLf.ld(x);
+            }
 #pragma unroll
-        for (int m = 0; m < MG; ++m) {
-            const int x = t + m * NT;
-            g[m] = ld_or_zero(Lb, x, x < gb);
-        }
+            for (int m = 0; m < MG; ++m) g[m] = gLb.ld((t + m * NT) * 8);
 #pragma unroll
-        for (int m = 0; m < MR; ++m) {
-            const int x = t + m * NT;
-            y[m] = ld_or_zero(Y, x, x < rb);
-            px[m] = PRIMAL ? ld_or_zero(XP, x, x < rb) : 0.0;
+            for (int m = 0; m < MR; ++m) {
+                const int x = (t + m * NT) * 8;
+                y[m] = gY.ld(x);
+                px[m] = PRIMAL ? gXP.ld(x) : 0.0;
+            }
+        } else {
+            const double *Ld = a.F + sd.oLd + (long long)s * b2, *Le = a.F + ch.coup_off(i);
+            const double *Lb = a.F + sd.oLb + (long long)s * gb;
+            const double *Lf = a.F + (hasF ? ch.fill_off(i) : 0);
+            const double *Y = a.rhs + sd.oRhs + (long long)s * rb;
+            const double *XP = PRIMAL ? a.xp + sd.oRhs + (long long)s * rb : Y;
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+                const int x = t + m * NT;
+                d[m] = ld_or_zero(Ld, x, x < b2);
+                e[m] = ld_or_zero(Le, x, hasE && x < b2);
+                f[m] = ld_or_zero(Lf, x, hasF && x < b2);
+            }
+#pragma unroll
+            for (int m = 0; m < MG; ++m) {
+                const int x = t + m * NT;
+                g[m] = ld_or_zero(Lb, x, x < gb);
+            }
+#pragma unroll
+            for (int m = 0; m < MR; ++m) {
+                const int x = t + m * NT;
+                y[m] = ld_or_zero(Y, x, x < rb);
+                px[m] = PRIMAL ? ld_or_zero(XP, x, x < rb) : 0.0;
+            }
         }
     }
 
