@@ -102,27 +102,51 @@ __device__ __forceinline__ void lstore(double *dst, long long n, const double *l
 // 1 / L_cc in myinv.  After the sweep lane t < BP holds row t of L (entries right
 // of the diagonal stale) and w_t^(t) (y_t = w_t myinv), panel lanes hold
 // P L^{-T} and w - P y.  A pivot that is not positive and finite gives a NaN myinv
-// (see sqrt_rsqrt), tested once after the sweep.
+// (see sqrt_rsqrt), tested once after the sweep.  inv is 1 / sqrt of pivot c: each
+// step updates the next pivot's column first, reads the pivot from its lane and
+// spreads the dependent stages of its square root over its own remaining updates,
+// which fill the latencies of that chain.
 template <int W, int NR, bool RHS, int c>
-__device__ __forceinline__ void lelim(double (&row)[W], double (&w)[NR], double &myinv, int t)
+__device__ __forceinline__ void lelim(double (&row)[W], double (&w)[NR], double &myinv, int t, double inv)
 {
     if constexpr (c < W) {
-        const double dcc = readlane_d(row[c], c);
-        double d, inv;
-        sqrt_rsqrt(dcc, d, inv);
-        (void)d;
         const double v = row[c] * inv;
         const double f = (t > c) ? v * inv : 0.0;
         row[c] = v;
         myinv = (t == c) ? inv : myinv;
-#pragma unroll
-        for (int m = c + 1; m < W; ++m) row[m] = fma(-f, readlane_d(row[m], c), row[m]);
-        if constexpr (RHS) {
+        if constexpr (c + 1 < W) {
+            row[c + 1] = fma(-f, readlane_d(row[c + 1], c), row[c + 1]);
+            RsqChain q{readlane_d(row[c + 1], c + 1), 0.0, 0.0, 0.0};
+            constexpr int NROWU = W - c - 2, NU = NROWU + (RHS ? NR : 0);
+            static_for<0, RSQ_STAGES>([&](auto ss) {
+                constexpr int st = decltype(ss)::value;
+                rsq_stage(st, q);
+                static_for<(NU * st) / RSQ_STAGES, (NU * (st + 1)) / RSQ_STAGES>([&](auto uu) {
+                    constexpr int u = decltype(uu)::value;
+                    if constexpr (u < NROWU) {
+                        row[c + 2 + u] = fma(-f, readlane_d(row[c + 2 + u], c), row[c + 2 + u]);
+                    } else {
+                        w[u - NROWU] = fma(-f, readlane_d(w[u - NROWU], c), w[u - NROWU]);
+                    }
+                });
+                __builtin_amdgcn_sched_barrier(0);
+            });
+            lelim<W, NR, RHS, c + 1>(row, w, myinv, t, q.h);
+        } else if constexpr (RHS) {
 #pragma unroll
             for (int j = 0; j < NR; ++j) w[j] = fma(-f, readlane_d(w[j], c), w[j]);
         }
-        lelim<W, NR, RHS, c + 1>(row, w, myinv, t);
     }
+}
+
+// the elimination from its first pivot
+template <int W, int NR, bool RHS>
+__device__ __forceinline__ void lelim_all(double (&row)[W], double (&w)[NR], double &myinv, int t)
+{
+    double d, inv;
+    sqrt_rsqrt(readlane_d(row[0], 0), d, inv);
+    (void)d;
+    lelim<W, NR, RHS, 0>(row, w, myinv, t, inv);
 }
 
 // ---------------------------------------------------------------- factor loads
@@ -346,7 +370,7 @@ __device__ __forceinline__ int lane_factor(const Args &a, const SysDesc &sd, int
 
         // ---- (3) elimination (Algorithm 1 potrf / trsm, Algorithm 2)
         double myinv = 1.0;
-        lelim<BP, NR, FWD, 0>(row, w, myinv, t);
+        lelim_all<BP, NR, FWD>(row, w, myinv, t);
         if (any_bad_pivot(t < b, myinv) && !failed) failed = gs + 1;
 
         // ---- (4) rows to LDS: the Gram's operands, the factor rows and y for their
