@@ -287,7 +287,7 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
                 }
         }
         // the same for a single rhs, row lane_s
-        const double rn1 = FWD ? ld_or_zero(a.rhs + sd.oRhs + (long long)(gs + 1) * b, lane_s, nextD && lane_s < b) : 0.0;
+        const double rn1 = FWD ? GBlock(a.rhs + sd.oRhs + (long long)(gs + 1) * b, nextD ? b : 0).ld(lane_s * 8) : 0.0;
         double cA[TB][KS];
         const GBlock gC(a.C + sd.oC + (long long)gs * b2, hasN ? b2 : 0);
 #pragma unroll
@@ -830,8 +830,14 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
         wave_sync();
         // y_i goes out only now: stored earlier, the wait for the next stage's blocks
         // in the Gram would also wait for these stores
-        if (FWD)
-            for (int e = lane; e < b * nr; e += NTL) a.rhs[sd.oRhs + (long long)gs * b * nr + e] = L.Y[e];
+        if (FWD) {
+            // uniform trip count, stores past the block dropped: no divergent branch
+            const GBlock gy(a.rhs + sd.oRhs + (long long)gs * b * nr, (long long)b * nr);
+            for (int e0 = 0; e0 < b * nr; e0 += NTL) {
+                const int e = e0 + lane_s;
+                gy.st(e * 8, L.Y[e < DB * nr ? e : 0]);
+            }
+        }
     }
 
     // ---- epilogue: separator partials (k >= 2) and the arrow partials of segment k
@@ -1115,8 +1121,13 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
         wave_sync();
         // x of the stage solved last goes out only now, after the wait for this
         // stage's blocks: stored earlier, that wait would also wait for the stores
-        if (i < len - 1)
-            for (int e = lane_s; e < b * nr; e += NTL) X[(long long)(gs + 1) * b * nr + e] = L.XN[e];
+        if (i < len - 1) {
+            const GBlock gx(X + (long long)(gs + 1) * b * nr, (long long)b * nr);
+            for (int e0 = 0; e0 < b * nr; e0 += NTL) {
+                const int e = e0 + lane_s;
+                gx.st(e * 8, L.XN[e < DB * nr ? e : 0]);
+            }
+        }
         if (i > 0) {
             pf.template fetch<ADJ>(a, sd, gs - 1, lane_s);
             if (hasF) pf.fetch_fill(a, sd, k, i - 1, lane_s);
