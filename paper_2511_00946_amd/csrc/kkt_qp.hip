@@ -163,9 +163,10 @@ __global__ void __launch_bounds__(256) qp_assemble_k(const QpSys *sys, const int
 
 // In thread t < E of a 256-thread workgroup: sum_{k < n} src[k * stride + t] (E <=
 // 256), the k range split over 256 / E slices with eight loads in flight each.
+template <int NT>
 __device__ inline double slice_sum(const double *src, long long stride, int n, int E, double *red)
 {
-    const int t = threadIdx.x, KS = 256 / E, e = t % E, ks = t / E;
+    const int t = threadIdx.x, KS = NT / E, e = t % E, ks = t / E;
     double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (ks < KS) {
         int k = ks;
@@ -183,15 +184,21 @@ __device__ inline double slice_sum(const double *src, long long stride, int n, i
     return s;
 }
 
+// The sums over a system's stages below run in one workgroup per system: 1024
+// threads when some horizon is long (NT / E threads per entry read the stage
+// partials in few rounds), 256 otherwise.
+constexpr int SUM_NT_LONG = 1024, SUM_NT_SHORT = 256, SUM_LONG_N = 512;
+
 // corner = Qg + rho I + sum of the groups' partials (one workgroup per system).
-__global__ void __launch_bounds__(256) qp_corner_k(const QpSys *sys, QpPtr d, double rho, double *corner,
-                                                   const double *part)
+template <int NT>
+__global__ void __launch_bounds__(NT) qp_corner_k(const QpSys *sys, QpPtr d, double rho, double *corner,
+                                                  const double *part)
 {
-    __shared__ double red[256];
+    __shared__ double red[NT];
     const QpSys q = sys[blockIdx.x];
     const int ng = q.ng, E = ng * ng, t = threadIdx.x;
     if (E == 0) return;
-    const double s = slice_sum(part + q.oPart, E, q.N, E, red);
+    const double s = slice_sum<NT>(part + q.oPart, E, q.N, E, red);
     if (t < E) {
         const long long o = q.oCor + t;
         corner[o] = d.Qg[o] + ((t / ng) == (t % ng) ? rho : 0.0) + s;
@@ -234,13 +241,14 @@ __global__ void __launch_bounds__(256) qp_rhs_k(const QpSys *sys, const int2 *un
 }
 
 // The g rows of the reduced rhs (one workgroup per system).
-__global__ void __launch_bounds__(256) qp_rhs_g_k(const QpSys *sys, const double *rx, double *rhs, const double *part)
+template <int NT>
+__global__ void __launch_bounds__(NT) qp_rhs_g_k(const QpSys *sys, const double *rx, double *rhs, const double *part)
 {
-    __shared__ double red[256];
+    __shared__ double red[NT];
     const QpSys q = sys[blockIdx.x];
     const int E = q.ng * q.nr, t = threadIdx.x;
     if (E == 0) return;
-    const double s = slice_sum(part + q.oPart, E, q.N, E, red);
+    const double s = slice_sum<NT>(part + q.oPart, E, q.N, E, red);
     if (t < E) {
         const long long o = q.oR + (long long)q.N * q.b * q.nr + t;
         rhs[o] = rx[o] + s;
@@ -346,14 +354,15 @@ __global__ void __launch_bounds__(256) ipm_resid_k(const QpSys *sys, const int2 
 }
 
 // The g rows of r_d: c_g + Qg x_g + the stages' parts (one workgroup per system).
-__global__ void __launch_bounds__(256) ipm_resid_g_k(const QpSys *sys, QpPtr d, const double *x, const double *c,
-                                                     double *rd, const double *part)
+template <int NT>
+__global__ void __launch_bounds__(NT) ipm_resid_g_k(const QpSys *sys, QpPtr d, const double *x, const double *c,
+                                                    double *rd, const double *part)
 {
-    __shared__ double red[256];
+    __shared__ double red[NT];
     const QpSys q = sys[blockIdx.x];
     const int ng = q.ng, t = threadIdx.x;
     if (ng == 0) return;
-    const double sum = slice_sum(part + q.oPart, ng, q.N, ng, red);
+    const double sum = slice_sum<NT>(part + q.oPart, ng, q.N, ng, red);
     if (t < ng) {
         const long long og = q.oR + (long long)q.N * q.b;
         double v = c[og + t] + sum;
@@ -564,6 +573,7 @@ struct kkt_qp {
     long long len[9] = {};
     QpMax mx{0, 0, 0, 0, 0};
     size_t lds = 0;
+    bool long_n = false;   // some horizon of SUM_LONG_N stages or more
     ~kkt_qp()
     {
         // teardown: nothing to recover from a failure
@@ -624,6 +634,7 @@ int kkt_qp_create(const kkt_plan *plan, const int32_t *n_eq, const int32_t *n_in
     std::vector<int2> units;
     long long o[9] = {}, oP = 0;
     QpMax mx{1, 1, 1, 1, nr};
+    bool long_n = false;
     for (int s = 0; s < S; ++s) {
         kkt_system_layout L;
         rc = kkt_plan_system(plan, s, &L);
@@ -631,6 +642,7 @@ int kkt_qp_create(const kkt_plan *plan, const int32_t *n_eq, const int32_t *n_in
         QpSys &q = sys[s];
         const long long N = L.N, b = L.b, ng = L.ng, pe = n_eq[s], me = n_in[s];
         q.N = L.N; q.b = L.b; q.ng = L.ng; q.pe = n_eq[s]; q.me = n_in[s]; q.nr = nr;
+        if (L.N >= SUM_LONG_N) long_n = true;
         q.oD = L.off_D; q.oC = L.off_C; q.oB = L.off_B; q.oCor = L.off_corner; q.oR = L.off_rhs;
         q.oEL = o[0]; o[0] += N * pe * b;
         q.oER = o[1]; o[1] += (N - 1) * pe * b;
@@ -653,6 +665,7 @@ int kkt_qp_create(const kkt_plan *plan, const int32_t *n_eq, const int32_t *n_in
     qp->hsys = sys;
     for (int k = 0; k < 9; ++k) qp->len[k] = o[k];
     qp->mx = mx;
+    qp->long_n = long_n;
     qp->lds = stage_lds_doubles(mx) * sizeof(double);
     if (qp->lds > 160 * 1024) { delete qp; return KKT_EDIMS; }
     const bool ok = hipMalloc((void **)&qp->dsys, sizeof(QpSys) * S) == hipSuccess &&
@@ -717,7 +730,12 @@ int kkt_qp_assemble(const kkt_qp *qp, const kkt_qp_data *data, double rho, doubl
                        rho, 1.0 / delta, D, C, B, qp->dpart);
     if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
     if (Col) {
-        hipLaunchKernelGGL(qp_corner_k, dim3(qp->S), dim3(256), 0, stream, qp->dsys, d, rho, corner, qp->dpart);
+        if (qp->long_n)
+            hipLaunchKernelGGL(qp_corner_k<SUM_NT_LONG>, dim3(qp->S), dim3(SUM_NT_LONG), 0, stream, qp->dsys, d, rho,
+                               corner, qp->dpart);
+        else
+            hipLaunchKernelGGL(qp_corner_k<SUM_NT_SHORT>, dim3(qp->S), dim3(SUM_NT_SHORT), 0, stream, qp->dsys, d, rho,
+                               corner, qp->dpart);
         if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
     }
     return KKT_OK;
@@ -737,7 +755,11 @@ int kkt_qp_reduce_rhs(const kkt_qp *qp, const kkt_qp_data *data, double delta, c
     hipLaunchKernelGGL(qp_rhs_k, dim3(qp->nunits), dim3(256), qp->lds, stream, qp->dsys, qp->dunits, d, qp->mx,
                        1.0 / delta, rx, ry, rz, rhs, qp->dpart);
     if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
-    hipLaunchKernelGGL(qp_rhs_g_k, dim3(qp->S), dim3(256), 0, stream, qp->dsys, rx, rhs, qp->dpart);
+    if (qp->long_n)
+        hipLaunchKernelGGL(qp_rhs_g_k<SUM_NT_LONG>, dim3(qp->S), dim3(SUM_NT_LONG), 0, stream, qp->dsys, rx, rhs, qp->dpart);
+    else
+        hipLaunchKernelGGL(qp_rhs_g_k<SUM_NT_SHORT>, dim3(qp->S), dim3(SUM_NT_SHORT), 0, stream, qp->dsys, rx, rhs,
+                           qp->dpart);
     return hipGetLastError() == hipSuccess ? KKT_OK : KKT_ELAUNCH;
 }
 
@@ -856,8 +878,12 @@ int kkt_ipm_solve(kkt_ipm *ipm, void *workspace, const kkt_qp_data *data, const 
         hipLaunchKernelGGL(ipm_resid_k, dim3(qp->nunits), dim3(256), qp->lds, stream, qp->dsys, qp->dunits, d, qp->mx,
                            (const double *)x, (const double *)y, (const double *)z, (const double *)s, c, beq, h, rd,
                            rp, rs, qp->dpart);
-        hipLaunchKernelGGL(ipm_resid_g_k, dim3(S), dim3(256), 0, stream, qp->dsys, d, (const double *)x, c, rd,
-                           (const double *)qp->dpart);
+        if (qp->long_n)
+            hipLaunchKernelGGL(ipm_resid_g_k<SUM_NT_LONG>, dim3(S), dim3(SUM_NT_LONG), 0, stream, qp->dsys, d,
+                               (const double *)x, c, rd, (const double *)qp->dpart);
+        else
+            hipLaunchKernelGGL(ipm_resid_g_k<SUM_NT_SHORT>, dim3(S), dim3(SUM_NT_SHORT), 0, stream, qp->dsys, d,
+                               (const double *)x, c, rd, (const double *)qp->dpart);
         hipLaunchKernelGGL(ipm_vec_k<4>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active, v, delta,
                            tol);
         if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
@@ -879,8 +905,12 @@ int kkt_ipm_solve(kkt_ipm *ipm, void *workspace, const kkt_qp_data *data, const 
         hipLaunchKernelGGL(ipm_resid_k, dim3(qp->nunits), dim3(256), qp->lds, stream, qp->dsys, qp->dunits, d, qp->mx,
                            (const double *)x, (const double *)y, (const double *)z, (const double *)s, c, beq, h, rd,
                            rp, rs, qp->dpart);
-        hipLaunchKernelGGL(ipm_resid_g_k, dim3(S), dim3(256), 0, stream, qp->dsys, d, (const double *)x, c, rd,
-                           (const double *)qp->dpart);
+        if (qp->long_n)
+            hipLaunchKernelGGL(ipm_resid_g_k<SUM_NT_LONG>, dim3(S), dim3(SUM_NT_LONG), 0, stream, qp->dsys, d,
+                               (const double *)x, c, rd, (const double *)qp->dpart);
+        else
+            hipLaunchKernelGGL(ipm_resid_g_k<SUM_NT_SHORT>, dim3(S), dim3(SUM_NT_SHORT), 0, stream, qp->dsys, d,
+                               (const double *)x, c, rd, (const double *)qp->dpart);
         hipLaunchKernelGGL(ipm_vec_k<0>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active, v, dk,
                            tol);
         if (hipGetLastError() != hipSuccess ||
