@@ -384,14 +384,15 @@ struct IpmVec {
     const int *info;
 };
 
-// Block-wide reductions over the 256 threads (every thread calls them).
+// Block-wide reductions over the NT threads (every thread calls them).
+template <int NT>
 __device__ inline double block_reduce(double v, double *red, int op)   // 0 sum, 1 max, 2 min
 {
     const int t = threadIdx.x;
     __syncthreads();
     red[t] = v;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = NT / 2; h > 0; h >>= 1) {
         if (t < h) {
             const double a = red[t], bb = red[t + h];
             red[t] = op == 0 ? a + bb : (op == 1 ? fmax(a, bb) : fmin(a, bb));
@@ -420,11 +421,11 @@ __device__ inline double ratio(double v, double dv) { return dv < 0.0 ? -v / dv 
 //        s += max(-1.5 min s, 0), z += max(-1.5 min z, 0), and with t = s^T z,
 //        s += t / (2 sum z), z += t / (2 sum s).  Systems without inequality rows
 //        start the loop at x = 0.
-template <int PH>
-__global__ void __launch_bounds__(256) ipm_vec_k(const QpSys *sys, IpmState *state, int *active, IpmVec v,
-                                                 double delta, double tol)
+template <int PH, int NT>
+__global__ void __launch_bounds__(NT) ipm_vec_k(const QpSys *sys, IpmState *state, int *active, IpmVec v,
+                                                double delta, double tol)
 {
-    __shared__ double red[256];
+    __shared__ double red[NT];
     const QpSys q = sys[blockIdx.x];
     const int t = threadIdx.x;
     IpmState st = state[blockIdx.x];
@@ -438,23 +439,23 @@ __global__ void __launch_bounds__(256) ipm_vec_k(const QpSys *sys, IpmState *sta
     const double *rs = v.rs + q.oz;
     if (PH == 0 || PH == 4) {
         double res = 0.0, sz = 0.0;
-        for (long long e = t; e < nx; e += 256) res = fmax(res, fabs(rd[e]));
-        for (long long e = t; e < ny; e += 256) res = fmax(res, fabs(rp[e]));
-        for (long long e = t; e < nz; e += 256) {
+        for (long long e = t; e < nx; e += NT) res = fmax(res, fabs(rd[e]));
+        for (long long e = t; e < ny; e += NT) res = fmax(res, fabs(rp[e]));
+        for (long long e = t; e < nz; e += NT) {
             res = fmax(res, fabs(rs[e]));
             sz += s[e] * z[e];
         }
-        res = block_reduce(res, red, 1);
-        sz = block_reduce(sz, red, 0);
+        res = block_reduce<NT>(res, red, 1);
+        sz = block_reduce<NT>(sz, red, 0);
         const double mu = nz > 0 ? sz / (double)nz : 0.0;
         bool run = st.status == 0;
         if (run && res <= tol && mu <= tol) {
             run = false;
             if (t == 0) state[blockIdx.x].status = 1;
         }
-        for (long long e = t; e < nx; e += 256) RX[e] = run ? -rd[e] : 0.0;
-        for (long long e = t; e < ny; e += 256) RY[e] = run ? -rp[e] : 0.0;
-        for (long long e = t; e < nz; e += 256) {
+        for (long long e = t; e < nx; e += NT) RX[e] = run ? -rd[e] : 0.0;
+        for (long long e = t; e < ny; e += NT) RY[e] = run ? -rp[e] : 0.0;
+        for (long long e = t; e < nz; e += NT) {
             w[e] = run ? z[e] / (s[e] + delta * z[e]) : 1.0;
             RZ[e] = run ? -rs[e] + s[e] : 0.0;
         }
@@ -473,59 +474,59 @@ __global__ void __launch_bounds__(256) ipm_vec_k(const QpSys *sys, IpmState *sta
     if (PH == 3) {
         if (nz == 0) return;
         double smin = 1e300, zmin = 1e300;
-        for (long long e = t; e < nx; e += 256) x[e] += X[e];
-        for (long long e = t; e < ny; e += 256) y[e] += DY[e];
-        for (long long e = t; e < nz; e += 256) {
+        for (long long e = t; e < nx; e += NT) x[e] += X[e];
+        for (long long e = t; e < ny; e += NT) y[e] += DY[e];
+        for (long long e = t; e < nz; e += NT) {
             s[e] += -rs[e] - RZ[e] - DZ[e] / w[e];
             z[e] += DZ[e];
             smin = fmin(smin, s[e]);
             zmin = fmin(zmin, z[e]);
         }
-        smin = block_reduce(smin, red, 2);
-        zmin = block_reduce(zmin, red, 2);
+        smin = block_reduce<NT>(smin, red, 2);
+        zmin = block_reduce<NT>(zmin, red, 2);
         const double ps = fmax(-1.5 * smin, 0.0), pz = fmax(-1.5 * zmin, 0.0);
         double tsz = 0.0, ss = 0.0, sumz = 0.0;
-        for (long long e = t; e < nz; e += 256) {
+        for (long long e = t; e < nz; e += NT) {
             s[e] += ps;
             z[e] += pz;
             tsz += s[e] * z[e];
             ss += s[e];
             sumz += z[e];
         }
-        tsz = block_reduce(tsz, red, 0);
-        ss = block_reduce(ss, red, 0);
-        sumz = block_reduce(sumz, red, 0);
+        tsz = block_reduce<NT>(tsz, red, 0);
+        ss = block_reduce<NT>(ss, red, 0);
+        sumz = block_reduce<NT>(sumz, red, 0);
         const double hs = 0.5 * tsz / sumz, hz = 0.5 * tsz / ss;
-        for (long long e = t; e < nz; e += 256) {
+        for (long long e = t; e < nz; e += NT) {
             s[e] += hs;
             z[e] += hz;
         }
         return;
     }
     double amax = 1.0;
-    for (long long e = t; e < nz; e += 256) {
+    for (long long e = t; e < nz; e += NT) {
         const double ds = -rs[e] - RZ[e] - DZ[e] / w[e];
         DS[e] = ds;
         amax = fmin(amax, fmin(ratio(s[e], ds), ratio(z[e], DZ[e])));
     }
-    amax = block_reduce(amax, red, 2);
+    amax = block_reduce<NT>(amax, red, 2);
     if (PH == 1) {
         if (nz == 0) return;
         double sz = 0.0;
-        for (long long e = t; e < nz; e += 256) sz += (s[e] + amax * DS[e]) * (z[e] + amax * DZ[e]);
-        sz = block_reduce(sz, red, 0);
+        for (long long e = t; e < nz; e += NT) sz += (s[e] + amax * DS[e]) * (z[e] + amax * DZ[e]);
+        sz = block_reduce<NT>(sz, red, 0);
         const double mu_aff = sz / (double)nz;
         const double sg = mu_aff / st.mu, sigma = sg * sg * sg;
-        for (long long e = t; e < nz; e += 256) {
+        for (long long e = t; e < nz; e += NT) {
             const double rc = -s[e] * z[e] + sigma * st.mu - DS[e] * DZ[e];
             RZ[e] = -rs[e] - rc / z[e];
         }
         return;
     }
     const double alpha = nz > 0 ? fmin(1.0, 0.99 * amax) : 1.0;
-    for (long long e = t; e < nx; e += 256) x[e] += alpha * X[e];
-    for (long long e = t; e < ny; e += 256) y[e] += alpha * DY[e];
-    for (long long e = t; e < nz; e += 256) {
+    for (long long e = t; e < nx; e += NT) x[e] += alpha * X[e];
+    for (long long e = t; e < ny; e += NT) y[e] += alpha * DY[e];
+    for (long long e = t; e < nz; e += NT) {
         z[e] += alpha * DZ[e];
         s[e] += alpha * DS[e];
     }
@@ -614,6 +615,20 @@ int set_lds(const void *fn, size_t lds)
     if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return KKT_ELAUNCH;
     return KKT_OK;
+}
+
+// One vector phase for every system: 1024 threads per system once a horizon is
+// long, 256 otherwise.
+template <int PH>
+void launch_vec(const kkt_qp *qp, int S, hipStream_t stream, IpmState *state, int *active, const IpmVec &v,
+                double delta, double tol)
+{
+    if (qp->long_n)
+        hipLaunchKernelGGL((ipm_vec_k<PH, SUM_NT_LONG>), dim3(S), dim3(SUM_NT_LONG), 0, stream, qp->dsys, state, active, v,
+                           delta, tol);
+    else
+        hipLaunchKernelGGL((ipm_vec_k<PH, SUM_NT_SHORT>), dim3(S), dim3(SUM_NT_SHORT), 0, stream, qp->dsys, state, active,
+                           v, delta, tol);
 }
 
 }  // namespace
@@ -884,8 +899,7 @@ int kkt_ipm_solve(kkt_ipm *ipm, void *workspace, const kkt_qp_data *data, const 
         else
             hipLaunchKernelGGL(ipm_resid_g_k<SUM_NT_SHORT>, dim3(S), dim3(SUM_NT_SHORT), 0, stream, qp->dsys, d,
                                (const double *)x, c, rd, (const double *)qp->dpart);
-        hipLaunchKernelGGL(ipm_vec_k<4>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active, v, delta,
-                           tol);
+        launch_vec<4>(qp, S, stream, ipm->state, ipm->active, v, delta, tol);
         if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
         rc = kkt_qp_assemble(qp, &dw, rho, delta, D, C, B, Cor, stream);
         if (rc == KKT_OK) rc = kkt_factor(ipm->plan, D, C, B, Cor, workspace, ipm->info, stream);
@@ -893,8 +907,7 @@ int kkt_ipm_solve(kkt_ipm *ipm, void *workspace, const kkt_qp_data *data, const 
         if (rc == KKT_OK) rc = kkt_solve(ipm->plan, workspace, X, stream);
         if (rc == KKT_OK) rc = kkt_qp_recover(qp, &dw, delta, X, RY, RZ, DY, DZ, stream);
         if (rc != KKT_OK) return rc;
-        hipLaunchKernelGGL(ipm_vec_k<3>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active, v, delta,
-                           tol);
+        launch_vec<3>(qp, S, stream, ipm->state, ipm->active, v, delta, tol);
         if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
     }
     for (int it = 0; it <= max_iter && rc == KKT_OK; ++it) {
@@ -911,8 +924,7 @@ int kkt_ipm_solve(kkt_ipm *ipm, void *workspace, const kkt_qp_data *data, const 
         else
             hipLaunchKernelGGL(ipm_resid_g_k<SUM_NT_SHORT>, dim3(S), dim3(SUM_NT_SHORT), 0, stream, qp->dsys, d,
                                (const double *)x, c, rd, (const double *)qp->dpart);
-        hipLaunchKernelGGL(ipm_vec_k<0>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active, v, dk,
-                           tol);
+        launch_vec<0>(qp, S, stream, ipm->state, ipm->active, v, dk, tol);
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(ipm->h_active, ipm->active, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
             hipStreamSynchronize(stream) != hipSuccess) {
@@ -929,11 +941,9 @@ int kkt_ipm_solve(kkt_ipm *ipm, void *workspace, const kkt_qp_data *data, const 
             if (rc == KKT_OK) rc = kkt_qp_recover(qp, &dw, dk, X, RY, RZ, DY, DZ, stream);
             if (rc == KKT_OK) {
                 if (ph == 1)
-                    hipLaunchKernelGGL(ipm_vec_k<1>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active,
-                                       v, dk, tol);
+                    launch_vec<1>(qp, S, stream, ipm->state, ipm->active, v, dk, tol);
                 else
-                    hipLaunchKernelGGL(ipm_vec_k<2>, dim3(S), dim3(256), 0, stream, qp->dsys, ipm->state, ipm->active,
-                                       v, dk, tol);
+                    launch_vec<2>(qp, S, stream, ipm->state, ipm->active, v, dk, tol);
                 if (hipGetLastError() != hipSuccess) rc = KKT_ELAUNCH;
             }
         }
