@@ -81,38 +81,41 @@ __device__ inline StageLds carve(double *p, const QpMax &m)
 
 // n doubles from src into dst (zeros when the block does not exist: src is then
 // never read).
+template <int NT>
 __device__ inline void stage(double *dst, const double *src, int n, bool have)
 {
-    for (int e = threadIdx.x; e < n; e += 256) dst[e] = have ? src[e] : 0.0;
+    for (int e = threadIdx.x; e < n; e += NT) dst[e] = have ? src[e] : 0.0;
 }
 
 // The constraint rows of group i on x_i and g (and their weights), with nextg its
 // rows on x_{i+1}, with prevg group i - 1's rows on x_i and g, into LDS.
+template <int NT>
 __device__ inline void stage_rows(const StageLds &L, const QpPtr &d, const QpSys &q, int i, bool nextg, bool prevg)
 {
     const int b = q.b, ng = q.ng, pe = q.pe, me = q.me;
     const bool nx = i + 1 < q.N, pv = i > 0;
     const long long pb = (long long)pe * b, pg = (long long)pe * ng, mb = (long long)me * b, mg = (long long)me * ng;
-    stage(L.EL, d.EL + q.oEL + i * pb, pe * b, true);
-    stage(L.EG, d.EG + q.oEG + i * pg, pe * ng, true);
-    stage(L.IL, d.IL + q.oIL + i * mb, me * b, true);
-    stage(L.IG, d.IG + q.oIG + i * mg, me * ng, true);
-    stage(L.w, d.w + q.ow + (long long)i * me, me, true);
+    stage<NT>(L.EL, d.EL + q.oEL + i * pb, pe * b, true);
+    stage<NT>(L.EG, d.EG + q.oEG + i * pg, pe * ng, true);
+    stage<NT>(L.IL, d.IL + q.oIL + i * mb, me * b, true);
+    stage<NT>(L.IG, d.IG + q.oIG + i * mg, me * ng, true);
+    stage<NT>(L.w, d.w + q.ow + (long long)i * me, me, true);
     if (nextg) {
-        stage(L.ER, d.ER + q.oER + i * pb, pe * b, nx);
-        stage(L.IR, d.IR + q.oIR + i * mb, me * b, nx);
+        stage<NT>(L.ER, d.ER + q.oER + i * pb, pe * b, nx);
+        stage<NT>(L.IR, d.IR + q.oIR + i * mb, me * b, nx);
     }
     if (prevg) {
-        stage(L.ERp, d.ER + q.oER + (i - 1) * pb, pe * b, pv);
-        stage(L.EGp, d.EG + q.oEG + (i - 1) * pg, pe * ng, pv);
-        stage(L.IRp, d.IR + q.oIR + (i - 1) * mb, me * b, pv);
-        stage(L.IGp, d.IG + q.oIG + (i - 1) * mg, me * ng, pv);
-        stage(L.wp, d.w + q.ow + (long long)(i - 1) * me, me, pv);
+        stage<NT>(L.ERp, d.ER + q.oER + (i - 1) * pb, pe * b, pv);
+        stage<NT>(L.EGp, d.EG + q.oEG + (i - 1) * pg, pe * ng, pv);
+        stage<NT>(L.IRp, d.IR + q.oIR + (i - 1) * mb, me * b, pv);
+        stage<NT>(L.IGp, d.IG + q.oIG + (i - 1) * mg, me * ng, pv);
+        stage<NT>(L.wp, d.w + q.ow + (long long)(i - 1) * me, me, pv);
     }
 }
 
 // Psi's blocks of stage i: D_i, C_i (i < N - 1), B_i, and group i's part of the corner.
-__global__ void __launch_bounds__(256) qp_assemble_k(const QpSys *sys, const int2 *units, QpPtr d, QpMax mx,
+template <int NT>
+__global__ void __launch_bounds__(NT) qp_assemble_k(const QpSys *sys, const int2 *units, QpPtr d, QpMax mx,
                                                      double rho, double rdelta, double *D, double *C, double *B,
                                                      double *part)
 {
@@ -121,10 +124,10 @@ __global__ void __launch_bounds__(256) qp_assemble_k(const QpSys *sys, const int
     const int2 u = units[blockIdx.x];
     const QpSys q = sys[u.x];
     const int i = u.y, b = q.b, ng = q.ng, pe = q.pe, me = q.me, t = threadIdx.x;
-    stage_rows(L, d, q, i, true, true);
+    stage_rows<NT>(L, d, q, i, true, true);
     __syncthreads();
     const long long b2 = (long long)b * b;
-    for (int e = t; e < b * b; e += 256) {
+    for (int e = t; e < b * b; e += NT) {
         const int r = e / b, c = e - r * b;
         double se = 0.0, si = 0.0;
         for (int k = 0; k < pe; ++k) se += L.EL[k * b + r] * L.EL[k * b + c] + L.ERp[k * b + r] * L.ERp[k * b + c];
@@ -134,7 +137,7 @@ __global__ void __launch_bounds__(256) qp_assemble_k(const QpSys *sys, const int
         D[o] = d.Q[o] + (r == c ? rho : 0.0) + se * rdelta + si;
     }
     if (i + 1 < q.N) {
-        for (int e = t; e < b * b; e += 256) {
+        for (int e = t; e < b * b; e += NT) {
             const int r = e / b, c = e - r * b;   // r: a variable of stage i + 1, c: of stage i
             double se = 0.0, si = 0.0;
             for (int k = 0; k < pe; ++k) se += L.ER[k * b + r] * L.EL[k * b + c];
@@ -143,7 +146,7 @@ __global__ void __launch_bounds__(256) qp_assemble_k(const QpSys *sys, const int
             C[o] = d.S[o] + se * rdelta + si;
         }
     }
-    for (int e = t; e < ng * b; e += 256) {
+    for (int e = t; e < ng * b; e += NT) {
         const int g = e / b, c = e - g * b;
         double se = 0.0, si = 0.0;
         for (int k = 0; k < pe; ++k) se += L.EG[k * ng + g] * L.EL[k * b + c] + L.EGp[k * ng + g] * L.ERp[k * b + c];
@@ -152,7 +155,7 @@ __global__ void __launch_bounds__(256) qp_assemble_k(const QpSys *sys, const int
         const long long o = q.oB + (long long)i * ng * b + e;
         B[o] = d.T[o] + se * rdelta + si;
     }
-    for (int e = t; e < ng * ng; e += 256) {
+    for (int e = t; e < ng * ng; e += NT) {
         const int g1 = e / ng, g2 = e - g1 * ng;
         double se = 0.0, si = 0.0;
         for (int k = 0; k < pe; ++k) se += L.EG[k * ng + g1] * L.EG[k * ng + g2];
@@ -188,6 +191,9 @@ __device__ inline double slice_sum(const double *src, long long stride, int n, i
 // threads when some horizon is long (NT / E threads per entry read the stage
 // partials in few rounds), 256 otherwise.
 constexpr int SUM_NT_LONG = 1024, SUM_NT_SHORT = 256, SUM_LONG_N = 512;
+// The kernels with one workgroup per (system, stage): 256 threads, or 64 when a
+// plan has many stages (small stages then keep more workgroups in flight).
+constexpr int UNIT_NT = 256, UNIT_NT_SMALL = 64, UNIT_MANY = 8192;
 
 // corner = Qg + rho I + sum of the groups' partials (one workgroup per system).
 template <int NT>
@@ -206,7 +212,8 @@ __global__ void __launch_bounds__(NT) qp_corner_k(const QpSys *sys, QpPtr d, dou
 }
 
 // The reduced rhs of stage i, and group i's part of its g rows.
-__global__ void __launch_bounds__(256) qp_rhs_k(const QpSys *sys, const int2 *units, QpPtr d, QpMax mx, double rdelta,
+template <int NT>
+__global__ void __launch_bounds__(NT) qp_rhs_k(const QpSys *sys, const int2 *units, QpPtr d, QpMax mx, double rdelta,
                                                 const double *rx, const double *ry, const double *rz, double *rhs,
                                                 double *part)
 {
@@ -216,13 +223,13 @@ __global__ void __launch_bounds__(256) qp_rhs_k(const QpSys *sys, const int2 *un
     const QpSys q = sys[u.x];
     const int i = u.y, b = q.b, ng = q.ng, pe = q.pe, me = q.me, nr = q.nr, t = threadIdx.x;
     const bool pv = i > 0;
-    stage_rows(L, d, q, i, false, true);
-    stage(L.ry, ry + q.oy + (long long)i * pe * nr, pe * nr, true);
-    stage(L.rz, rz + q.oz + (long long)i * me * nr, me * nr, true);
-    stage(L.ryp, ry + q.oy + (long long)(i - 1) * pe * nr, pe * nr, pv);
-    stage(L.rzp, rz + q.oz + (long long)(i - 1) * me * nr, me * nr, pv);
+    stage_rows<NT>(L, d, q, i, false, true);
+    stage<NT>(L.ry, ry + q.oy + (long long)i * pe * nr, pe * nr, true);
+    stage<NT>(L.rz, rz + q.oz + (long long)i * me * nr, me * nr, true);
+    stage<NT>(L.ryp, ry + q.oy + (long long)(i - 1) * pe * nr, pe * nr, pv);
+    stage<NT>(L.rzp, rz + q.oz + (long long)(i - 1) * me * nr, me * nr, pv);
     __syncthreads();
-    for (int e = t; e < b * nr; e += 256) {
+    for (int e = t; e < b * nr; e += NT) {
         const int r = e / nr, j = e - r * nr;
         double se = 0.0, si = 0.0;
         for (int k = 0; k < pe; ++k) se += L.EL[k * b + r] * L.ry[k * nr + j] + L.ERp[k * b + r] * L.ryp[k * nr + j];
@@ -231,7 +238,7 @@ __global__ void __launch_bounds__(256) qp_rhs_k(const QpSys *sys, const int2 *un
         const long long o = q.oR + (long long)i * b * nr + e;
         rhs[o] = rx[o] + se * rdelta + si;
     }
-    for (int e = t; e < ng * nr; e += 256) {
+    for (int e = t; e < ng * nr; e += NT) {
         const int g = e / nr, j = e - g * nr;
         double se = 0.0, si = 0.0;
         for (int k = 0; k < pe; ++k) se += L.EG[k * ng + g] * L.ry[k * nr + j];
@@ -256,7 +263,8 @@ __global__ void __launch_bounds__(NT) qp_rhs_g_k(const QpSys *sys, const double 
 }
 
 // dy and dz of constraint group i.
-__global__ void __launch_bounds__(256) qp_recover_k(const QpSys *sys, const int2 *units, QpPtr d, QpMax mx,
+template <int NT>
+__global__ void __launch_bounds__(NT) qp_recover_k(const QpSys *sys, const int2 *units, QpPtr d, QpMax mx,
                                                     double rdelta, const double *dx, const double *ry,
                                                     const double *rz, double *dy, double *dz)
 {
@@ -266,13 +274,13 @@ __global__ void __launch_bounds__(256) qp_recover_k(const QpSys *sys, const int2
     const QpSys q = sys[u.x];
     const int i = u.y, b = q.b, ng = q.ng, pe = q.pe, me = q.me, nr = q.nr, t = threadIdx.x;
     const bool nx = i + 1 < q.N;
-    stage_rows(L, d, q, i, true, false);
+    stage_rows<NT>(L, d, q, i, true, false);
     const long long rb = (long long)b * nr;
-    stage(L.xi, dx + q.oR + i * rb, b * nr, true);
-    stage(L.xn, dx + q.oR + (i + 1) * rb, b * nr, nx);
-    stage(L.xg, dx + q.oR + (long long)q.N * rb, ng * nr, true);
+    stage<NT>(L.xi, dx + q.oR + i * rb, b * nr, true);
+    stage<NT>(L.xn, dx + q.oR + (i + 1) * rb, b * nr, nx);
+    stage<NT>(L.xg, dx + q.oR + (long long)q.N * rb, ng * nr, true);
     __syncthreads();
-    for (int e = t; e < pe * nr; e += 256) {
+    for (int e = t; e < pe * nr; e += NT) {
         const int k = e / nr, j = e - k * nr;
         double s = 0.0;
         for (int c = 0; c < b; ++c) s += L.EL[k * b + c] * L.xi[c * nr + j] + L.ER[k * b + c] * L.xn[c * nr + j];
@@ -280,7 +288,7 @@ __global__ void __launch_bounds__(256) qp_recover_k(const QpSys *sys, const int2
         const long long o = q.oy + (long long)i * pe * nr + e;
         dy[o] = (s - ry[o]) * rdelta;
     }
-    for (int e = t; e < me * nr; e += 256) {
+    for (int e = t; e < me * nr; e += NT) {
         const int k = e / nr, j = e - k * nr;
         double s = 0.0;
         for (int c = 0; c < b; ++c) s += L.IL[k * b + c] * L.xi[c * nr + j] + L.IR[k * b + c] * L.xn[c * nr + j];
@@ -295,7 +303,8 @@ __global__ void __launch_bounds__(256) qp_recover_k(const QpSys *sys, const int2
 //   r_d = P x + c + A^T y + G^T z,  r_p = A x - beq,  r_s = G x + s - h.
 // Stage i's rows of r_d (and group i's part of its g rows), and group i's rows of
 // r_p and r_s.  P's blocks are read from the Q, S, T pools where they are used.
-__global__ void __launch_bounds__(256) ipm_resid_k(const QpSys *sys, const int2 *units, QpPtr d, QpMax mx,
+template <int NT>
+__global__ void __launch_bounds__(NT) ipm_resid_k(const QpSys *sys, const int2 *units, QpPtr d, QpMax mx,
                                                    const double *x, const double *y, const double *z,
                                                    const double *s, const double *c, const double *beq,
                                                    const double *h, double *rd, double *rp, double *rs, double *part)
@@ -306,20 +315,20 @@ __global__ void __launch_bounds__(256) ipm_resid_k(const QpSys *sys, const int2 
     const QpSys q = sys[u.x];
     const int i = u.y, b = q.b, ng = q.ng, pe = q.pe, me = q.me, N = q.N, t = threadIdx.x;
     const bool nx = i + 1 < N, pv = i > 0;
-    stage_rows(L, d, q, i, true, true);
-    stage(L.xi, x + q.oR + (long long)i * b, b, true);
-    stage(L.xn, x + q.oR + (long long)(i + 1) * b, b, nx);
-    stage(L.xp, x + q.oR + (long long)(i - 1) * b, b, pv);
-    stage(L.xg, x + q.oR + (long long)N * b, ng, true);
-    stage(L.ry, y + q.oy + (long long)i * pe, pe, true);
-    stage(L.ryp, y + q.oy + (long long)(i - 1) * pe, pe, pv);
-    stage(L.rz, z + q.oz + (long long)i * me, me, true);
-    stage(L.rzp, z + q.oz + (long long)(i - 1) * me, me, pv);
+    stage_rows<NT>(L, d, q, i, true, true);
+    stage<NT>(L.xi, x + q.oR + (long long)i * b, b, true);
+    stage<NT>(L.xn, x + q.oR + (long long)(i + 1) * b, b, nx);
+    stage<NT>(L.xp, x + q.oR + (long long)(i - 1) * b, b, pv);
+    stage<NT>(L.xg, x + q.oR + (long long)N * b, ng, true);
+    stage<NT>(L.ry, y + q.oy + (long long)i * pe, pe, true);
+    stage<NT>(L.ryp, y + q.oy + (long long)(i - 1) * pe, pe, pv);
+    stage<NT>(L.rz, z + q.oz + (long long)i * me, me, true);
+    stage<NT>(L.rzp, z + q.oz + (long long)(i - 1) * me, me, pv);
     __syncthreads();
     const long long b2 = (long long)b * b;
     const double *Qi = d.Q + q.oD + i * b2, *Si = d.S + q.oC + i * b2, *Sp = d.S + q.oC + (i - 1) * b2;
     const double *Ti = d.T + q.oB + (long long)i * ng * b;
-    for (int r = t; r < b; r += 256) {
+    for (int r = t; r < b; r += NT) {
         double v = c[q.oR + (long long)i * b + r];
         for (int cc = 0; cc < b; ++cc) v += Qi[r * b + cc] * L.xi[cc];
         if (nx)
@@ -331,20 +340,20 @@ __global__ void __launch_bounds__(256) ipm_resid_k(const QpSys *sys, const int2 
         for (int k = 0; k < me; ++k) v += L.IL[k * b + r] * L.rz[k] + L.IRp[k * b + r] * L.rzp[k];
         rd[q.oR + (long long)i * b + r] = v;
     }
-    for (int g = t; g < ng; g += 256) {
+    for (int g = t; g < ng; g += NT) {
         double v = 0.0;
         for (int cc = 0; cc < b; ++cc) v += Ti[g * b + cc] * L.xi[cc];
         for (int k = 0; k < pe; ++k) v += L.EG[k * ng + g] * L.ry[k];
         for (int k = 0; k < me; ++k) v += L.IG[k * ng + g] * L.rz[k];
         part[q.oPart + (long long)i * ng + g] = v;
     }
-    for (int k = t; k < pe; k += 256) {
+    for (int k = t; k < pe; k += NT) {
         double v = -beq[q.oy + (long long)i * pe + k];
         for (int cc = 0; cc < b; ++cc) v += L.EL[k * b + cc] * L.xi[cc] + L.ER[k * b + cc] * L.xn[cc];
         for (int g = 0; g < ng; ++g) v += L.EG[k * ng + g] * L.xg[g];
         rp[q.oy + (long long)i * pe + k] = v;
     }
-    for (int k = t; k < me; k += 256) {
+    for (int k = t; k < me; k += NT) {
         const long long o = q.oz + (long long)i * me + k;
         double v = s[o] - h[o];
         for (int cc = 0; cc < b; ++cc) v += L.IL[k * b + cc] * L.xi[cc] + L.IR[k * b + cc] * L.xn[cc];
@@ -575,6 +584,7 @@ struct kkt_qp {
     QpMax mx{0, 0, 0, 0, 0};
     size_t lds = 0;
     bool long_n = false;   // some horizon of SUM_LONG_N stages or more
+    int unit_nt = UNIT_NT; // threads per (system, stage) workgroup
     ~kkt_qp()
     {
         // teardown: nothing to recover from a failure
@@ -624,10 +634,12 @@ void launch_vec(const kkt_qp *qp, int S, hipStream_t stream, IpmState *state, in
                 double delta, double tol)
 {
     if (qp->long_n)
-        hipLaunchKernelGGL((ipm_vec_k<PH, SUM_NT_LONG>), dim3(S), dim3(SUM_NT_LONG), 0, stream, qp->dsys, state, active, v,
+        hipLaunchKernelGGL((ipm_vec_k<PH, SUM_NT_LONG>), dim3(S), dim3(SUM_NT_LONG), 0, stream, qp->dsys, state,
+                           active, v,
                            delta, tol);
     else
-        hipLaunchKernelGGL((ipm_vec_k<PH, SUM_NT_SHORT>), dim3(S), dim3(SUM_NT_SHORT), 0, stream, qp->dsys, state, active,
+        hipLaunchKernelGGL((ipm_vec_k<PH, SUM_NT_SHORT>), dim3(S), dim3(SUM_NT_SHORT), 0, stream, qp->dsys, state,
+                           active,
                            v, delta, tol);
 }
 
@@ -681,6 +693,7 @@ int kkt_qp_create(const kkt_plan *plan, const int32_t *n_eq, const int32_t *n_in
     for (int k = 0; k < 9; ++k) qp->len[k] = o[k];
     qp->mx = mx;
     qp->long_n = long_n;
+    qp->unit_nt = units.size() >= (size_t)UNIT_MANY ? UNIT_NT_SMALL : UNIT_NT;
     qp->lds = stage_lds_doubles(mx) * sizeof(double);
     if (qp->lds > 160 * 1024) { delete qp; return KKT_EDIMS; }
     const bool ok = hipMalloc((void **)&qp->dsys, sizeof(QpSys) * S) == hipSuccess &&
@@ -688,8 +701,12 @@ int kkt_qp_create(const kkt_plan *plan, const int32_t *n_eq, const int32_t *n_in
                     hipMalloc((void **)&qp->dpart, sizeof(double) * std::max(1LL, oP)) == hipSuccess &&
                     hipMemcpy(qp->dsys, sys.data(), sizeof(QpSys) * S, hipMemcpyHostToDevice) == hipSuccess &&
                     hipMemcpy(qp->dunits, units.data(), sizeof(int2) * units.size(), hipMemcpyHostToDevice) == hipSuccess;
-    if (!ok || set_lds((const void *)qp_assemble_k, qp->lds) != KKT_OK ||
-        set_lds((const void *)qp_rhs_k, qp->lds) != KKT_OK || set_lds((const void *)qp_recover_k, qp->lds) != KKT_OK) {
+    if (!ok || set_lds((const void *)qp_assemble_k<UNIT_NT>, qp->lds) != KKT_OK ||
+        set_lds((const void *)qp_assemble_k<UNIT_NT_SMALL>, qp->lds) != KKT_OK ||
+        set_lds((const void *)qp_rhs_k<UNIT_NT>, qp->lds) != KKT_OK ||
+        set_lds((const void *)qp_rhs_k<UNIT_NT_SMALL>, qp->lds) != KKT_OK ||
+        set_lds((const void *)qp_recover_k<UNIT_NT>, qp->lds) != KKT_OK ||
+        set_lds((const void *)qp_recover_k<UNIT_NT_SMALL>, qp->lds) != KKT_OK) {
         delete qp;
         return KKT_ELAUNCH;
     }
@@ -741,8 +758,12 @@ int kkt_qp_assemble(const kkt_qp *qp, const kkt_qp_data *data, double rho, doubl
         return KKT_EPOINTER;
     if (qp->nunits == 0) return KKT_OK;
     const QpPtr d = ptrs(data);
-    hipLaunchKernelGGL(qp_assemble_k, dim3(qp->nunits), dim3(256), qp->lds, stream, qp->dsys, qp->dunits, d, qp->mx,
-                       rho, 1.0 / delta, D, C, B, qp->dpart);
+    if (qp->unit_nt == UNIT_NT_SMALL)
+        hipLaunchKernelGGL(qp_assemble_k<UNIT_NT_SMALL>, dim3(qp->nunits), dim3(UNIT_NT_SMALL), qp->lds, stream,
+                           qp->dsys, qp->dunits, d, qp->mx, rho, 1.0 / delta, D, C, B, qp->dpart);
+    else
+        hipLaunchKernelGGL(qp_assemble_k<UNIT_NT>, dim3(qp->nunits), dim3(UNIT_NT), qp->lds, stream, qp->dsys,
+                           qp->dunits, d, qp->mx, rho, 1.0 / delta, D, C, B, qp->dpart);
     if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
     if (Col) {
         if (qp->long_n)
@@ -767,11 +788,16 @@ int kkt_qp_reduce_rhs(const kkt_qp *qp, const kkt_qp_data *data, double delta, c
         return KKT_EPOINTER;
     if (qp->nunits == 0) return KKT_OK;
     const QpPtr d = ptrs(data);
-    hipLaunchKernelGGL(qp_rhs_k, dim3(qp->nunits), dim3(256), qp->lds, stream, qp->dsys, qp->dunits, d, qp->mx,
-                       1.0 / delta, rx, ry, rz, rhs, qp->dpart);
+    if (qp->unit_nt == UNIT_NT_SMALL)
+        hipLaunchKernelGGL(qp_rhs_k<UNIT_NT_SMALL>, dim3(qp->nunits), dim3(UNIT_NT_SMALL), qp->lds, stream, qp->dsys,
+                           qp->dunits, d, qp->mx, 1.0 / delta, rx, ry, rz, rhs, qp->dpart);
+    else
+        hipLaunchKernelGGL(qp_rhs_k<UNIT_NT>, dim3(qp->nunits), dim3(UNIT_NT), qp->lds, stream, qp->dsys, qp->dunits,
+                           d, qp->mx, 1.0 / delta, rx, ry, rz, rhs, qp->dpart);
     if (hipGetLastError() != hipSuccess) return KKT_ELAUNCH;
     if (qp->long_n)
-        hipLaunchKernelGGL(qp_rhs_g_k<SUM_NT_LONG>, dim3(qp->S), dim3(SUM_NT_LONG), 0, stream, qp->dsys, rx, rhs, qp->dpart);
+        hipLaunchKernelGGL(qp_rhs_g_k<SUM_NT_LONG>, dim3(qp->S), dim3(SUM_NT_LONG), 0, stream, qp->dsys, rx, rhs,
+                           qp->dpart);
     else
         hipLaunchKernelGGL(qp_rhs_g_k<SUM_NT_SHORT>, dim3(qp->S), dim3(SUM_NT_SHORT), 0, stream, qp->dsys, rx, rhs,
                            qp->dpart);
@@ -788,8 +814,12 @@ int kkt_qp_recover(const kkt_qp *qp, const kkt_qp_data *data, double delta, cons
         !aligned8(rz) || !aligned8(dy) || !aligned8(dz))
         return KKT_EPOINTER;
     if (qp->nunits == 0) return KKT_OK;
-    hipLaunchKernelGGL(qp_recover_k, dim3(qp->nunits), dim3(256), qp->lds, stream, qp->dsys, qp->dunits, ptrs(data),
-                       qp->mx, 1.0 / delta, dx, ry, rz, dy, dz);
+    if (qp->unit_nt == UNIT_NT_SMALL)
+        hipLaunchKernelGGL(qp_recover_k<UNIT_NT_SMALL>, dim3(qp->nunits), dim3(UNIT_NT_SMALL), qp->lds, stream,
+                           qp->dsys, qp->dunits, ptrs(data), qp->mx, 1.0 / delta, dx, ry, rz, dy, dz);
+    else
+        hipLaunchKernelGGL(qp_recover_k<UNIT_NT>, dim3(qp->nunits), dim3(UNIT_NT), qp->lds, stream, qp->dsys,
+                           qp->dunits, ptrs(data), qp->mx, 1.0 / delta, dx, ry, rz, dy, dz);
     return hipGetLastError() == hipSuccess ? KKT_OK : KKT_ELAUNCH;
 }
 
@@ -835,7 +865,8 @@ int kkt_ipm_create(const kkt_plan *plan, const kkt_qp *qp, kkt_ipm **out)
                     hipMalloc((void **)&m->active, sizeof(int)) == hipSuccess &&
                     hipMalloc((void **)&m->info, sizeof(int) * std::max(1, qp->S)) == hipSuccess &&
                     hipHostMalloc((void **)&m->h_active, sizeof(int), hipHostMallocDefault) == hipSuccess &&
-                    set_lds((const void *)ipm_resid_k, qp->lds) == KKT_OK;
+                    set_lds((const void *)ipm_resid_k<UNIT_NT>, qp->lds) == KKT_OK &&
+                    set_lds((const void *)ipm_resid_k<UNIT_NT_SMALL>, qp->lds) == KKT_OK;
     if (!ok) {
         delete m;
         return KKT_ELAUNCH;
@@ -890,9 +921,14 @@ int kkt_ipm_solve(kkt_ipm *ipm, void *workspace, const kkt_qp_data *data, const 
     int rc = KKT_OK;
     // the starting point: a predictor solve from x = 0, s = z = 1, then the shift
     if (ipm->nz > 0) {
-        hipLaunchKernelGGL(ipm_resid_k, dim3(qp->nunits), dim3(256), qp->lds, stream, qp->dsys, qp->dunits, d, qp->mx,
-                           (const double *)x, (const double *)y, (const double *)z, (const double *)s, c, beq, h, rd,
-                           rp, rs, qp->dpart);
+        if (qp->unit_nt == UNIT_NT_SMALL)
+            hipLaunchKernelGGL(ipm_resid_k<UNIT_NT_SMALL>, dim3(qp->nunits), dim3(UNIT_NT_SMALL), qp->lds, stream,
+                               qp->dsys, qp->dunits, d, qp->mx, (const double *)x, (const double *)y,
+                               (const double *)z, (const double *)s, c, beq, h, rd, rp, rs, qp->dpart);
+        else
+            hipLaunchKernelGGL(ipm_resid_k<UNIT_NT>, dim3(qp->nunits), dim3(UNIT_NT), qp->lds, stream, qp->dsys,
+                               qp->dunits, d, qp->mx, (const double *)x, (const double *)y, (const double *)z,
+                               (const double *)s, c, beq, h, rd, rp, rs, qp->dpart);
         if (qp->long_n)
             hipLaunchKernelGGL(ipm_resid_g_k<SUM_NT_LONG>, dim3(S), dim3(SUM_NT_LONG), 0, stream, qp->dsys, d,
                                (const double *)x, c, rd, (const double *)qp->dpart);
@@ -915,9 +951,14 @@ int kkt_ipm_solve(kkt_ipm *ipm, void *workspace, const kkt_qp_data *data, const 
         const double f = std::max(1e-4, std::pow(10.0, -(double)(it + 1)));
         const double rk = rho * f, dk = delta * f;
         hipLaunchKernelGGL(ipm_clear_k, dim3(1), dim3(64), 0, stream, ipm->active);
-        hipLaunchKernelGGL(ipm_resid_k, dim3(qp->nunits), dim3(256), qp->lds, stream, qp->dsys, qp->dunits, d, qp->mx,
-                           (const double *)x, (const double *)y, (const double *)z, (const double *)s, c, beq, h, rd,
-                           rp, rs, qp->dpart);
+        if (qp->unit_nt == UNIT_NT_SMALL)
+            hipLaunchKernelGGL(ipm_resid_k<UNIT_NT_SMALL>, dim3(qp->nunits), dim3(UNIT_NT_SMALL), qp->lds, stream,
+                               qp->dsys, qp->dunits, d, qp->mx, (const double *)x, (const double *)y,
+                               (const double *)z, (const double *)s, c, beq, h, rd, rp, rs, qp->dpart);
+        else
+            hipLaunchKernelGGL(ipm_resid_k<UNIT_NT>, dim3(qp->nunits), dim3(UNIT_NT), qp->lds, stream, qp->dsys,
+                               qp->dunits, d, qp->mx, (const double *)x, (const double *)y, (const double *)z,
+                               (const double *)s, c, beq, h, rd, rp, rs, qp->dpart);
         if (qp->long_n)
             hipLaunchKernelGGL(ipm_resid_g_k<SUM_NT_LONG>, dim3(S), dim3(SUM_NT_LONG), 0, stream, qp->dsys, d,
                                (const double *)x, c, rd, (const double *)qp->dpart);
