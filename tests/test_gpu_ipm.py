@@ -32,12 +32,13 @@ SHAPES = [
 ]
 
 
-def test_ipm_batch_matches_the_oracle_loop():
+def _solve_and_compare(probs, ps, label, check=None, tol=1e-9):
+    """Run the device loop on the problems (one system each, segment counts ps) and
+    compare the systems listed in check (all by default) with the oracle loop, both
+    stopped at the same tolerance."""
     from paper_2511_00946_amd import kkt
-    rng = np.random.default_rng(2024)
-    probs = [workloads.draw_qp_problem(rng, *sh[:5]) for sh in SHAPES]
     qps = [p[0] for p in probs]
-    plan = kkt.Plan([(q.N, q.b, q.ng, sh[5]) for q, sh in zip(qps, SHAPES)], nrhs=1)
+    plan = kkt.Plan([(q.N, q.b, q.ng, p) for q, p in zip(qps, ps)], nrhs=1)
     qp = kkt.QP(plan, [q.pe for q in qps], [q.me for q in qps])
     pools = {k: torch.from_numpy(v).cuda() for k, v in workloads.pack_qp(qps).items()}
     c = np.zeros(plan.info.rhs_len)
@@ -50,15 +51,16 @@ def test_ipm_batch_matches_the_oracle_loop():
         h[off["rz"]:off["rz"] + hv.size] = hv
     ipm = kkt.IPM(plan, qp)
     ws = plan.new_workspace()
-    print("gpu case: interior-point batch shapes=%s" % SHAPES, file=sys.stderr, flush=True)
-    out = ipm.solve(ws, pools, *(torch.from_numpy(v).cuda() for v in (c, beq, h)))
+    print("gpu case: interior-point %s" % label, file=sys.stderr, flush=True)
+    out = ipm.solve(ws, pools, *(torch.from_numpy(v).cuda() for v in (c, beq, h)), tol=tol)
     torch.cuda.synchronize()
     status = out["status"].cpu().numpy()
     x, y, z, sl = (out[k].cpu().numpy() for k in ("x", "y", "z", "s"))
-    for s, (q, cv, bv, hv) in enumerate(probs):
+    for s in (range(len(probs)) if check is None else check):
+        q, cv, bv, hv = probs[s]
         lay, off = plan.layouts[s], qp.offsets[s]
         n = q.N * q.b + q.ng
-        ref = oipm.solve(q.arrays, cv, bv, hv)
+        ref = oipm.solve(q.arrays, cv, bv, hv, tol=tol)
         assert ref["converged"]
         assert status[s] >= 0 and abs(int(status[s]) - ref["iterations"]) <= 1, (s, status[s], ref["iterations"])
         got = dict(x=x[lay.off_rhs:lay.off_rhs + n], y=y[off["ry"]:off["ry"] + bv.size],
@@ -75,6 +77,31 @@ def test_ipm_batch_matches_the_oracle_loop():
         assert max(np.max(np.abs(rd)), np.max(np.abs(rp), initial=0.0), np.max(np.abs(rs), initial=0.0), gap) < 1e-8, s
         if hv.size:
             assert np.all(got["s"] > 0) and np.all(got["z"] > 0)
+    return status
+
+
+def test_ipm_batch_matches_the_oracle_loop():
+    rng = np.random.default_rng(2024)
+    probs = [workloads.draw_qp_problem(rng, *sh[:5]) for sh in SHAPES]
+    _solve_and_compare(probs, [sh[5] for sh in SHAPES], "batch shapes=%s" % SHAPES)
+
+
+def test_ipm_long_horizon_matches_the_oracle_loop():
+    """A horizon of 512 stages: the sums over a system's stages (corner, g rows, dual
+    residual) and the vector phases then run with 1024 threads per system.  Over so
+    long a chain a stopping tolerance of 1e-9 pins x only to about 2e-5 (the oracle's
+    own 1e-9 and 1e-12 iterates differ by that much), so both loops run to 1e-12."""
+    rng = np.random.default_rng(512)
+    probs = [workloads.draw_qp_problem(rng, 512, 3, 2, 2, 4)]
+    _solve_and_compare(probs, [8], "long horizon N=512 b=3 ng=2 pe=2 me=4 p=8", tol=1e-12)
+
+
+def test_ipm_many_stages_matches_the_oracle_loop():
+    """128 QPs of 64 stages (8192 stage units): the per-stage kernels then run with
+    64 threads per workgroup; eight systems compared with the oracle loop."""
+    rng = np.random.default_rng(8192)
+    probs = [workloads.draw_qp_problem(rng, 64, 4, 2, 2, 4) for _ in range(128)]
+    _solve_and_compare(probs, [1] * 128, "128 x (N=64 b=4 ng=2 pe=2 me=4)", check=[0, 17, 38, 63, 64, 90, 111, 127])
 
 
 def test_ipm_on_a_nested_plan():
