@@ -670,14 +670,27 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
 #pragma unroll
             for (int t = 0; t < TB; ++t) ek[kk][t] = RA[(16 * t + li) * PD + 4 * kk + lk];
         }
+        // Only the tiles on and below the diagonal carry the product into the next
+        // factorization: it reads sym of the block, so the tiles below the diagonal
+        // are written back as D - 2 hat E hat E^T and those above as D alone, whose
+        // half-sum is sym(D) - hat E hat E^T.  A segment end keeps every tile.
         if (hasN) {
 #pragma unroll
             for (int kk = 0; kk < KS; ++kk)
 #pragma unroll
                 for (int rt = 0; rt < TB; ++rt)
 #pragma unroll
-                    for (int ct = 0; ct < TB; ++ct)
+                    for (int ct = 0; ct <= rt; ++ct)
                         accD[rt][ct] = mfma4(-ek[kk][rt], ek[kk][ct], accD[rt][ct]);
+            if (endS) {
+#pragma unroll
+                for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+                    for (int rt = 0; rt < TB; ++rt)
+#pragma unroll
+                        for (int ct = rt + 1; ct < TB; ++ct)
+                            accD[rt][ct] = mfma4(-ek[kk][rt], ek[kk][ct], accD[rt][ct]);
+            }
         }
         double accB4[T4];
 #pragma unroll
@@ -790,7 +803,12 @@ __device__ __forceinline__ int dense_factor(const Args &a, const SysDesc &sd, co
 #pragma unroll
                 for (int ct = 0; ct < TB; ++ct)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) RA[(16 * rt + 4 * v + lk) * PD + 16 * ct + li] = accD[rt][ct][v];
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * rt + 4 * v + lk, c = 16 * ct + li;
+                        double o = accD[rt][ct][v];
+                        if (ct < rt) o = fma(2.0, o, -((r < b && c < b) ? dn[rt][ct][v] : 0.0));
+                        RA[r * PD + c] = o;
+                    }
             if (g4) {
 #pragma unroll
                 for (int t = 0; t < T4; ++t) RG[y4 * PD + 4 * (4 * t + k4) + x4] = accB4[t];
