@@ -126,20 +126,16 @@ __device__ __forceinline__ double row_dot1(const double *A, int pa, int row, con
 }
 
 // x[c] of T^T x = rhs for a lower triangular T, lane c holding accs = rhs[c] / T[c][c]
-// and dcs[l] = T[l][c] / T[c][c]: with the scaling done beforehand the serial chain
-// is one broadcast and one FMA per column.
+// and dcs[l] = T[l][c] / T[c][c] for l > c, zero for l <= c: with the scaling done
+// beforehand the serial chain is one broadcast and one FMA per column.  Lane c's own
+// step subtracts nothing, so its accs is x[c] from then on (the later steps subtract
+// zeros), and the sweep ends with x on every lane: no per-lane select.
 template <int DB>
 __device__ __forceinline__ double back_subst_scaled(const double (&dcs)[DB], double accs)
 {
-    const int lane = threadIdx.x;
-    double xv = 0.0;
 #pragma unroll
-    for (int c2 = DB - 1; c2 >= 0; --c2) {
-        const double x2 = readlane_d(accs, c2);
-        if (lane == c2) xv = x2;
-        accs = fma(-dcs[c2], x2, accs);
-    }
-    return xv;
+    for (int c2 = DB - 1; c2 >= 0; --c2) accs = fma(-dcs[c2], readlane_d(accs, c2), accs);
+    return accs;
 }
 
 // Dense LDS layout: a panel area of (2 DB + 16) rows with pitch DB + 1 (the
@@ -1154,7 +1150,7 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
 #pragma unroll
         for (int l = 0; l < DB; ++l) {
             const double v = stD[l * PD + (cv ? c : 0)];
-            dcol[l] = (cv && l < b) ? v : (l == c ? 1.0 : 0.0);
+            dcol[l] = (cv && l < b && l != c) ? v : 0.0;   // the diagonal is taken out
         }
         const double dinv = cv ? 1.0 / stD[c * PD + c] : 1.0;
         double dcs[DB];
