@@ -1191,7 +1191,25 @@ __device__ __forceinline__ void dense_backward(const Args &a, const SysDesc &sd,
             if (cv) L.XC[c * nr + j] = xv;
             wave_sync();
         }
-        if (ADJ && cv) {
+        if (ADJ && nr == 1) {
+            // one rhs: the rows unrolled, so their reads from LDS issue together;
+            // lane c forms column c of each block.  Rows at or past b land past the
+            // block's end and lanes past b are moved there, so the stores are
+            // dropped without a per-row mask.
+            const int cc = cv ? c : 0, ce = cv ? c : (1 << 20);
+            const double pcc = L.PC[cc], xcc = L.XC[cc];
+            const GBlock gdD(a.dD + sd.oD + (long long)gs * b2, b2);
+            const GBlock gdC(a.dC + sd.oC + (long long)gs * b2, hasE ? b2 : 0);
+            const GBlock gdB(a.dB + sd.oB + (long long)gs * ng * b, (long long)ng * b);
+#pragma unroll
+            for (int r = 0; r < DB; ++r) {
+                const int o = (r * b + ce) * 8;
+                gdD.st(o, -0.5 * fma(L.XC[r], pcc, L.PC[r] * xcc));
+                gdC.st(o, -fma(L.XN[r], pcc, L.PN[r] * xcc));
+            }
+#pragma unroll
+            for (int q = 0; q < NGM; ++q) gdB.st((q * b + ce) * 8, -fma(L.XG[q], pcc, L.PG[q] * xcc));
+        } else if (ADJ && cv) {
             double *dD = a.dD + sd.oD + (long long)gs * b2;
             for (int r = 0; r < b; ++r) {
                 double s = 0.0;
